@@ -1,0 +1,201 @@
+"""Pins of the FP64 oracle against what mathematics fixes, independent of its own formulas.
+
+P1 closed form at L = 0; P2 two-electron systems = FCI; P3 brute-force e^-T H e^T projections
+and [H-bar, R] for random T and R; P4 first iterate = second-order Rayleigh-Schroedinger energy
+from the Fock-space Hamiltonian; P6 integral symmetries; P8 phase gauge invariance; P9 real limit;
+P10 non-interacting fragments; P11 one electron; P12 Davidson = dense eig.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_06805_amd import synth
+from oracle import ccsd, eom, fockspace as fk, integrals
+
+
+def _rand_t(o, v, seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+    t1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * scale
+    t2 = (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v))) * scale
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    return t1, t2
+
+
+# --------------------------------------------------------------------------- P3
+@pytest.mark.parametrize("o,v,N,seed", [(3, 4, 6, 5), (2, 5, 4, 8), (4, 3, 5, 2), (3, 5, 3, 13)])
+def test_p3_residuals_equal_fockspace_projections(o, v, N, seed):
+    inst = synth.make_instance(o, v, N, seed=seed, kappa=1.0)
+    t1, t2 = _rand_t(o, v, seed + 100)
+    fs = fk.FockSpace(o + v)
+    H = fk.build_h(fs, inst.eps, inst.L, o)
+    Hb = fk.hbar(fs, H, fk.cluster_operator(fs, t1, t2, o))
+    E, w1, w2 = fk.projections(fs, Hb, o, v)
+    g = integrals.Blocks(inst.L, o)
+    e_ref = np.vdot(fk.reference(fs, o), H @ fk.reference(fs, o))
+    r1, r2 = ccsd.residuals(g, inst.eps, t1, t2)
+    assert abs((E - e_ref) - ccsd.energy(g, t1, t2)) < 1e-12
+    assert np.abs(r1 - w1).max() < 1e-12
+    assert np.abs(r2 - w2).max() < 1e-12
+
+
+@pytest.mark.parametrize("o,v,N,seed", [(3, 4, 6, 5), (2, 5, 4, 8), (4, 3, 5, 2)])
+def test_p3_sigma_equals_commutator(o, v, N, seed):
+    inst = synth.make_instance(o, v, N, seed=seed, kappa=1.0)
+    t1, t2 = _rand_t(o, v, seed + 200)
+    fs = fk.FockSpace(o + v)
+    H = fk.build_h(fs, inst.eps, inst.L, o)
+    Hb = fk.hbar(fs, H, fk.cluster_operator(fs, t1, t2, o))
+    h = eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    rng = np.random.default_rng(seed)
+    vec = rng.standard_normal(eom.dim(o, v)) + 1j * rng.standard_normal(eom.dim(o, v))
+    r1, r2 = eom.unpack(vec, o, v)
+    assert np.abs(fk.ip_sigma(fs, Hb, o, v, r1, r2) - eom.sigma(h, vec)).max() < 1e-12
+
+
+def test_p3_reference_energy():
+    o, v = 3, 4
+    inst = synth.make_instance(o, v, 5, seed=3)
+    fs = fk.FockSpace(o + v)
+    H = fk.build_h(fs, inst.eps, inst.L, o)
+    g = integrals.Blocks(inst.L, o)
+    e_ref = inst.eps[:o].sum() - 0.5 * np.einsum("ijij->", g.oooo)
+    assert abs(np.vdot(fk.reference(fs, o), H @ fk.reference(fs, o)) - e_ref) < 1e-12
+
+
+# --------------------------------------------------------------------------- P2
+@pytest.mark.parametrize("v,N,seed,kappa", [(4, 6, 1, 1.0), (6, 8, 2, 0.8), (8, 10, 3, 0.6)])
+def test_p2_two_electrons_ccsd_is_fci(v, N, seed, kappa):
+    o = 2
+    inst = synth.make_instance(o, v, N, seed=seed, kappa=kappa)
+    e, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, o, e_tol=1e-12, r_tol=1e-11)
+    assert conv
+    fs = fk.FockSpace(o + v)
+    H = fk.build_h(fs, inst.eps, inst.L, o)
+    e_ref = np.vdot(fk.reference(fs, o), H @ fk.reference(fs, o)).real
+    e2 = fk.sector_eigenvalues(fs, H, 2)
+    e_tot = e_ref + e.real
+    assert np.min(np.abs(e2 - e_tot)) < 1e-9
+    assert abs(e.imag) < 1e-9          # FCI energies of a Hermitian H are real
+    # IP-EOM-CCSD is exact for two electrons: every one-electron level minus E_FCI
+    h = eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    w = np.sort_complex(np.linalg.eigvals(eom.dense_matrix(h)))
+    e1 = np.sort(fk.sector_eigenvalues(fs, H, 1).real) - e_tot
+    assert np.abs(np.sort(w.real) - e1).max() < 1e-9
+    assert np.abs(w.imag).max() < 1e-9
+
+
+# --------------------------------------------------------------------------- P1, P11
+def test_p1_no_interaction_closed_form():
+    o, v = 4, 6
+    inst = synth.make_instance(o, v, 5, seed=4)
+    L = np.zeros_like(inst.L)
+    e, t1, t2, _, conv = ccsd.solve(L, inst.eps, o)
+    assert conv and e == 0 and not np.any(t1) and not np.any(t2)
+    h = eom.Hbar(integrals.Blocks(L, o), inst.eps, t1, t2)
+    w = np.linalg.eigvals(eom.dense_matrix(h))
+    eo, ev = inst.eps[:o], inst.eps[o:]
+    expect = list(-eo) + [ev[b] - eo[i] - eo[j] for i in range(o) for j in range(i + 1, o) for b in range(v)]
+    assert np.allclose(np.sort(w.real), np.sort(expect), atol=1e-14, rtol=0)
+
+
+def test_p11_one_electron():
+    o, v = 1, 7
+    inst = synth.make_instance(o, v, 9, seed=6)
+    e, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, o)
+    assert conv and abs(e) < 1e-14 and np.abs(t1).max() < 1e-14
+    h = eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    w = np.linalg.eigvals(eom.dense_matrix(h))
+    assert w.shape == (1,) and abs(w[0] + inst.eps[0]) < 1e-14
+
+
+# --------------------------------------------------------------------------- P4
+def test_p4_first_iterate_is_rs_second_order():
+    o, v = 3, 4
+    inst = synth.make_instance(o, v, 6, seed=9, kappa=0.7)
+    fs = fk.FockSpace(o + v)
+    H = fk.build_h(fs, inst.eps, inst.L, o)
+    phi0 = fk.reference(fs, o)
+    # Rayleigh-Schroedinger second order with the Fock operator as H0 (Moller-Plesset partitioning)
+    e2 = 0.0
+    for i in range(o):
+        for j in range(i + 1, o):
+            for a in range(v):
+                for b in range(a + 1, v):
+                    d = fs.ad(o + a) @ (fs.ad(o + b) @ (fs.a(j) @ (fs.a(i) @ phi0)))
+                    x = np.vdot(d, H @ phi0)
+                    e2 += abs(x) ** 2 / (inst.eps[i] + inst.eps[j] - inst.eps[o + a] - inst.eps[o + b])
+    e1, _, _, _, _ = ccsd.solve(inst.L, inst.eps, o, max_iter=1, diis_size=1)
+    assert abs(e1 - e2) < 1e-13
+    assert abs(ccsd.mp2_energy(inst.L, inst.eps, o) - e2) < 1e-13
+
+
+# --------------------------------------------------------------------------- P6
+def test_p6_integral_symmetries():
+    inst = synth.make_instance(3, 5, 7, seed=12)
+    g = integrals.full_antisym(inst.L)
+    assert np.abs(g + g.transpose(1, 0, 2, 3)).max() < 1e-14
+    assert np.abs(g + g.transpose(0, 1, 3, 2)).max() < 1e-14
+    assert np.abs(g.conj() - g.transpose(2, 3, 0, 1)).max() < 1e-14
+    for P in range(inst.ncd):
+        assert np.abs(inst.L[P] - inst.L[P].conj().T).max() == 0
+
+
+# --------------------------------------------------------------------------- P8, P9, P10
+def _solve_all(inst, k):
+    e, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, inst.o)
+    assert conv
+    w, _ = eom.dense_roots(eom.Hbar(integrals.Blocks(inst.L, inst.o), inst.eps, t1, t2), k)
+    return e, w
+
+
+def test_p8_phase_gauge_invariance():
+    inst = synth.make_instance(4, 8, 12, seed=14, kappa=0.5)
+    e0, w0 = _solve_all(inst, 5)
+    e1, w1 = _solve_all(synth.gauge_transform(inst, 99), 5)
+    assert abs(e0 - e1) < 1e-9
+    assert np.abs(w0 - w1).max() < 1e-9
+
+
+def test_p9_real_limit():
+    inst = synth.make_instance(4, 8, 12, seed=15, kappa=0.5, real=True)
+    e, t1, t2, _, _ = ccsd.solve(inst.L, inst.eps, inst.o)
+    assert abs(e.imag) < 1e-13 and np.abs(t1.imag).max() < 1e-13 and np.abs(t2.imag).max() < 1e-13
+    # complex input differing only by a gauge is the same physics
+    e2, _, _, _, _ = ccsd.solve(synth.gauge_transform(inst, 3).L, inst.eps, inst.o)
+    assert abs(e2 - e) < 1e-9
+
+
+def test_p10_noninteracting_fragments_exact():
+    a = synth.make_instance(2, 3, 5, seed=21, kappa=0.9)
+    b = synth.make_instance(2, 4, 6, seed=22, kappa=0.9)
+    ab = synth.combine_fragments(a, b)
+    ea, wa = _solve_all(a, eom.dim(2, 3))
+    eb, wb = _solve_all(b, eom.dim(2, 4))
+    eab, _, _, _, conv = ccsd.solve(ab.L, ab.eps, ab.o)
+    assert conv and abs(eab - (ea + eb)) < 1e-9
+    # 2-electron fragments: every fragment IP is an IP of the union (size consistency)
+    e_, t1, t2, _, _ = ccsd.solve(ab.L, ab.eps, ab.o)
+    w = np.linalg.eigvals(eom.dense_matrix(eom.Hbar(integrals.Blocks(ab.L, ab.o), ab.eps, t1, t2)))
+    for x in np.concatenate([wa, wb]):
+        assert np.min(np.abs(w - x)) < 1e-8
+    # and the fragment answers are exact (FCI)
+    for inst, e in ((a, ea), (b, eb)):
+        fs = fk.FockSpace(inst.n)
+        H = fk.build_h(fs, inst.eps, inst.L, 2)
+        e_ref = np.vdot(fk.reference(fs, 2), H @ fk.reference(fs, 2)).real
+        assert np.min(np.abs(fk.sector_eigenvalues(fs, H, 2) - (e_ref + e))) < 1e-9
+
+
+# --------------------------------------------------------------------------- P12
+def test_p12_davidson_equals_dense():
+    inst = synth.make_instance(5, 14, 30, seed=31, kappa=synth.kappa_for(14, 30))
+    e, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, inst.o)
+    assert conv
+    h = eom.Hbar(integrals.Blocks(inst.L, inst.o), inst.eps, t1, t2)
+    wd, _ = eom.dense_roots(h, 4)
+    wv, X, _ = eom.davidson(h, 4)
+    assert np.abs(wd - wv).max() < 1e-9
+    # Ritz vectors are eigenvectors of the explicit matrix
+    M = eom.dense_matrix(h)
+    for k in range(4):
+        assert np.linalg.norm(M @ X[k] - wv[k] * X[k]) < 1e-8
