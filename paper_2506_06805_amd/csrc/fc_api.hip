@@ -1,0 +1,478 @@
+// C ABI entry points of libfnscc: context, integral and amplitude handles, CCSD driver (Jacobi +
+// complex DIIS), frozen natural spinors, IP-EOM sigma and Davidson.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <sstream>
+
+#include "fc_state.hpp"
+
+namespace fc {
+void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype);
+void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2);
+int davidson_one(fc_ctx ctx, fc_ints I, fc_amps T, int k, const fc_eom_opts& op, z* omega, z* Rout, int* iters);
+int learned_step(fc_ctx ctx, fc_ints I, const void* mlp, const z* t1, const z* t2, const z* r1, const z* r2,
+                 z* o1, z* o2);
+
+namespace {
+constexpr int TPB = 256;
+inline unsigned nblk(long n) { return (unsigned)std::max(1L, std::min(1048576L, (n + TPB * 4 - 1) / (TPB * 4))); }
+__global__ void k_mp2_amp(const z* vvoo, const double* eps, z* t, long o, long v) {
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < o * o * v * v; x += (long)gridDim.x * blockDim.x) {
+    long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
+    double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    t[x] = make_double2(vvoo[x].x / d, vvoo[x].y / d);
+  }
+}
+}  // namespace
+
+// ------------------------------------------------------------------------------ CCSD driver
+struct DiisState {
+  int size = 8;
+  long nt = 0;
+  DBuf vecs, errs;
+  std::deque<int> order;          // slots, oldest first
+  std::vector<z> B;               // size x size, by slot
+  void init(fc_ctx ctx, int sz, long n) {
+    size = sz; nt = n;
+    vecs = DBuf(ctx, sizeof(z) * (size_t)sz * n);
+    errs = DBuf(ctx, sizeof(z) * (size_t)sz * n);
+    B.assign((size_t)sz * sz, make_double2(0, 0));
+    order.clear();
+  }
+  z* vec(int s) { return vecs.as<z>() + (size_t)s * nt; }
+  z* err(int s) { return errs.as<z>() + (size_t)s * nt; }
+};
+
+// push (t_new, t_new - t_old) and write the extrapolated amplitudes into out
+static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const z* told, z* out) {
+  int slot;
+  if ((int)D.order.size() < D.size) {
+    std::vector<bool> used(D.size, false);
+    for (int s : D.order) used[s] = true;
+    slot = 0;
+    while (used[slot]) ++slot;
+  } else {
+    slot = D.order.front();
+    D.order.pop_front();
+  }
+  FC_HIP(hipMemcpyAsync(D.vec(slot), tnew, sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
+  FC_HIP(hipMemcpyAsync(D.err(slot), tnew, sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
+  axpy(ctx, D.nt, make_double2(-1, 0), told, D.err(slot));
+  D.order.push_back(slot);
+  for (int s : D.order) {
+    z b = dotc(ctx, D.nt, D.err(slot), D.err(s));
+    D.B[slot * D.size + s] = b;
+    D.B[s * D.size + slot] = make_double2(b.x, -b.y);
+  }
+  while (D.order.size() >= 2) {
+    const int m = (int)D.order.size();
+    std::vector<z> A((m + 1) * (size_t)(m + 1), make_double2(0, 0)), rhs(m + 1, make_double2(0, 0));
+    double sc = 0;
+    for (int k = 0; k < m; ++k) sc = std::max(sc, std::hypot(D.B[D.order[k] * D.size + D.order[k]].x, D.B[D.order[k] * D.size + D.order[k]].y));
+    if (sc == 0.0) break;
+    for (int k = 0; k < m; ++k)
+      for (int l = 0; l < m; ++l) {
+        z b = D.B[D.order[k] * D.size + D.order[l]];
+        A[k * (m + 1) + l] = make_double2(b.x / sc, b.y / sc);
+      }
+    for (int k = 0; k < m; ++k) { A[m * (m + 1) + k] = make_double2(1, 0); A[k * (m + 1) + m] = make_double2(1, 0); }
+    rhs[m] = make_double2(1, 0);
+    if (cond_herm(m + 1, A) < 1e12 && lin_solve(m + 1, A, rhs)) {
+      fill(ctx, out, D.nt, make_double2(0, 0));
+      for (int k = 0; k < m; ++k) axpy(ctx, D.nt, rhs[k], D.vec(D.order[k]), out);
+      return;
+    }
+    D.order.pop_front();  // ill-conditioned: drop the oldest vector
+  }
+  FC_HIP(hipMemcpyAsync(out, D.vec(D.order.back()), sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
+}
+
+static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tout, z* ecorr, int* iters) {
+  StageTimer st(ctx, "ccsd");
+  const long o = I->o, v = I->v, n1 = o * v, n2 = o * o * v * v, nt = n1 + n2;
+  const int prec = op.precision >= 0 ? op.precision : I->precision;
+  ZTensor t(ctx, {nt}), tn(ctx, {nt}), r(ctx, {nt}), tx(ctx, {nt});
+  if (op.t1_init && op.t2_init) {
+    FC_HIP(hipMemcpyAsync(t.p(), op.t1_init, sizeof(z) * n1, hipMemcpyDeviceToDevice, ctx->stream));
+    FC_HIP(hipMemcpyAsync(t.p() + n1, op.t2_init, sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    fill(ctx, t.p(), nt, make_double2(0, 0));
+  }
+  DiisState D;
+  if (op.diis_dim > 1) D.init(ctx, op.diis_dim, nt);
+  z e_old = ccsd_energy_dev(ctx, I, t.p(), t.p() + n1);
+  const double nuniq = (double)n1 + (double)(o * (o - 1) / 2) * (double)(v * (v - 1) / 2);
+  int status = FC_ENOCONV, it;
+  z e = e_old;
+  bool learned = op.learned && op.mlp;
+  double best_rms = INFINITY;
+  int since_best = 0;
+  for (it = 1; it <= op.max_iter; ++it) {
+    ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec);
+    z a = dotc(ctx, n1, r.p(), r.p()), b = dotc(ctx, n2, r.p() + n1, r.p() + n1);
+    const double rms = std::sqrt(std::max(0.0, (a.x + 0.25 * b.x) / std::max(1.0, nuniq)));
+    if (!std::isfinite(rms)) throw Error(FC_ENUMERIC, "ccsd_solve: residual is not finite");
+    if (learned) {
+      if (rms < best_rms * 0.999) { best_rms = rms; since_best = 0; } else if (++since_best >= op.stall_window) learned = false;
+    }
+    if (learned) learned_step(ctx, I, op.mlp, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
+    else jacobi_step(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
+    if (op.diis_dim > 1 && !learned) {
+      diis_push_extrapolate(ctx, D, tn.p(), t.p(), tx.p());
+      std::swap(t, tx);
+    } else {
+      std::swap(t, tn);
+    }
+    e = ccsd_energy_dev(ctx, I, t.p(), t.p() + n1);
+    const double de = std::hypot(e.x - e_old.x, e.y - e_old.y);
+    if (ctx->verbose)
+      fprintf(stderr, "[ccsd] it %3d E %.12f %+.2e dE %.2e rms %.2e %s\n", it, e.x, e.y, de, rms, learned ? "learned" : "jacobi");
+    if (de < op.e_tol && rms < op.r_tol) { status = FC_OK; break; }
+    e_old = e;
+  }
+  *ecorr = e;
+  *iters = std::min(it, op.max_iter);
+  auto* T = new fc_amps_s();
+  T->ctx = ctx; T->ints = I;
+  T->t1 = ZTensor(ctx, {o, v});
+  T->t2 = ZTensor(ctx, {o, o, v, v});
+  FC_HIP(hipMemcpyAsync(T->t1.p(), t.p(), sizeof(z) * n1, hipMemcpyDeviceToDevice, ctx->stream));
+  FC_HIP(hipMemcpyAsync(T->t2.p(), t.p() + n1, sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  *tout = T;
+  return status;
+}
+
+// ------------------------------------------------------------------------------ FNS
+static fc_ints fns_impl(fc_ctx ctx, fc_ints I, double thresh, int* v_kept, double* occ_out, void* U_out) {
+  StageTimer st(ctx, "fns");
+  const long o = I->o, v = I->v, N = I->ncd;
+  const z one = make_double2(1, 0), zero = make_double2(0, 0);
+  ZTensor t(ctx, {o, o, v, v}), Dv(ctx, {v, v});
+  hipLaunchKernelGGL(k_mp2_amp, dim3(nblk(t.size())), dim3(TPB), 0, ctx->stream, I->vvoo.p(), I->eps_d.as<double>(), t.p(), o, v);
+  // D_ab = 1/2 sum_ijc t_ij^ac conj(t_ij^bc)   (Eq. 24)
+  zein(ctx, "ijac,ijbc->ab", make_double2(0.5, 0), t, t, zero, Dv, false, true);
+  std::vector<z> Dh(v * v);
+  FC_HIP(hipMemcpyAsync(Dh.data(), Dv.p(), sizeof(z) * v * v, hipMemcpyDeviceToHost, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  std::vector<double> nocc;
+  herm_eig((int)v, Dh, nocc);                   // ascending; columns are natural spinors (Eq. 25)
+  std::vector<int> keep;
+  for (long c = v - 1; c >= 0; --c)
+    if (nocc[c] > thresh) keep.push_back((int)c);  // descending occupation
+  const long vp = (long)keep.size();
+  FC_REQUIRE(vp >= 1, FC_EARG, "fns_truncate: threshold removes every virtual spinor");
+  if (occ_out) for (long c = 0; c < v; ++c) occ_out[c] = nocc[v - 1 - c];
+  // F^NS = V~^H diag(eps_v) V~ (Eq. 26), semicanonical Z~ (Eq. 27), U = V~ Z~ (Eq. 28)
+  std::vector<z> F(vp * vp);
+  for (long p = 0; p < vp; ++p)
+    for (long q = 0; q < vp; ++q) {
+      double re = 0, im = 0;
+      for (long a = 0; a < v; ++a) {
+        z x = Dh[a * v + keep[p]], y = Dh[a * v + keep[q]];
+        double e = I->eps[o + a];
+        re += e * (x.x * y.x + x.y * y.y);
+        im += e * (x.x * y.y - x.y * y.x);
+      }
+      F[p * vp + q] = make_double2(re, im);
+    }
+  std::vector<double> enew;
+  herm_eig((int)vp, F, enew);
+  std::vector<z> U(v * vp);
+  for (long a = 0; a < v; ++a)
+    for (long c = 0; c < vp; ++c) {
+      double re = 0, im = 0;
+      for (long p = 0; p < vp; ++p) {
+        z x = Dh[a * v + keep[p]], y = F[p * vp + c];
+        re += x.x * y.x - x.y * y.y;
+        im += x.x * y.y + x.y * y.x;
+      }
+      U[a * vp + c] = make_double2(re, im);
+    }
+  if (U_out) std::memcpy(U_out, U.data(), sizeof(z) * v * vp);
+  *v_kept = (int)vp;
+  auto* J = new fc_ints_s();
+  J->ctx = ctx; J->o = (int)o; J->v = (int)vp; J->ncd = (int)N; J->precision = I->precision;
+  J->eps.assign(I->eps.begin(), I->eps.begin() + o);
+  for (double e : enew) J->eps.push_back(e);
+  J->eps_d = DBuf(ctx, sizeof(double) * J->eps.size());
+  FC_HIP(hipMemcpyAsync(J->eps_d.p, J->eps.data(), sizeof(double) * J->eps.size(), hipMemcpyHostToDevice, ctx->stream));
+  ZTensor Ud(ctx, {v, vp});
+  FC_HIP(hipMemcpyAsync(Ud.p(), U.data(), sizeof(z) * v * vp, hipMemcpyHostToDevice, ctx->stream));
+  J->Loo = ZTensor(ctx, {o, o, N});
+  FC_HIP(hipMemcpyAsync(J->Loo.p(), I->Loo.p(), sizeof(z) * J->Loo.size(), hipMemcpyDeviceToDevice, ctx->stream));
+  J->Lov = ZTensor(ctx, {o, vp, N});
+  zein(ctx, "iaP,ak->ikP", one, I->Lov, Ud, zero, J->Lov);
+  J->Lvo = ZTensor(ctx, {vp, o, N});
+  zein(ctx, "ak,aiP->kiP", one, Ud, I->Lvo, zero, J->Lvo, true, false);
+  ZTensor tmp(ctx, {vp, v, N});
+  zein(ctx, "ak,abP->kbP", one, Ud, I->Lvv, zero, tmp, true, false);
+  J->Lvv = ZTensor(ctx, {vp, vp, N});
+  zein(ctx, "kbP,bl->klP", one, tmp, Ud, zero, J->Lvv);
+  assemble_integrals(ctx, J);
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  return J;
+}
+
+}  // namespace fc
+
+using namespace fc;
+
+#define FC_TRY(ctx, ...)                                                   \
+  try {                                                                    \
+    __VA_ARGS__                                                            \
+  } catch (const fc::Error& e_) {                                          \
+    if (ctx) (ctx)->last_error = e_.what();                                \
+    return e_.code;                                                        \
+  } catch (const std::exception& e_) {                                     \
+    if (ctx) (ctx)->last_error = e_.what();                                \
+    return FC_ENUMERIC;                                                    \
+  }
+
+extern "C" {
+
+int fc_create(fc_ctx* out, int device, void* stream, fc_alloc_fn alloc, fc_free_fn release, void* user) {
+  if (!out) return FC_EARG;
+  *out = nullptr;
+  auto* c = new fc_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->alloc = alloc;
+  c->release = release;
+  c->user = user;
+  const char* vb = getenv("FNSCC_VERBOSE");
+  c->verbose = vb ? atoi(vb) : 0;
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete c;
+    return FC_EHIP;
+  }
+  *out = c;
+  return FC_OK;
+}
+
+void fc_destroy(fc_ctx ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& e : ctx->ladder_events) { (void)hipEventDestroy(e.first); (void)hipEventDestroy(e.second); }
+  release_cache(ctx);
+  delete ctx;
+}
+
+const char* fc_last_error(fc_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+int fc_set_timing(fc_ctx ctx, int on) {
+  if (!ctx) return FC_EARG;
+  ctx->timing = on;
+  return FC_OK;
+}
+
+int fc_take_timings(fc_ctx ctx, char* buf, size_t len) {
+  if (!ctx || !buf || len == 0) return FC_EARG;
+  FC_TRY(ctx, {
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    std::ostringstream os;
+    for (auto& kv : ctx->stage_ms) os << kv.first << "=" << kv.second << ";";
+    // ladder launches: per-launch durations from events on the context stream
+    double tot = 0;
+    for (auto& e : ctx->ladder_events) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) tot += ms;
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    os << "ladder_events=" << ctx->ladder_events.size() << ";ladder_event_ms=" << tot << ";";
+    ctx->ladder_events.clear();
+    for (auto& kv : ctx->stage_calls) os << "calls_" << kv.first << "=" << kv.second << ";";
+    ctx->stage_ms.clear();
+    ctx->stage_calls.clear();
+    std::string s = os.str();
+    size_t n = std::min(len - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+    return FC_OK;
+  })
+}
+
+int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const void* L, int l_dtype, int l_on_device,
+                 int precision, fc_ints* out) {
+  if (!ctx || !out) return FC_EARG;
+  *out = nullptr;
+  FC_TRY(ctx, {
+    FC_REQUIRE(o >= 1 && v >= 1 && ncd >= 1, FC_EARG, "cd_integrals: o, v and ncd must be >= 1");
+    FC_REQUIRE(eps && L, FC_EARG, "cd_integrals: NULL eps or L");
+    FC_REQUIRE(l_dtype == FC_C128 || l_dtype == FC_C64, FC_EARG, "cd_integrals: l_dtype must be FC_C128 or FC_C64");
+    FC_REQUIRE(precision >= FC_FP64 && precision <= FC_SPLIT_FP16, FC_EARG, "cd_integrals: bad precision");
+    StageTimer st(ctx, "cd_integrals");
+    auto* I = new fc_ints_s();
+    std::unique_ptr<fc_ints_s> guard(I);
+    I->ctx = ctx; I->o = o; I->v = v; I->ncd = ncd; I->precision = precision;
+    const long n = (long)o + v;
+    I->eps.assign(eps, eps + n);
+    I->eps_d = DBuf(ctx, sizeof(double) * n);
+    FC_HIP(hipMemcpyAsync(I->eps_d.p, eps, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    const size_t esz = l_dtype == FC_C128 ? 16 : 8;
+    const size_t lbytes = esz * (size_t)ncd * n * n;
+    DBuf Ld;
+    const void* Lsrc = L;
+    if (!l_on_device) {
+      Ld = DBuf(ctx, lbytes);
+      FC_HIP(hipMemcpyAsync(Ld.p, L, lbytes, hipMemcpyHostToDevice, ctx->stream));
+      Lsrc = Ld.p;
+    }
+    stage_cholesky(ctx, I, Lsrc, l_dtype);
+    assemble_integrals(ctx, I);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    *out = guard.release();
+    return FC_OK;
+  })
+}
+
+int fc_ints_info(fc_ints I, int* o, int* v, int* ncd) {
+  if (!I) return FC_EARG;
+  if (o) *o = I->o;
+  if (v) *v = I->v;
+  if (ncd) *ncd = I->ncd;
+  return FC_OK;
+}
+
+void fc_free_ints(fc_ints I) { delete I; }
+
+int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v_kept, double* occ, void* U) {
+  if (!ctx || !in || !out || !v_kept) return FC_EARG;
+  *out = nullptr;
+  FC_TRY(ctx, {
+    *out = fns_impl(ctx, in, occ_thresh, v_kept, occ, U);
+    return FC_OK;
+  })
+}
+
+void fc_ccsd_default_opts(fc_ccsd_opts* op) {
+  if (!op) return;
+  std::memset(op, 0, sizeof(*op));
+  op->e_tol = 1e-10;
+  op->r_tol = 1e-9;
+  op->max_iter = 200;
+  op->diis_dim = 8;
+  op->learned = 0;
+  op->precision = -1;  // inherit from the integral handle
+  op->stall_window = 3;
+}
+
+int ccsd_solve(fc_ctx ctx, int nb, const fc_ints* ints, const fc_ccsd_opts* opts, fc_amps* t, double* e_corr, int* iters) {
+  if (!ctx || nb < 1 || !ints || !t || !e_corr || !iters) return FC_EARG;
+  FC_TRY(ctx, {
+    fc_ccsd_opts op;
+    if (opts) op = *opts; else fc_ccsd_default_opts(&op);
+    FC_REQUIRE(op.max_iter >= 1, FC_EARG, "ccsd_solve: max_iter must be >= 1");
+    int status = FC_OK;
+    for (int b = 0; b < nb; ++b) {
+      FC_REQUIRE(ints[b], FC_EARG, "ccsd_solve: NULL integral handle");
+      z e;
+      int s = solve_one(ctx, ints[b], op, &t[b], &e, &iters[b]);
+      e_corr[2 * b] = e.x;
+      e_corr[2 * b + 1] = e.y;
+      if (s != FC_OK) status = s;
+    }
+    if (status == FC_ENOCONV) ctx->last_error = "ccsd_solve: not converged within max_iter";
+    return status;
+  })
+}
+
+int ccsd_residual(fc_ctx ctx, fc_ints I, const void* t1, const void* t2, void* r1, void* r2, int precision) {
+  if (!ctx || !I || !t1 || !t2 || !r1 || !r2) return FC_EARG;
+  FC_TRY(ctx, {
+    ccsd_residual_dev(ctx, I, (const z*)t1, (const z*)t2, (z*)r1, (z*)r2, precision < 0 ? I->precision : precision);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
+int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, int precision) {
+  if (!ctx || !I || !tau || !R) return FC_EARG;
+  FC_TRY(ctx, {
+    ladder_dev(ctx, I, (const z*)tau, (const z*)t1, (z*)R, precision < 0 ? I->precision : precision);
+    return FC_OK;
+  })
+}
+
+int fc_amps_create(fc_ctx ctx, fc_ints I, const void* t1, const void* t2, fc_amps* out) {
+  if (!ctx || !I || !t1 || !t2 || !out) return FC_EARG;
+  FC_TRY(ctx, {
+    auto* T = new fc_amps_s();
+    T->ctx = ctx; T->ints = I;
+    const long o = I->o, v = I->v;
+    T->t1 = ZTensor(ctx, {o, v});
+    T->t2 = ZTensor(ctx, {o, o, v, v});
+    FC_HIP(hipMemcpyAsync(T->t1.p(), t1, sizeof(z) * o * v, hipMemcpyDeviceToDevice, ctx->stream));
+    FC_HIP(hipMemcpyAsync(T->t2.p(), t2, sizeof(z) * o * o * v * v, hipMemcpyDeviceToDevice, ctx->stream));
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    *out = T;
+    return FC_OK;
+  })
+}
+
+int fc_amps_read(fc_amps T, void* t1, void* t2) {
+  if (!T) return FC_EARG;
+  fc_ctx ctx = T->ctx;
+  FC_TRY(ctx, {
+    if (t1) FC_HIP(hipMemcpyAsync(t1, T->t1.p(), sizeof(z) * T->t1.size(), hipMemcpyDeviceToDevice, ctx->stream));
+    if (t2) FC_HIP(hipMemcpyAsync(t2, T->t2.p(), sizeof(z) * T->t2.size(), hipMemcpyDeviceToDevice, ctx->stream));
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
+void fc_free_amps(fc_amps T) { delete T; }
+
+int ipeom_sigma(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* R, void* S) {
+  if (!ctx || !I || !T || nvec < 0 || (nvec > 0 && (!R || !S))) return FC_EARG;
+  FC_TRY(ctx, {
+    FC_REQUIRE(T->ints == I, FC_EARG, "ipeom_sigma: amplitudes belong to another integral handle");
+    sigma_dev(ctx, I, T, nvec, (const z*)R, (z*)S);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
+void fc_eom_default_opts(fc_eom_opts* op) {
+  if (!op) return;
+  op->r_tol = 1e-9;
+  op->w_tol = 1e-10;
+  op->max_iter = 200;
+  op->max_subspace = 0;  // 0 = 20 x roots
+  op->guess_per_root = 2;
+}
+
+int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
+                   const fc_eom_opts* opts, double* omega, void* R_out, int* iters) {
+  if (!ctx || nb < 1 || !ints || !t || !nroots || !omega) return FC_EARG;
+  FC_TRY(ctx, {
+    fc_eom_opts op;
+    if (opts) op = *opts; else fc_eom_default_opts(&op);
+    int status = FC_OK;
+    long off = 0, roff = 0;
+    for (int b = 0; b < nb; ++b) {
+      FC_REQUIRE(ints[b] && t[b] && t[b]->ints == ints[b], FC_EARG, "ipeom_davidson: bad handles");
+      const int k = nroots[b];
+      fc_eom_opts ob = op;
+      if (ob.max_subspace <= 0) ob.max_subspace = 20 * k;
+      std::vector<z> w(k);
+      const long o = ints[b]->o, v = ints[b]->v, dim = o + o * (o - 1) / 2 * v;
+      z* rout = R_out ? (z*)R_out + roff : nullptr;
+      int itb = 0;
+      int s = davidson_one(ctx, ints[b], t[b], k, ob, w.data(), rout, &itb);
+      for (int r = 0; r < k; ++r) { omega[2 * (off + r)] = w[r].x; omega[2 * (off + r) + 1] = w[r].y; }
+      if (iters) iters[b] = itb;
+      off += k;
+      roff += (long)k * dim;
+      if (s != FC_OK) status = s;
+    }
+    return status;
+  })
+}
+
+}  // extern "C"

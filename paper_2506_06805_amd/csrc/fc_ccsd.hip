@@ -1,0 +1,319 @@
+// CCSD residuals (Eq. 13-14), energy (Eq. 15) and the particle-particle ladder.
+//
+// Working equations: spin-orbital Stanton-Gauss intermediates in complex-correct index order
+// (creation-side indices in the bra).  Integrals with three virtual indices are never formed:
+// each such contraction is factorised through the Cholesky vectors, and the four-virtual
+// ladder sum_ef tau_ij^ef <ab||ef>/2 (plus the T1 part of W_abef) is evaluated as
+//   sum_ef tau_ij^ef sum_P Lb^P_ae Lb^P_bf,   Lb^P_ae = L^P_ae - sum_m t_m^a L^P_me,
+// with (ae|bf) rebuilt tile by tile from the Cholesky vectors (Eq. 21, 23).  The remaining
+// pieces of the same terms are folded into
+//   1/2 sum_mn tau_mn^ab W0_mnij + 1/4 sum_mn t_mn^ab X_ijmn,
+//   W0_mnij = <mn||ij> + P(ij) sum_e t_j^e <mn||ie>,  X_ijmn = sum_ef tau_ij^ef <mn||ef>.
+#include <algorithm>
+#include <cmath>
+
+#include "fc_state.hpp"
+
+namespace fc {
+namespace {
+constexpr int TPB = 256;
+inline unsigned nblk(long n) { return (unsigned)std::max(1L, std::min(1048576L, (n + TPB * 4 - 1) / (TPB * 4))); }
+#define GRID_STRIDE(i, n) for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
+
+__device__ inline z cmul(z a, z b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+
+// tau~ = t2 + 1/2 (t_i^a t_j^b - t_i^b t_j^a), tau = t2 + t_i^a t_j^b - t_i^b t_j^a
+__global__ void k_tau(const z* t1, const z* t2, z* tau, z* taut, long o, long v) {
+  GRID_STRIDE(t, o * o * v * v) {
+    long b = t % v, a = (t / v) % v, j = (t / (v * v)) % o, i = t / (v * v * o);
+    z x = cmul(t1[i * v + a], t1[j * v + b]), y = cmul(t1[i * v + b], t1[j * v + a]);
+    z d = make_double2(x.x - y.x, x.y - y.y);
+    z s = t2[t];
+    if (tau) tau[t] = make_double2(s.x + d.x, s.y + d.y);
+    if (taut) taut[t] = make_double2(s.x + 0.5 * d.x, s.y + 0.5 * d.y);
+  }
+}
+// Z[j,n,f,b] = 1/2 t2[j,n,f,b] + t1[j,f] t1[n,b]   (scale_t2 = 1/2 for W_mbej, 1 for W-bar_mbej)
+__global__ void k_ring_amp(const z* t1, const z* t2, z* Z, long o, long v, double scale_t2) {
+  GRID_STRIDE(t, o * o * v * v) {
+    long b = t % v, f = (t / v) % v, n = (t / (v * v)) % o, j = t / (v * v * o);
+    z p = cmul(t1[j * v + f], t1[n * v + b]);
+    Z[t] = make_double2(scale_t2 * t2[t].x + p.x, scale_t2 * t2[t].y + p.y);
+  }
+}
+// r -= D t with D_i^a = e_i - e_a, D_ij^ab = e_i + e_j - e_a - e_b
+__global__ void k_sub_denom1(z* r, const z* t, const double* eps, long o, long v) {
+  GRID_STRIDE(x, o * v) {
+    long a = x % v, i = x / v;
+    double d = eps[i] - eps[o + a];
+    r[x].x -= d * t[x].x; r[x].y -= d * t[x].y;
+  }
+}
+__global__ void k_sub_denom2(z* r, const z* t, const double* eps, long o, long v) {
+  GRID_STRIDE(x, o * o * v * v) {
+    long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
+    double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    r[x].x -= d * t[x].x; r[x].y -= d * t[x].y;
+  }
+}
+// out = t + r / D   (Jacobi step); diagonal (i==j or a==b) entries of t2 stay zero
+__global__ void k_jacobi1(const z* t, const z* r, z* out, const double* eps, long o, long v) {
+  GRID_STRIDE(x, o * v) {
+    long a = x % v, i = x / v;
+    double d = eps[i] - eps[o + a];
+    out[x] = make_double2(t[x].x + r[x].x / d, t[x].y + r[x].y / d);
+  }
+}
+__global__ void k_jacobi2(const z* t, const z* r, z* out, const double* eps, long o, long v) {
+  GRID_STRIDE(x, o * o * v * v) {
+    long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
+    if (i == j || a == b) { out[x] = make_double2(0, 0); continue; }
+    double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    out[x] = make_double2(t[x].x + r[x].x / d, t[x].y + r[x].y / d);
+  }
+}
+// X[m,n,i,j] -> X - X^(i<->j) added into W (o^4)
+__global__ void k_antisym_oooo(z* W, const z* X, long o) {
+  GRID_STRIDE(t, o * o * o * o) {
+    long j = t % o, i = (t / o) % o, mn = t / (o * o);
+    z a = X[t], b = X[(mn * o + j) * o + i];
+    W[t].x += a.x - b.x; W[t].y += a.y - b.y;
+  }
+}
+
+// ---- ladder helpers
+// taup[pij][pef] = tau[i,j,e,f] for i<j, e<f
+__global__ void k_pack_tau(const z* __restrict__ tau, z* __restrict__ taup, long o, long v, const int2* po,
+                           const int2* pv, long no, long nv) {
+  GRID_STRIDE(t, no * nv) {
+    long pe = t % nv, pi = t / nv;
+    int2 ij = po[pi], ef = pv[pe];
+    taup[t] = tau[((ij.x * o + ij.y) * v + ef.x) * v + ef.y];
+  }
+}
+// Wp[pef][(a-a0)*nB + (b-b0)] = W[(a,e),(b,f)] - W[(a,f),(b,e)],  W row-major (nA*v) x (nB*v)
+__global__ void k_ladder_anti(const z* __restrict__ W, z* __restrict__ Wp, long v, long nA, long nB,
+                              const int2* pv, long nv) {
+  const long nab = nA * nB, ldw = nB * v;
+  GRID_STRIDE(t, nv * nab) {
+    long ab = t % nab, pe = t / nab;
+    long a = ab / nB, b = ab % nB;
+    int2 ef = pv[pe];
+    z x = W[(a * v + ef.x) * ldw + b * v + ef.y];
+    z y = W[(a * v + ef.y) * ldw + b * v + ef.x];
+    Wp[t] = make_double2(x.x - y.x, x.y - y.y);
+  }
+}
+// R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][(a-a0)*nB + (b-b0)]
+__global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, long a0, long nA,
+                                 long b0, long nB, const int2* po, long no, int diag) {
+  const long nab = nA * nB;
+  GRID_STRIDE(t, no * nab) {
+    long ab = t % nab, pi = t / nab;
+    long a = a0 + ab / nB, b = b0 + ab % nB;
+    if (diag && a >= b) continue;
+    int2 ij = po[pi];
+    z r = Rp[t], m = make_double2(-r.x, -r.y);
+    long i = ij.x, j = ij.y;
+    R[((i * o + j) * v + a) * v + b] = r;
+    R[((j * o + i) * v + a) * v + b] = m;
+    R[((i * o + j) * v + b) * v + a] = m;
+    R[((j * o + i) * v + b) * v + a] = r;
+  }
+}
+}  // namespace
+
+static DBuf pair_table(fc_ctx ctx, long n, long& np) {
+  std::vector<int2> h;
+  for (long i = 0; i < n; ++i)
+    for (long j = i + 1; j < n; ++j) h.push_back(make_int2((int)i, (int)j));
+  np = (long)h.size();
+  DBuf d(ctx, sizeof(int2) * std::max(1L, np));
+  if (np) FC_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(int2) * np, hipMemcpyHostToDevice, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  return d;
+}
+
+// R = sum_ef tau_ij^ef sum_P Lb^P_ae Lb^P_bf  (overwrites R)
+void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision) {
+  StageTimer st(ctx, "ladder");
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (ctx->timing) {
+    FC_HIP(hipEventCreate(&ev0)); FC_HIP(hipEventCreate(&ev1));
+    FC_HIP(hipEventRecord(ev0, ctx->stream));
+  }
+  const long o = I->o, v = I->v, N = I->ncd;
+  const z one = make_double2(1, 0), zero = make_double2(0, 0);
+  // dressed Cholesky vectors
+  ZTensor Lb(ctx, {v, v, N});
+  FC_HIP(hipMemcpyAsync(Lb.p(), I->Lvv.p(), sizeof(z) * Lb.size(), hipMemcpyDeviceToDevice, ctx->stream));
+  if (t1dress) zein(ctx, "ma,meP->aeP", make_double2(-1, 0), ZT((z*)t1dress, {o, v}), I->Lov, one, Lb);
+  long no, nv;
+  DBuf po = pair_table(ctx, o, no), pv = pair_table(ctx, v, nv);
+  fill(ctx, R, o * o * v * v, zero);
+  if (no == 0 || nv == 0) return;
+  DBuf taup(ctx, sizeof(z) * no * nv);
+  hipLaunchKernelGGL(k_pack_tau, dim3(nblk(no * nv)), dim3(TPB), 0, ctx->stream, tau, taup.as<z>(), o, v,
+                     po.as<int2>(), pv.as<int2>(), no, nv);
+  // ab tile: W of nA*v x nB*v complex entries kept within a fixed budget
+  const double budget = 768.0 * 1024 * 1024;
+  long T = (long)std::floor(std::sqrt(budget / (16.0 * (double)v * (double)v)));
+  T = std::max(1L, std::min(T, v));
+  DBuf W(ctx, sizeof(z) * T * v * T * v), Wp(ctx, sizeof(z) * nv * T * T), Rp(ctx, sizeof(z) * no * T * T);
+  for (long a0 = 0; a0 < v; a0 += T) {
+    const long nA = std::min(T, v - a0);
+    for (long b0 = a0; b0 < v; b0 += T) {
+      const long nB = std::min(T, v - b0);
+      // W[(a,e),(b,f)] = sum_P Lb[a,e,P] Lb[b,f,P]
+      if (precision == FC_FP64)
+        zgemm(ctx, 'N', 'T', nA * v, nB * v, N, one, Lb.p() + a0 * v * N, N, Lb.p() + b0 * v * N, N, zero,
+              W.as<z>(), nB * v);
+      else
+        zgemm_split(ctx, precision, 'N', 'T', nA * v, nB * v, N, one, Lb.p() + a0 * v * N, N,
+                    Lb.p() + b0 * v * N, N, zero, W.as<z>(), nB * v);
+      hipLaunchKernelGGL(k_ladder_anti, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
+                         Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
+      // Rp[pij][ab] = sum_pef taup[pij][pef] Wp[pef][ab]
+      if (precision == FC_FP64)
+        zgemm(ctx, 'N', 'N', no, nA * nB, nv, one, taup.as<z>(), nv, Wp.as<z>(), nA * nB, zero, Rp.as<z>(),
+              nA * nB);
+      else
+        zgemm_split(ctx, precision, 'N', 'N', no, nA * nB, nv, one, taup.as<z>(), nv, Wp.as<z>(), nA * nB,
+                    zero, Rp.as<z>(), nA * nB);
+      hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nA * nB)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R,
+                         o, v, a0, nA, b0, nB, po.as<int2>(), no, (int)(a0 == b0));
+      FC_HIP(hipGetLastError());
+    }
+  }
+  if (ev0) {
+    FC_HIP(hipEventRecord(ev1, ctx->stream));
+    ctx->ladder_events.emplace_back(ev0, ev1);
+  }
+}
+
+z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
+  const long o = I->o, v = I->v;
+  ZTensor tau(ctx, {o, o, v, v});
+  hipLaunchKernelGGL(k_tau, dim3(nblk(tau.size())), dim3(TPB), 0, ctx->stream, t1, t2, tau.p(), (z*)nullptr, o, v);
+  z e = dotu(ctx, tau.size(), I->oovv.p(), tau.p());
+  return make_double2(0.25 * e.x, 0.25 * e.y);
+}
+
+void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p, z* r2p, int precision) {
+  StageTimer st(ctx, "residual");
+  const long o = I->o, v = I->v, N = I->ncd;
+  const z one = make_double2(1, 0), zero = make_double2(0, 0), half = make_double2(0.5, 0),
+          mone = make_double2(-1, 0), mhalf = make_double2(-0.5, 0), quarter = make_double2(0.25, 0);
+  ZT T1((z*)t1p, {o, v}), T2((z*)t2p, {o, o, v, v});
+  ZT R1(r1p, {o, v}), R2(r2p, {o, o, v, v});
+  const long n2 = o * o * v * v;
+
+  ZTensor tau(ctx, {o, o, v, v}), taut(ctx, {o, o, v, v});
+  hipLaunchKernelGGL(k_tau, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, t1p, t2p, tau.p(), taut.p(), o, v);
+  FC_HIP(hipGetLastError());
+
+  // ---- Cholesky-factorised three-virtual pieces
+  ZTensor xP(ctx, {N});                 // x_P = sum_mf t_m^f L^P_mf
+  zein(ctx, "mf,mfP->P", one, T1, I->Lov, zero, xP);
+  ZTensor Y(ctx, {v, o, N});            // Y[a,m,P] = sum_f L^P_af t_m^f
+  zgemm(ctx, 'N', 'N', o, N, v, one, t1p, v, I->Lvv.p(), N, zero, Y.p(), N, (int)v, 0, v * N, o * N);
+  ZTensor Cm(ctx, {o, o, N});           // C[m,j,P] = sum_f L^P_mf t_j^f
+  zgemm(ctx, 'N', 'N', o, N, v, one, t1p, v, I->Lov.p(), N, zero, Cm.p(), N, (int)o, 0, v * N, o * N);
+
+  // ---- intermediates
+  ZTensor Fme(ctx, {o, v}), Fae(ctx, {v, v}), Fmi(ctx, {o, o});
+  zein(ctx, "nf,mnef->me", one, T1, I->oovv, zero, Fme);
+  // F_ae = sum_mf t_m^f <ma||fe> - 1/2 sum tau~_mn^af <mn||ef>,  <ma||fe> = (mf|ae) - (me|af)
+  zein(ctx, "P,aeP->ae", one, xP, I->Lvv, zero, Fae);
+  zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, Fae);
+  zein(ctx, "mnaf,mnef->ae", mhalf, taut, I->oovv, one, Fae);
+  // F_mi = sum_ne t_n^e <mn||ie> + 1/2 sum tau~_in^ef <mn||ef>
+  zein(ctx, "ne,mnie->mi", one, T1, I->ooov, zero, Fmi);
+  zein(ctx, "inef,mnef->mi", half, taut, I->oovv, one, Fmi);
+  // W0_mnij = <mn||ij> + P(ij) sum_e t_j^e <mn||ie>
+  ZTensor W0(ctx, {o, o, o, o}), tmp4(ctx, {o, o, o, o});
+  FC_HIP(hipMemcpyAsync(W0.p(), I->oooo.p(), sizeof(z) * W0.size(), hipMemcpyDeviceToDevice, ctx->stream));
+  zein(ctx, "mnie,je->mnij", one, I->ooov, T1, zero, tmp4);
+  hipLaunchKernelGGL(k_antisym_oooo, dim3(nblk(W0.size())), dim3(TPB), 0, ctx->stream, W0.p(), tmp4.p(), o);
+  // X_ijmn = sum_ef tau_ij^ef <mn||ef>
+  ZTensor X(ctx, {o, o, o, o});
+  zein(ctx, "ijef,mnef->ijmn", one, tau, I->oovv, zero, X);
+  // W_mbej = <mb||ej> + sum_f t_j^f <mb||ef> - sum_n t_n^b <mn||ej> - sum_nf (t_jn^fb/2 + t_j^f t_n^b) <mn||ef>
+  //   sum_f t_j^f <mb||ef> = sum_P L^P_me Y[b,j,P] - sum_P C[m,j,P] L^P_be
+  ZTensor Wmbej(ctx, {o, v, v, o});
+  FC_HIP(hipMemcpyAsync(Wmbej.p(), I->ovvo.p(), sizeof(z) * Wmbej.size(), hipMemcpyDeviceToDevice, ctx->stream));
+  zein(ctx, "meP,bjP->mbej", one, I->Lov, Y, one, Wmbej);
+  zein(ctx, "mjP,beP->mbej", mone, Cm, I->Lvv, one, Wmbej);
+  zein(ctx, "nb,mnej->mbej", mone, T1, I->oovo, one, Wmbej);
+  {
+    ZTensor Z(ctx, {o, o, v, v});
+    hipLaunchKernelGGL(k_ring_amp, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, t1p, t2p, Z.p(), o, v, 0.5);
+    zein(ctx, "jnfb,mnef->mbej", mone, Z, I->oovv, one, Wmbej);
+  }
+
+  // ---- T1 residual
+  zein(ctx, "ie,ae->ia", one, T1, Fae, zero, R1);
+  zein(ctx, "ma,mi->ia", mone, T1, Fmi, one, R1);
+  zein(ctx, "imae,me->ia", one, T2, Fme, one, R1);
+  zein(ctx, "nf,naif->ia", mone, T1, I->ovov, one, R1);
+  {  // -1/2 sum_mef t_im^ef <ma||ef> = - sum_fP Q[i,f,P] L^P_af,  Q[i,f,P] = sum_me t_im^ef L^P_me
+    ZTensor Q(ctx, {o, v, N});
+    zein(ctx, "imef,meP->ifP", one, T2, I->Lov, zero, Q);
+    zein(ctx, "ifP,afP->ia", mone, Q, I->Lvv, one, R1);
+  }
+  zein(ctx, "mnae,nmei->ia", mhalf, T2, I->oovo, one, R1);
+
+  // ---- T2 residual
+  FC_HIP(hipMemcpyAsync(r2p, I->vvoo.p(), sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
+  ZTensor x(ctx, {o, o, v, v});
+  {  // P(ab) sum_e t_ij^ae (F_be - 1/2 sum_m t_m^b F_me)
+    ZTensor Fp(ctx, {v, v});
+    FC_HIP(hipMemcpyAsync(Fp.p(), Fae.p(), sizeof(z) * Fp.size(), hipMemcpyDeviceToDevice, ctx->stream));
+    zein(ctx, "mb,me->be", mhalf, T1, Fme, one, Fp);
+    zein(ctx, "ijae,be->ijab", one, T2, Fp, zero, x);
+    antisym_add(ctx, r2p, x.p(), o, v, 1, one);
+  }
+  {  // -P(ij) sum_m t_im^ab (F_mj + 1/2 sum_e t_j^e F_me)
+    ZTensor Fp(ctx, {o, o});
+    FC_HIP(hipMemcpyAsync(Fp.p(), Fmi.p(), sizeof(z) * Fp.size(), hipMemcpyDeviceToDevice, ctx->stream));
+    zein(ctx, "je,me->mj", half, T1, Fme, one, Fp);
+    zein(ctx, "imab,mj->ijab", one, T2, Fp, zero, x);
+    antisym_add(ctx, r2p, x.p(), o, v, 2, mone);
+  }
+  zein(ctx, "mnab,mnij->ijab", half, tau, W0, one, R2);
+  zein(ctx, "mnab,ijmn->ijab", quarter, T2, X, one, R2);
+  {  // particle-particle ladder with T1-dressed Cholesky vectors
+    ladder_dev(ctx, I, tau.p(), t1p, x.p(), precision);
+    axpy(ctx, n2, one, x.p(), r2p);
+  }
+  {  // P(ij)P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
+    zein(ctx, "imae,mbej->ijab", one, T2, Wmbej, zero, x);
+    ZTensor U(ctx, {o, o, v, o});
+    zein(ctx, "ie,mbej->imbj", one, T1, I->ovvo, zero, U);
+    zein(ctx, "ma,imbj->ijab", mone, T1, U, one, x);
+    antisym_add(ctx, r2p, x.p(), o, v, 3, one);
+  }
+  {  // P(ij) sum_e t_i^e <ab||ej> = P(ij) [sum_P Y[a,i,P] L^P_bj - sum_P L^P_aj Y[b,i,P]]
+    zein(ctx, "aiP,bjP->ijab", one, Y, I->Lvo, zero, x);
+    zein(ctx, "ajP,biP->ijab", mone, I->Lvo, Y, one, x);
+    antisym_add(ctx, r2p, x.p(), o, v, 2, one);
+  }
+  {  // -P(ab) sum_m t_m^a <mb||ij>
+    zein(ctx, "ma,mbij->ijab", one, T1, I->ovoo, zero, x);
+    antisym_add(ctx, r2p, x.p(), o, v, 1, mone);
+  }
+  // Omega = RHS - D t
+  hipLaunchKernelGGL(k_sub_denom1, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, r1p, t1p, I->eps_d.as<double>(), o, v);
+  hipLaunchKernelGGL(k_sub_denom2, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, r2p, t2p, I->eps_d.as<double>(), o, v);
+  FC_HIP(hipGetLastError());
+}
+
+// Jacobi step out = t + Omega/D (exported for the solver)
+void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2) {
+  const long o = I->o, v = I->v;
+  hipLaunchKernelGGL(k_jacobi1, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, t1, r1, o1, I->eps_d.as<double>(), o, v);
+  hipLaunchKernelGGL(k_jacobi2, dim3(nblk(o * o * v * v)), dim3(TPB), 0, ctx->stream, t2, r2, o2, I->eps_d.as<double>(), o, v);
+  FC_HIP(hipGetLastError());
+}
+
+}  // namespace fc

@@ -1,0 +1,97 @@
+// Cholesky-vector staging and assembly of the stored antisymmetrised integrals.
+//
+// Eq. 21/23: (pr|qs) = sum_P L^P_pr L^P_qs and <pq||rs> = (pr|qs) - (ps|qr).  Each Mulliken block
+// is one complex GEMM over P (K = ncd) with both operands P-contiguous; the antisymmetrised block
+// is then formed by index permutation.  Only blocks with at most two virtual indices are stored.
+#include "fc_state.hpp"
+
+namespace fc {
+namespace {
+constexpr int TPB = 256;
+
+// in: L[P][p][q] (complex128 or complex64), out: block [p - p0][q - q0][P] as complex128.
+template <class T>
+__global__ void k_stage_block(const T* __restrict__ L, long n, long ncd, long p0, long np, long q0, long nq,
+                              z* __restrict__ out) {
+  const long total = np * nq * ncd;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    long P = t % ncd, q = (t / ncd) % nq, p = t / (ncd * nq);
+    const T v = L[(P * n + p0 + p) * n + q0 + q];
+    out[t] = make_double2((double)v.x, (double)v.y);
+  }
+}
+}  // namespace
+
+// Stage the four L blocks from L[P][p][q] (device, complex128 or complex64).
+void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype) {
+  const long o = I->o, v = I->v, n = o + v, N = I->ncd;
+  I->Loo = ZTensor(ctx, {o, o, N});
+  I->Lov = ZTensor(ctx, {o, v, N});
+  I->Lvo = ZTensor(ctx, {v, o, N});
+  I->Lvv = ZTensor(ctx, {v, v, N});
+  struct B { ZTensor* t; long p0, np, q0, nq; } blocks[4] = {
+      {&I->Loo, 0, o, 0, o}, {&I->Lov, 0, o, o, v}, {&I->Lvo, o, v, 0, o}, {&I->Lvv, o, v, o, v}};
+  for (auto& b : blocks) {
+    long total = b.np * b.nq * N;
+    unsigned g = (unsigned)std::min<long>(1048576, (total + TPB * 4 - 1) / (TPB * 4));
+    if (l_dtype == FC_C128)
+      hipLaunchKernelGGL(k_stage_block<double2>, dim3(g), dim3(TPB), 0, ctx->stream, (const double2*)Ldev, n, N,
+                         b.p0, b.np, b.q0, b.nq, b.t->p());
+    else
+      hipLaunchKernelGGL(k_stage_block<float2>, dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev, n, N,
+                         b.p0, b.np, b.q0, b.nq, b.t->p());
+    FC_HIP(hipGetLastError());
+  }
+}
+
+// J[(p,r),(q,s)] = sum_P X[p,r,P] Y[q,s,P]   (Mulliken block, one GEMM, K = ncd)
+static void mulliken(fc_ctx ctx, int precision, const ZTensor& X, const ZTensor& Y, ZTensor& J) {
+  const long M = X.dims[0] * X.dims[1], Nn = Y.dims[0] * Y.dims[1], K = X.dims[2];
+  J = ZTensor(ctx, {X.dims[0], X.dims[1], Y.dims[0], Y.dims[1]});
+  if (precision == FC_FP64)
+    zgemm(ctx, 'N', 'T', M, Nn, K, make_double2(1, 0), X.p(), K, Y.p(), K, make_double2(0, 0), J.p(), Nn);
+  else
+    zgemm_split(ctx, precision, 'N', 'T', M, Nn, K, make_double2(1, 0), X.p(), K, Y.p(), K, make_double2(0, 0),
+                J.p(), Nn);
+}
+
+void assemble_integrals(fc_ctx ctx, fc_ints I) {
+  StageTimer st(ctx, "assemble");
+  const long o = I->o, v = I->v;
+  const z one = make_double2(1, 0), mone = make_double2(-1, 0), zero = make_double2(0, 0);
+  const int prec = I->precision;
+  ZTensor J, J2;
+  // <mn||ij> = (mi|nj) - (mj|ni);  J[m,i,n,j]
+  mulliken(ctx, prec, I->Loo, I->Loo, J);
+  I->oooo = ZTensor(ctx, {o, o, o, o});
+  permute(ctx, J, {0, 2, 1, 3}, one, zero, I->oooo.p());     // (m,n,i,j) <- J[m,i,n,j]
+  permute(ctx, J, {0, 2, 3, 1}, mone, one, I->oooo.p());     // -(mj|ni) = -J[m,j,n,i]
+  // <mn||ie> = (mi|ne) - (me|ni);  J[m,i,n,e], (me|ni) = (ni|me) = J[n,i,m,e]
+  mulliken(ctx, prec, I->Loo, I->Lov, J);
+  I->ooov = ZTensor(ctx, {o, o, o, v});
+  permute(ctx, J, {0, 2, 1, 3}, one, zero, I->ooov.p());     // (m,n,i,e) <- J[m,i,n,e]
+  permute(ctx, J, {2, 0, 1, 3}, mone, one, I->ooov.p());     // (m,n,i,e) <- J[n,i,m,e]
+  // <mn||ef> = (me|nf) - (mf|ne);  J[m,e,n,f]
+  mulliken(ctx, prec, I->Lov, I->Lov, J);
+  I->oovv = ZTensor(ctx, {o, o, v, v});
+  permute(ctx, J, {0, 2, 1, 3}, one, zero, I->oovv.p());
+  permute(ctx, J, {0, 2, 3, 1}, mone, one, I->oovv.p());
+  // <mb||ej> = (me|bj) - (mj|be);  J[m,e,b,j], J2[m,j,b,e]
+  mulliken(ctx, prec, I->Lov, I->Lvo, J);
+  mulliken(ctx, prec, I->Loo, I->Lvv, J2);
+  I->ovvo = ZTensor(ctx, {o, v, v, o});
+  permute(ctx, J, {0, 2, 1, 3}, one, zero, I->ovvo.p());     // (m,b,e,j) <- J[m,e,b,j]
+  permute(ctx, J2, {0, 2, 3, 1}, mone, one, I->ovvo.p());    // (m,b,e,j) <- J2[m,j,b,e]
+  J = ZTensor(); J2 = ZTensor();
+  // symmetry copies
+  I->oovo = ZTensor(ctx, {o, o, v, o});                      // <mn||ej> = -<mn||je>
+  permute(ctx, I->ooov, {0, 1, 3, 2}, mone, zero, I->oovo.p());
+  I->ovov = ZTensor(ctx, {o, v, o, v});                      // <ma||if> = -<ma||fi>
+  permute(ctx, I->ovvo, {0, 1, 3, 2}, mone, zero, I->ovov.p());
+  I->ovoo = ZTensor(ctx, {o, v, o, o});                      // <mb||ij> = conj <ij||mb>
+  permute(ctx, I->ooov, {2, 3, 0, 1}, one, zero, I->ovoo.p(), true);
+  I->vvoo = ZTensor(ctx, {o, o, v, v});                      // <ab||ij> stored as [i][j][a][b]
+  copy_conj(ctx, I->oovv.size(), I->oovv.p(), I->vvoo.p(), true);
+}
+
+}  // namespace fc

@@ -1,0 +1,148 @@
+// Internal declarations of libfnscc (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fnscc.h"
+
+namespace fc {
+
+using z = double2;  // complex FP64, interleaved (re, im)
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define FC_HIP(call)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw ::fc::Error(FC_EHIP, std::string(#call) + ": " + hipGetErrorString(e_) + " at " + \
+                                     __FILE__ + ":" + std::to_string(__LINE__));            \
+  } while (0)
+
+#define FC_REQUIRE(cond, code, msg)                 \
+  do {                                              \
+    if (!(cond)) throw ::fc::Error((code), (msg));  \
+  } while (0)
+
+}  // namespace fc
+
+// ----------------------------------------------------------------------------------------------
+// Context: device, stream, allocator callbacks, a size-keyed cache of freed blocks.
+struct fc_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  fc_alloc_fn alloc = nullptr;
+  fc_free_fn release = nullptr;
+  void* user = nullptr;
+  std::string last_error;
+  std::multimap<size_t, void*> cache;          // freed blocks kept for reuse
+  std::unordered_map<void*, size_t> live;      // pointer -> rounded size
+  size_t cached_bytes = 0;
+  int verbose = 0;
+  // per-stage timers (ms), filled when timing is enabled
+  int timing = 0;
+  std::map<std::string, double> stage_ms;
+  std::map<std::string, long> stage_calls;
+  // hipEvents bracketing ladder launches (measured on this context's stream)
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ladder_events;
+};
+
+namespace fc {
+
+void* dmalloc(fc_ctx ctx, size_t bytes);
+void dfree(fc_ctx ctx, void* p);
+void release_cache(fc_ctx ctx);
+
+// Owning device buffer (freed back into the context cache).
+struct DBuf {
+  fc_ctx ctx = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(fc_ctx c, size_t b) : ctx(c), p(b ? dmalloc(c, b) : nullptr), bytes(b) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : ctx(o.ctx), p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { reset(); ctx = o.ctx; p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DBuf() { reset(); }
+  void reset() { if (p && ctx) dfree(ctx, p); p = nullptr; bytes = 0; }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Non-owning row-major complex tensor view.
+struct ZT {
+  z* p = nullptr;
+  std::vector<long> dims;
+  long size() const { long s = 1; for (long d : dims) s *= d; return s; }
+  ZT() = default;
+  ZT(z* p_, std::vector<long> d) : p(p_), dims(std::move(d)) {}
+};
+
+// Owning complex tensor.
+struct ZTensor {
+  DBuf buf;
+  std::vector<long> dims;
+  ZTensor() = default;
+  ZTensor(fc_ctx c, std::vector<long> d) : dims(std::move(d)) {
+    long s = 1; for (long x : dims) s *= x;
+    buf = DBuf(c, (size_t)s * sizeof(z));
+  }
+  z* p() const { return buf.as<z>(); }
+  long size() const { long s = 1; for (long d : dims) s *= d; return s; }
+  ZT view() const { return ZT(p(), dims); }
+  operator ZT() const { return view(); }
+};
+
+// ---------------------------------------------------------------- kernels (fc_gemm.hip)
+// Row-major complex GEMM, C = alpha * op(A) op(B) + beta * C, FP64 MFMA.
+// opA: 'N' A[m*lda+k], 'T' A[k*lda+m], 'C' conj(A[k*lda+m]), 'R' conj(A[m*lda+k]).
+// opB: 'N' B[k*ldb+n], 'T' B[n*ldb+k], 'C' conj(B[n*ldb+k]), 'R' conj(B[k*ldb+n]).
+void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+           const z* B, long ldb, z beta, z* C, long ldc, int batch = 1, long sA = 0, long sB = 0,
+           long sC = 0);
+
+// Split-precision variant (hi/lo BF16 or FP16 parts, FP32 accumulation, three products).
+void zgemm_split(fc_ctx ctx, int precision, char opA, char opB, long M, long N, long K, z alpha,
+                 const z* A, long lda, const z* B, long ldb, z beta, z* C, long ldc);
+
+// ---------------------------------------------------------------- tensor ops (fc_tensor.hip)
+void fill(fc_ctx ctx, z* p, long n, z value);
+void scale(fc_ctx ctx, z* p, long n, z alpha);
+void axpy(fc_ctx ctx, long n, z alpha, const z* x, z* y);               // y += alpha x
+void copy_conj(fc_ctx ctx, long n, const z* x, z* y, bool conj);
+// out[perm index] = alpha * op(in) + beta * out; in has dims `dims` (row-major), the output
+// dims are dims[perm[0]], dims[perm[1]], ...
+void permute(fc_ctx ctx, const ZT& in, const std::vector<int>& perm, z alpha, z beta, z* out,
+             bool conj = false);
+// Einstein-summation contraction of two tensors into a third (two operands, no batch indices):
+// C = alpha * sum A B + beta * C; conjA/conjB conjugate an operand.
+void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z beta, const ZT& C,
+          bool conjA = false, bool conjB = false);
+// r[i,j,a,b] += x - x^(a<->b) (mode 1), x - x^(i<->j) (mode 2),
+// x - x^(ij) - x^(ab) + x^(ij,ab) (mode 3); dims o,o,v,v.
+void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha);
+// Dot products with FP64 accumulation in a fixed order (deterministic).
+z dotu(fc_ctx ctx, long n, const z* x, const z* y);    // sum x*y
+z dotc(fc_ctx ctx, long n, const z* x, const z* y);    // sum conj(x)*y
+
+// Timing helper: adds elapsed stream time of a scope to ctx->stage_ms[name] when enabled.
+struct StageTimer {
+  fc_ctx ctx; std::string name; hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(fc_ctx c, const char* n);
+  ~StageTimer();
+};
+
+}  // namespace fc

@@ -1,0 +1,47 @@
+// Device-resident state behind the opaque handles of the C ABI.
+#pragma once
+#include "fc_internal.hpp"
+
+// Integrals in the (possibly natural-spinor) basis.  Cholesky vectors are stored per block with
+// the Cholesky index P fastest ([p][q][P]), the contraction dimension of every GEMM over P.
+struct fc_ints_s {
+  fc_ctx ctx = nullptr;
+  int o = 0, v = 0, ncd = 0, precision = FC_FP64;
+  std::vector<double> eps;        // host copy, n entries
+  fc::DBuf eps_d;                 // device copy
+  fc::ZTensor Loo, Lov, Lvo, Lvv; // L^P_ij, L^P_ia, L^P_ai, L^P_ab as [p][q][P]
+  // stored antisymmetrised integrals with <= 2 virtual indices (Sec. 3)
+  fc::ZTensor oooo, ooov, oovv, ovvo;  // <mn||ij>, <mn||ie>, <mn||ef>, <mb||ej>
+  // the same integrals re-indexed (symmetry copies kept for contiguous GEMM operands)
+  fc::ZTensor oovo, ovov, ovoo, vvoo;  // <mn||ej>, <ma||if>, <mb||ij>, <ab||ij> as [i][j][a][b]
+};
+
+// H-bar blocks with at most two virtual indices, built once from converged amplitudes.
+struct HbarBlocks {
+  fc::ZTensor Fmi, Fae, Fme;           // F-bar_mi, F-bar_ae, F-bar_me
+  fc::ZTensor Wmnij, Wmnie, Wmbej, Wmbij;
+  bool ready = false;
+};
+
+struct fc_amps_s {
+  fc_ctx ctx = nullptr;
+  fc_ints ints = nullptr;
+  fc::ZTensor t1, t2;   // [i][a], [i][j][a][b]
+  HbarBlocks hb;
+};
+
+namespace fc {
+// fc_ccsd.hip
+void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, z* r1, z* r2, int precision);
+void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision);
+z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2);
+void assemble_integrals(fc_ctx ctx, fc_ints I);
+// fc_eom.hip
+void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T);
+void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S);
+// fc_linalg.cpp (host FP64)
+void herm_eig(int n, std::vector<z>& A, std::vector<double>& w);           // A -> eigenvectors (columns)
+void gen_eig(int n, const std::vector<z>& A, std::vector<z>& w, std::vector<z>& VR);
+bool lin_solve(int n, std::vector<z> A, std::vector<z>& b);                  // partial pivoting
+double cond_herm(int n, const std::vector<z>& A);
+}  // namespace fc

@@ -1,0 +1,351 @@
+// Streaming tensor kernels (HBM-bound) and the two-operand contraction planner.
+#include <algorithm>
+#include <cstring>
+
+#include "fc_internal.hpp"
+
+namespace fc {
+
+// ------------------------------------------------------------------------------ memory
+static size_t round_up(size_t b) {
+  const size_t g = 256;
+  return (b + g - 1) / g * g;
+}
+
+void* dmalloc(fc_ctx ctx, size_t bytes) {
+  size_t rb = round_up(bytes);
+  auto it = ctx->cache.lower_bound(rb);
+  // reuse a cached block of the same size class (at most 1/8 larger)
+  if (it != ctx->cache.end() && it->first <= rb + rb / 8) {
+    void* p = it->second;
+    size_t sz = it->first;
+    ctx->cache.erase(it);
+    ctx->cached_bytes -= sz;
+    ctx->live[p] = sz;
+    return p;
+  }
+  void* p = nullptr;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (ctx->alloc) {
+      p = ctx->alloc(rb, (void*)ctx->stream, ctx->user);
+    } else {
+      if (hipMalloc(&p, rb) != hipSuccess) { (void)hipGetLastError(); p = nullptr; }
+    }
+    if (p) break;
+    release_cache(ctx);  // give cached blocks back and retry once
+  }
+  if (!p) throw Error(FC_ENOMEM, "device allocation of " + std::to_string(rb) + " bytes failed");
+  ctx->live[p] = rb;
+  return p;
+}
+
+void dfree(fc_ctx ctx, void* p) {
+  auto it = ctx->live.find(p);
+  if (it == ctx->live.end()) return;
+  ctx->cache.emplace(it->second, p);
+  ctx->cached_bytes += it->second;
+  ctx->live.erase(it);
+}
+
+void release_cache(fc_ctx ctx) {
+  if (ctx->cache.empty()) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->cache) {
+    if (ctx->release) ctx->release(kv.second, kv.first, (void*)ctx->stream, ctx->user);
+    else (void)hipFree(kv.second);
+  }
+  ctx->cache.clear();
+  ctx->cached_bytes = 0;
+}
+
+// ------------------------------------------------------------------------------ timers
+StageTimer::StageTimer(fc_ctx c, const char* n) : ctx(c), name(n) {
+  if (ctx->timing) {
+    FC_HIP(hipEventCreate(&a));
+    FC_HIP(hipEventCreate(&b));
+    FC_HIP(hipEventRecord(a, ctx->stream));
+  }
+}
+StageTimer::~StageTimer() {
+  if (!a) return;
+  float ms = 0.f;
+  if (hipEventRecord(b, ctx->stream) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+      hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+    ctx->stage_ms[name] += ms;
+    ctx->stage_calls[name] += 1;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+}
+
+// ------------------------------------------------------------------------------ elementwise
+namespace {
+constexpr int TPB = 256;
+inline unsigned nblocks(long n, long per = 1) {
+  long b = (n + TPB * per - 1) / (TPB * per);
+  if (b < 1) b = 1;
+  if (b > 1048576) b = 1048576;
+  return (unsigned)b;
+}
+__device__ inline z cmul(z a, z b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline z cadd(z a, z b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline z csub(z a, z b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+__global__ void k_fill(z* p, long n, z v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_scale(z* p, long n, z a) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = cmul(a, p[i]);
+}
+__global__ void k_axpy(long n, z a, const z* x, z* y) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    y[i] = cadd(y[i], cmul(a, x[i]));
+}
+__global__ void k_copy(long n, const z* x, z* y, int conj) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    z v = x[i];
+    if (conj) v.y = -v.y;
+    y[i] = v;
+  }
+}
+
+constexpr int MAXD = 8;
+struct PermArgs {
+  int nd;
+  long odims[MAXD];   // output dims (row-major)
+  long istr[MAXD];    // input stride of each output dim
+  long n;
+  z alpha, beta;
+  int conj, use_beta;
+};
+__global__ void k_permute(const z* __restrict__ in, z* __restrict__ out, PermArgs a) {
+  for (long o = blockIdx.x * (long)blockDim.x + threadIdx.x; o < a.n; o += (long)gridDim.x * blockDim.x) {
+    long rem = o, ioff = 0;
+    for (int d = a.nd - 1; d >= 0; --d) {
+      long c = rem % a.odims[d];
+      rem /= a.odims[d];
+      ioff += c * a.istr[d];
+    }
+    z v = in[ioff];
+    if (a.conj) v.y = -v.y;
+    z r = cmul(a.alpha, v);
+    if (a.use_beta) r = cadd(r, cmul(a.beta, out[o]));
+    out[o] = r;
+  }
+}
+
+// r[i,j,a,b] += alpha * P(..) x
+__global__ void k_antisym_add(z* __restrict__ r, const z* __restrict__ x, long o, long v, int mode, z alpha) {
+  const long n = o * o * v * v;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    long b = t % v, a = (t / v) % v, j = (t / (v * v)) % o, i = t / (v * v * o);
+    z val = x[t];
+    if (mode & 1) val = csub(val, x[((i * o + j) * v + b) * v + a]);
+    if (mode & 2) val = csub(val, x[((j * o + i) * v + a) * v + b]);
+    if (mode == 3) val = cadd(val, x[((j * o + i) * v + b) * v + a]);
+    r[t] = cadd(r[t], cmul(alpha, val));
+  }
+}
+
+// Deterministic dot product: fixed grid, fixed per-thread striding, fixed tree.
+constexpr int DOT_BLOCKS = 1024;
+__global__ void k_dot_partial(long n, const z* __restrict__ x, const z* __restrict__ y, int conjx, z* part) {
+  __shared__ double sr[TPB], si[TPB];
+  double ar = 0, ai = 0;
+  for (long i = blockIdx.x * (long)TPB + threadIdx.x; i < n; i += (long)DOT_BLOCKS * TPB) {
+    z a = x[i], b = y[i];
+    if (conjx) a.y = -a.y;
+    ar += a.x * b.x - a.y * b.y;
+    ai += a.x * b.y + a.y * b.x;
+  }
+  sr[threadIdx.x] = ar; si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sr[0], si[0]);
+}
+__global__ void k_dot_final(const z* part, z* out) {
+  __shared__ double sr[TPB], si[TPB];
+  double ar = 0, ai = 0;
+  for (int i = threadIdx.x; i < DOT_BLOCKS; i += TPB) { ar += part[i].x; ai += part[i].y; }
+  sr[threadIdx.x] = ar; si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = make_double2(sr[0], si[0]);
+}
+}  // namespace
+
+void fill(fc_ctx ctx, z* p, long n, z value) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, p, n, value);
+  FC_HIP(hipGetLastError());
+}
+void scale(fc_ctx ctx, z* p, long n, z alpha) {
+  if (n <= 0) return;
+  if (alpha.x == 0.0 && alpha.y == 0.0) { fill(ctx, p, n, make_double2(0, 0)); return; }
+  hipLaunchKernelGGL(k_scale, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, p, n, alpha);
+  FC_HIP(hipGetLastError());
+}
+void axpy(fc_ctx ctx, long n, z alpha, const z* x, z* y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpy, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, alpha, x, y);
+  FC_HIP(hipGetLastError());
+}
+void copy_conj(fc_ctx ctx, long n, const z* x, z* y, bool conj) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_copy, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, x, y, (int)conj);
+  FC_HIP(hipGetLastError());
+}
+
+void permute(fc_ctx ctx, const ZT& in, const std::vector<int>& perm, z alpha, z beta, z* out, bool conj) {
+  const int nd = (int)in.dims.size();
+  FC_REQUIRE((int)perm.size() == nd && nd <= MAXD, FC_EARG, "permute: bad rank");
+  PermArgs a;
+  a.nd = nd;
+  std::vector<long> istr(nd);
+  long s = 1;
+  for (int d = nd - 1; d >= 0; --d) { istr[d] = s; s *= in.dims[d]; }
+  a.n = s;
+  for (int d = 0; d < nd; ++d) { a.odims[d] = in.dims[perm[d]]; a.istr[d] = istr[perm[d]]; }
+  a.alpha = alpha; a.beta = beta; a.conj = conj;
+  a.use_beta = (beta.x != 0.0 || beta.y != 0.0);
+  if (a.n <= 0) return;
+  hipLaunchKernelGGL(k_permute, dim3(nblocks(a.n, 4)), dim3(TPB), 0, ctx->stream, in.p, out, a);
+  FC_HIP(hipGetLastError());
+}
+
+void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha) {
+  long n = o * o * v * v;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_antisym_add, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, r, x, o, v, mode, alpha);
+  FC_HIP(hipGetLastError());
+}
+
+static z dot_impl(fc_ctx ctx, long n, const z* x, const z* y, int conjx) {
+  if (n <= 0) return make_double2(0, 0);
+  DBuf part(ctx, sizeof(z) * (DOT_BLOCKS + 1));
+  hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(TPB), 0, ctx->stream, n, x, y, conjx, part.as<z>());
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(TPB), 0, ctx->stream, part.as<z>(), part.as<z>() + DOT_BLOCKS);
+  FC_HIP(hipGetLastError());
+  z h;
+  FC_HIP(hipMemcpyAsync(&h, part.as<z>() + DOT_BLOCKS, sizeof(z), hipMemcpyDeviceToHost, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  return h;
+}
+z dotu(fc_ctx ctx, long n, const z* x, const z* y) { return dot_impl(ctx, n, x, y, 0); }
+z dotc(fc_ctx ctx, long n, const z* x, const z* y) { return dot_impl(ctx, n, x, y, 1); }
+
+// ------------------------------------------------------------------------------ contraction planner
+// Transpose-transpose-GEMM-transpose: permute operands only when their index order does not
+// already form [free, summed] blocks, run one complex GEMM, and permute the product into C only
+// when C's order is neither [freeA, freeB] nor [freeB, freeA].
+namespace {
+struct Spec { std::string a, b, c; };
+Spec parse(const char* s) {
+  Spec r;
+  std::string str(s);
+  auto comma = str.find(','), arrow = str.find("->");
+  FC_REQUIRE(comma != std::string::npos && arrow != std::string::npos, FC_EARG, "zein: bad spec");
+  r.a = str.substr(0, comma);
+  r.b = str.substr(comma + 1, arrow - comma - 1);
+  r.c = str.substr(arrow + 2);
+  return r;
+}
+bool is_perm_of(const std::string& x, const std::string& set) {
+  if (x.size() != set.size()) return false;
+  for (char ch : x) if (set.find(ch) == std::string::npos) return false;
+  return true;
+}
+std::vector<int> perm_to(const std::string& from, const std::string& to) {
+  std::vector<int> p;
+  for (char ch : to) p.push_back((int)from.find(ch));
+  return p;
+}
+}  // namespace
+
+void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z beta, const ZT& C, bool conjA, bool conjB) {
+  Spec s = parse(spec);
+  FC_REQUIRE(s.a.size() == A.dims.size() && s.b.size() == B.dims.size() && s.c.size() == C.dims.size(),
+             FC_EARG, std::string("zein: rank mismatch in ") + spec);
+  std::map<char, long> dim;
+  auto reg = [&](const std::string& idx, const ZT& t) {
+    for (size_t k = 0; k < idx.size(); ++k) {
+      auto it = dim.find(idx[k]);
+      FC_REQUIRE(it == dim.end() || it->second == t.dims[k], FC_EARG, std::string("zein: dim mismatch in ") + spec);
+      dim[idx[k]] = t.dims[k];
+    }
+  };
+  reg(s.a, A); reg(s.b, B); reg(s.c, C);
+  std::string K, FA, FB;
+  for (char ch : s.a) {
+    bool inb = s.b.find(ch) != std::string::npos, inc = s.c.find(ch) != std::string::npos;
+    FC_REQUIRE(!(inb && inc), FC_EARG, std::string("zein: batch index unsupported in ") + spec);
+    FC_REQUIRE(inb || inc, FC_EARG, std::string("zein: index summed in one operand only in ") + spec);
+    if (inb) K += ch; else FA += ch;
+  }
+  for (char ch : s.b) {
+    bool ina = s.a.find(ch) != std::string::npos, inc = s.c.find(ch) != std::string::npos;
+    FC_REQUIRE(ina || inc, FC_EARG, std::string("zein: index summed in one operand only in ") + spec);
+    if (!ina) FB += ch;
+  }
+  FC_REQUIRE(is_perm_of(s.c, FA + FB), FC_EARG, std::string("zein: output indices mismatch in ") + spec);
+  auto prod = [&](const std::string& x) { long p = 1; for (char ch : x) p *= dim[ch]; return p; };
+  const long M = prod(FA), N = prod(FB), KK = prod(K);
+
+  // A operand: as [FA, K] (N) or [K, FA] (T) in A's own order, else permuted to [FA(C order), K].
+  std::string faOrd, kOrd;
+  const z* Ap = A.p; char opA; DBuf Atmp;
+  {
+    std::string pre = s.a.substr(0, FA.size()), post = s.a.substr(FA.size());
+    std::string pre2 = s.a.substr(0, K.size()), post2 = s.a.substr(K.size());
+    if (is_perm_of(pre, FA) && is_perm_of(post, K)) { faOrd = pre; kOrd = post; opA = conjA ? 'R' : 'N'; }
+    else if (is_perm_of(pre2, K) && is_perm_of(post2, FA)) { kOrd = pre2; faOrd = post2; opA = conjA ? 'C' : 'T'; }
+    else {
+      faOrd.clear();
+      for (char ch : s.c) if (FA.find(ch) != std::string::npos) faOrd += ch;
+      kOrd = K;
+      Atmp = DBuf(ctx, sizeof(z) * std::max(1L, A.size()));
+      permute(ctx, A, perm_to(s.a, faOrd + kOrd), make_double2(1, 0), make_double2(0, 0), Atmp.as<z>(), conjA);
+      Ap = Atmp.as<z>(); opA = 'N';
+    }
+  }
+  // B operand: [K(kOrd), FB] (N) or [FB, K(kOrd)] (T), else permuted to [K(kOrd), FB(C order)].
+  std::string fbOrd;
+  const z* Bp = B.p; char opB; DBuf Btmp;
+  {
+    std::string pre = s.b.substr(0, K.size()), post = s.b.substr(K.size());
+    std::string pre2 = s.b.substr(0, FB.size()), post2 = s.b.substr(FB.size());
+    if (pre == kOrd && is_perm_of(post, FB)) { fbOrd = post; opB = conjB ? 'R' : 'N'; }
+    else if (post2 == kOrd && is_perm_of(pre2, FB)) { fbOrd = pre2; opB = conjB ? 'C' : 'T'; }
+    else {
+      fbOrd.clear();
+      for (char ch : s.c) if (FB.find(ch) != std::string::npos) fbOrd += ch;
+      Btmp = DBuf(ctx, sizeof(z) * std::max(1L, B.size()));
+      permute(ctx, B, perm_to(s.b, kOrd + fbOrd), make_double2(1, 0), make_double2(0, 0), Btmp.as<z>(), conjB);
+      Bp = Btmp.as<z>(); opB = 'N';
+    }
+  }
+  const long lda = (opA == 'N' || opA == 'R') ? KK : M;
+  const long ldb = (opB == 'N' || opB == 'R') ? N : KK;
+  if (s.c == faOrd + fbOrd) {
+    zgemm(ctx, opA, opB, M, N, KK, alpha, Ap, lda, Bp, ldb, beta, C.p, N);
+  } else if (s.c == fbOrd + faOrd) {
+    // C^T = op(B)^T op(A)^T: swap operands and flip their transposition.
+    auto flip = [](char op) { return op == 'N' ? 'T' : op == 'T' ? 'N' : op == 'R' ? 'C' : 'R'; };
+    zgemm(ctx, flip(opB), flip(opA), N, M, KK, alpha, Bp, ldb, Ap, lda, beta, C.p, M);
+  } else {
+    DBuf Ctmp(ctx, sizeof(z) * std::max(1L, M * N));
+    zgemm(ctx, opA, opB, M, N, KK, make_double2(1, 0), Ap, lda, Bp, ldb, make_double2(0, 0), Ctmp.as<z>(), N);
+    std::vector<long> tdims;
+    std::string tord = faOrd + fbOrd;
+    for (char ch : tord) tdims.push_back(dim[ch]);
+    permute(ctx, ZT(Ctmp.as<z>(), tdims), perm_to(tord, s.c), alpha, beta, C.p);
+  }
+}
+
+}  // namespace fc

@@ -1,0 +1,333 @@
+"""Thin ctypes binding of libfnscc (argument marshalling only).
+
+Every step of the hot path runs inside the HIP library.  PyTorch supplies the device memory (its
+caching allocator, through the allocator callbacks of fc_create) and the stream.  Loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import pathlib
+
+import numpy as np
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfnscc.so"
+if not _LIB_PATH.exists():
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2506_06805_amd.build`")
+lib = C.CDLL(str(_LIB_PATH))
+
+FC_OK, FC_EARG, FC_EHIP, FC_ENOMEM, FC_ENOCONV, FC_ENUMERIC, FC_EUNSUPPORTED = range(7)
+FC_C128, FC_C64 = 0, 1
+FC_FP64, FC_SPLIT_BF16, FC_SPLIT_FP16 = 0, 1, 2
+PRECISION = {"fp64": FC_FP64, "split-bf16": FC_SPLIT_BF16, "split-fp16": FC_SPLIT_FP16}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class CcsdOpts(C.Structure):
+    _fields_ = [("e_tol", C.c_double), ("r_tol", C.c_double), ("max_iter", C.c_int), ("diis_dim", C.c_int),
+                ("learned", C.c_int), ("precision", C.c_int), ("t1_init", C.c_void_p), ("t2_init", C.c_void_p),
+                ("mlp", C.c_void_p), ("stall_window", C.c_int)]
+
+
+class EomOpts(C.Structure):
+    _fields_ = [("r_tol", C.c_double), ("w_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
+                ("guess_per_root", C.c_int)]
+
+
+P = C.c_void_p
+_sig = {
+    "fc_create": (C.c_int, [C.POINTER(P), C.c_int, P, ALLOC_FN, FREE_FN, P]),
+    "fc_destroy": (None, [P]),
+    "fc_last_error": (C.c_char_p, [P]),
+    "fc_set_timing": (C.c_int, [P, C.c_int]),
+    "fc_take_timings": (C.c_int, [P, C.c_char_p, C.c_size_t]),
+    "cd_integrals": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(P)]),
+    "fc_ints_info": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "fc_free_ints": (None, [P]),
+    "fns_truncate": (C.c_int, [P, P, C.c_double, C.POINTER(P), C.POINTER(C.c_int), P, P]),
+    "fc_ccsd_default_opts": (None, [C.POINTER(CcsdOpts)]),
+    "ccsd_solve": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(CcsdOpts), C.POINTER(P), P, P]),
+    "ccsd_residual": (C.c_int, [P, P, P, P, P, P, C.c_int]),
+    "fc_ladder": (C.c_int, [P, P, P, P, P, C.c_int]),
+    "fc_amps_create": (C.c_int, [P, P, P, P, C.POINTER(P)]),
+    "fc_amps_read": (C.c_int, [P, P, P]),
+    "fc_free_amps": (None, [P]),
+    "ipeom_sigma": (C.c_int, [P, P, P, C.c_int, P, P]),
+    "fc_eom_default_opts": (None, [C.POINTER(EomOpts)]),
+    "ipeom_davidson": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P), P, C.POINTER(EomOpts), P, P, P]),
+    "fc_host_zheev": (C.c_int, [C.c_int, P, P]),
+    "fc_host_zgeev": (C.c_int, [C.c_int, P, P, P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+class FcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    """Address of a numpy array or a torch tensor (contiguous)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return a.ctypes.data
+    assert a.is_contiguous()
+    return a.data_ptr()
+
+
+# ------------------------------------------------------------------------------ host utilities
+def host_zheev(A):
+    A = np.array(A, dtype=np.complex128, order="C")
+    n = A.shape[0]
+    w = np.zeros(n)
+    rc = lib.fc_host_zheev(n, A.ctypes.data, w.ctypes.data)
+    if rc:
+        raise FcError(rc, "fc_host_zheev failed")
+    return w, A
+
+
+def host_zgeev(A):
+    A = np.ascontiguousarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    w = np.zeros(n, dtype=np.complex128)
+    V = np.zeros((n, n), dtype=np.complex128)
+    rc = lib.fc_host_zgeev(n, A.ctypes.data, w.ctypes.data, V.ctypes.data)
+    if rc:
+        raise FcError(rc, "fc_host_zgeev failed")
+    return w, V
+
+
+# ------------------------------------------------------------------------------ device context
+class Context:
+    """fc_ctx bound to a torch device and its current stream; device memory from torch."""
+
+    def __init__(self, device=0, stream=None, use_torch_allocator=True):
+        import torch
+
+        self.torch = torch
+        self.device = device
+        self.stream = stream or torch.cuda.current_stream(device)
+        self._live = {}
+        if use_torch_allocator:
+            def _alloc(nbytes, _stream, _user):
+                try:
+                    p = torch.cuda.caching_allocator_alloc(int(nbytes), device, self.stream)
+                except Exception:  # out of memory: the library reports FC_ENOMEM
+                    return None
+                return p
+
+            def _free(ptr, _nbytes, _stream, _user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cb = ALLOC_FN(_alloc)
+            self._free_cb = FREE_FN(_free)
+        else:
+            self._alloc_cb = ALLOC_FN()
+            self._free_cb = FREE_FN()
+        h = P()
+        rc = lib.fc_create(C.byref(h), device, P(self.stream.cuda_stream), self._alloc_cb, self._free_cb, None)
+        if rc:
+            raise FcError(rc, "fc_create failed")
+        self.h = h
+
+    def check(self, rc, what):
+        if rc not in (FC_OK,):
+            raise FcError(rc, f"{what}: {lib.fc_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.fc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on=True):
+        lib.fc_set_timing(self.h, int(on))
+
+    def take_timings(self):
+        buf = C.create_string_buffer(1 << 16)
+        lib.fc_take_timings(self.h, buf, len(buf))
+        out = {}
+        for kv in buf.value.decode().split(";"):
+            if "=" in kv:
+                k, v = kv.split("=")
+                out[k] = float(v)
+        return out
+
+
+class Ints:
+    def __init__(self, ctx: Context, h, o, v, ncd):
+        self.ctx, self.h, self.o, self.v, self.ncd = ctx, h, o, v, ncd
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.fc_free_ints(self.h)
+            self.h = None
+
+    @property
+    def dim(self):
+        return self.o + self.o * (self.o - 1) // 2 * self.v
+
+
+class Amps:
+    def __init__(self, ctx: Context, ints: Ints, h):
+        self.ctx, self.ints, self.h = ctx, ints, h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.fc_free_amps(self.h)
+            self.h = None
+
+    def read(self):
+        torch = self.ctx.torch
+        o, v = self.ints.o, self.ints.v
+        t1 = torch.empty((o, v), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        t2 = torch.empty((o, o, v, v), dtype=torch.complex128, device=f"cuda:{self.ctx.device}")
+        self.ctx.check(lib.fc_amps_read(self.h, t1.data_ptr(), t2.data_ptr()), "fc_amps_read")
+        return t1, t2
+
+
+def cd_integrals(ctx: Context, eps, L, o, precision="fp64"):
+    """Stage Cholesky vectors L[P, p, q] (numpy host array or torch device tensor) and build integrals."""
+    eps = np.ascontiguousarray(eps, dtype=np.float64)
+    n = eps.shape[0]
+    v = n - o
+    ncd = L.shape[0]
+    if isinstance(L, np.ndarray):
+        L = np.ascontiguousarray(L)
+        dt = FC_C128 if L.dtype == np.complex128 else FC_C64
+        on_dev = 0
+    else:
+        import torch
+        dt = FC_C128 if L.dtype == torch.complex128 else FC_C64
+        on_dev = 1
+    h = P()
+    rc = lib.cd_integrals(ctx.h, o, v, ncd, eps.ctypes.data, _ptr(L), dt, on_dev,
+                          PRECISION.get(precision, precision), C.byref(h))
+    ctx.check(rc, "cd_integrals")
+    return Ints(ctx, h, o, v, ncd)
+
+
+def fns_truncate(ctx: Context, ints: Ints, thresh):
+    vk = C.c_int()
+    occ = np.zeros(ints.v)
+    h = P()
+    rc = lib.fns_truncate(ctx.h, ints.h, float(thresh), C.byref(h), C.byref(vk), occ.ctypes.data, None)
+    ctx.check(rc, "fns_truncate")
+    return Ints(ctx, h, ints.o, vk.value, ints.ncd), occ
+
+
+def ccsd_opts(**kw):
+    op = CcsdOpts()
+    lib.fc_ccsd_default_opts(C.byref(op))
+    for k, val in kw.items():
+        if k == "precision":
+            val = PRECISION.get(val, val)
+        setattr(op, k, val)
+    return op
+
+
+def ccsd_solve(ctx: Context, ints, allow_noconv=False, **kw):
+    """Returns (E_corr complex, iterations, Amps) for one handle or lists for several."""
+    single = isinstance(ints, Ints)
+    lst = [ints] if single else list(ints)
+    nb = len(lst)
+    arr = (P * nb)(*[x.h for x in lst])
+    outs = (P * nb)()
+    e = np.zeros(2 * nb)
+    it = np.zeros(nb, dtype=np.int32)
+    op = ccsd_opts(**kw)
+    rc = lib.ccsd_solve(ctx.h, nb, arr, C.byref(op), outs, e.ctypes.data, it.ctypes.data)
+    if rc == FC_ENOCONV and allow_noconv:
+        rc = FC_OK
+    amps = [Amps(ctx, x, P(outs[b])) for b, x in enumerate(lst)]
+    ctx.check(rc, "ccsd_solve")
+    E = e[0::2] + 1j * e[1::2]
+    if single:
+        return complex(E[0]), int(it[0]), amps[0]
+    return E, it, amps
+
+
+def ccsd_residual(ctx: Context, ints: Ints, t1, t2, precision=-1):
+    torch = ctx.torch
+    r1 = torch.empty_like(t1)
+    r2 = torch.empty_like(t2)
+    ctx.check(lib.ccsd_residual(ctx.h, ints.h, _ptr(t1), _ptr(t2), _ptr(r1), _ptr(r2),
+                                PRECISION.get(precision, precision)), "ccsd_residual")
+    return r1, r2
+
+
+def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
+    torch = ctx.torch
+    R = out if out is not None else torch.empty_like(tau)
+    ctx.check(lib.fc_ladder(ctx.h, ints.h, _ptr(tau), _ptr(t1), _ptr(R), PRECISION.get(precision, precision)),
+              "fc_ladder")
+    return R
+
+
+def amps_create(ctx: Context, ints: Ints, t1, t2):
+    h = P()
+    ctx.check(lib.fc_amps_create(ctx.h, ints.h, _ptr(t1), _ptr(t2), C.byref(h)), "fc_amps_create")
+    return Amps(ctx, ints, h)
+
+
+def ipeom_sigma(ctx: Context, ints: Ints, amps: Amps, R):
+    torch = ctx.torch
+    R = R.contiguous()
+    if R.dim() == 1:
+        R = R[None]
+    S = torch.empty_like(R)
+    ctx.check(lib.ipeom_sigma(ctx.h, ints.h, amps.h, R.shape[0], _ptr(R), _ptr(S)), "ipeom_sigma")
+    return S
+
+
+def eom_opts(**kw):
+    op = EomOpts()
+    lib.fc_eom_default_opts(C.byref(op))
+    for k, val in kw.items():
+        setattr(op, k, val)
+    return op
+
+
+def ipeom_davidson(ctx: Context, ints, amps, nroots, want_vectors=False, allow_noconv=False, **kw):
+    """Lowest-nroots IPs (complex, ascending real part); optionally the right eigenvectors."""
+    torch = ctx.torch
+    single = isinstance(ints, Ints)
+    il = [ints] if single else list(ints)
+    al = [amps] if single else list(amps)
+    nr = [nroots] * len(il) if isinstance(nroots, int) else list(nroots)
+    nb = len(il)
+    ai = (P * nb)(*[x.h for x in il])
+    aa = (P * nb)(*[x.h for x in al])
+    nra = np.array(nr, dtype=np.int32)
+    om = np.zeros(2 * sum(nr))
+    its = np.zeros(nb, dtype=np.int32)
+    Rout = None
+    if want_vectors:
+        Rout = torch.empty(sum(k * x.dim for k, x in zip(nr, il)), dtype=torch.complex128,
+                           device=f"cuda:{ctx.device}")
+    op = eom_opts(**kw)
+    rc = lib.ipeom_davidson(ctx.h, nb, ai, aa, nra.ctypes.data, C.byref(op), om.ctypes.data, _ptr(Rout),
+                            its.ctypes.data)
+    if rc == FC_ENOCONV and allow_noconv:
+        rc = FC_OK
+    ctx.check(rc, "ipeom_davidson")
+    w = om[0::2] + 1j * om[1::2]
+    if single:
+        vecs = Rout.view(nr[0], il[0].dim) if want_vectors else None
+        return (w, int(its[0]), vecs) if want_vectors else (w, int(its[0]))
+    return (w, its, Rout) if want_vectors else (w, its)
