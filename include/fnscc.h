@@ -49,9 +49,11 @@ int fc_create(fc_ctx* ctx, int device, void* hip_stream, fc_alloc_fn alloc, fc_f
               void* user);
 void fc_destroy(fc_ctx ctx);
 const char* fc_last_error(fc_ctx ctx);
-/* Per-stage stream timings (milliseconds) accumulated while timing is on. */
-int fc_set_timing(fc_ctx ctx, int on);
-/* Writes "name=ms;name=ms;..." into buf (truncated to len) and clears the timers. */
+/* Timing flags: bit 0 = per-stage stream timers (each stage synchronises the stream);
+ * bit 1 = hipEvents around every ladder evaluation on the context stream (no synchronisation). */
+int fc_set_timing(fc_ctx ctx, int flags);
+/* Writes "name=ms;...;ladder_events=n;ladder_event_ms=ms;calls_name=n;..." into buf (truncated
+ * to len) and clears the timers. */
 int fc_take_timings(fc_ctx ctx, char* buf, size_t len);
 
 /* cd_integrals - stage the Cholesky vectors (Eq. 22) and assemble the stored antisymmetrised

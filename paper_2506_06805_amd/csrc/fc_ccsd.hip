@@ -138,7 +138,7 @@ static DBuf pair_table(fc_ctx ctx, long n, long& np) {
 void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision) {
   StageTimer st(ctx, "ladder");
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (ctx->timing) {
+  if (ctx->timing & 2) {
     FC_HIP(hipEventCreate(&ev0)); FC_HIP(hipEventCreate(&ev1));
     FC_HIP(hipEventRecord(ev0, ctx->stream));
   }
@@ -151,7 +151,10 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
   long no, nv;
   DBuf po = pair_table(ctx, o, no), pv = pair_table(ctx, v, nv);
   fill(ctx, R, o * o * v * v, zero);
-  if (no == 0 || nv == 0) return;
+  if (no == 0 || nv == 0) {
+    if (ev0) { FC_HIP(hipEventRecord(ev1, ctx->stream)); ctx->ladder_events.emplace_back(ev0, ev1); }
+    return;
+  }
   DBuf taup(ctx, sizeof(z) * no * nv);
   hipLaunchKernelGGL(k_pack_tau, dim3(nblk(no * nv)), dim3(TPB), 0, ctx->stream, tau, taup.as<z>(), o, v,
                      po.as<int2>(), pv.as<int2>(), no, nv);

@@ -8,6 +8,7 @@
 // MFMA f64 16x16x4 lane layout (lane l of a 64-wide wave):
 //   A fragment: A[row = l % 16][k = l / 16];  B fragment: B[k = l / 16][col = l % 16];
 //   accumulator register r: D[row = l / 16 + 4 * r][col = l % 16]  (measured on gfx950).
+#include <algorithm>
 #include <cstring>
 
 #include "fc_internal.hpp"
@@ -28,6 +29,8 @@ struct GemmArgs {
   z* C; long ldc; long sC;
   z alpha, beta;
   int conjA, conjB;
+  long kchunk;        // K range per split (multiple of BK); blockIdx.y selects the split
+  z* part;            // split-K partial products [split][M][N] (nullptr: write C directly)
 };
 
 // TA: A stored K-major (A[k*lda+m]); TB: B stored K-minor (B[n*ldb+k]).
@@ -46,6 +49,8 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmArgs g) {
   const z* __restrict__ B = g.B + (long)blockIdx.z * g.sB;
   z* __restrict__ C = g.C + (long)blockIdx.z * g.sC;
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  const long klo = (long)blockIdx.y * g.kchunk;
+  const long khi = klo + g.kchunk < g.K ? klo + g.kchunk : g.K;
 
   // Each thread stages two complex elements of A and two of B per BK step.
   z ra[2], rb[2];
@@ -57,13 +62,13 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmArgs g) {
       if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
       long gm = m0 + mm, gk = k0 + kk;
       z val = make_double2(0.0, 0.0);
-      if (gm < g.M && gk < g.K) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
+      if (gm < g.M && gk < khi) val = TA ? A[gk * g.lda + gm] : A[gm * g.lda + gk];
       ra[r] = val;
       int nn;
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
       long gn = n0 + nn; gk = k0 + kk;
       val = make_double2(0.0, 0.0);
-      if (gn < g.N && gk < g.K) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
+      if (gn < g.N && gk < khi) val = TB ? B[gn * g.ldb + gk] : B[gk * g.ldb + gn];
       rb[r] = val;
     }
   };
@@ -88,14 +93,14 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) { cr[i][j] = d4{0, 0, 0, 0}; ci[i][j] = d4{0, 0, 0, 0}; }
 
-  const long nk = (g.K + BK - 1) / BK;
-  load_tile(0);
+  const long nk = (khi - klo + BK - 1) / BK;
+  load_tile(klo);
   store_tile(0);
   __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
   for (long kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load_tile((kt + 1) * BK);
+    if (kt + 1 < nk) load_tile(klo + (kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       double ar[2], ai[2], nai[2], br[2], bi[2];
@@ -131,6 +136,20 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmArgs g) {
     __syncthreads();
   }
 
+  if (g.part) {  // split-K: raw partial sums, reduced in a fixed order by k_splitk_reduce
+    z* P = g.part + (long)blockIdx.y * g.M * g.N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          long m = m0 + wm + 16 * i + lk + 4 * r;
+          long n = n0 + wn + 16 * j + lr;
+          if (m < g.M && n < g.N) P[m * g.N + n] = make_double2(cr[i][j][r], ci[i][j][r]);
+        }
+    return;
+  }
   const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -151,6 +170,25 @@ __global__ __launch_bounds__(NT) void zgemm_f64_kernel(GemmArgs g) {
           C[m * g.ldc + n] = out;
         }
       }
+}
+
+// C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic)
+__global__ void k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N, z* __restrict__ C, long ldc,
+                                z alpha, z beta) {
+  const long MN = M * N;
+  const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < MN; t += (long)gridDim.x * blockDim.x) {
+    double re = 0, im = 0;
+    for (int s = 0; s < ns; ++s) { z p = P[s * MN + t]; re += p.x; im += p.y; }
+    long m = t / N, n = t % N;
+    z out = make_double2(alpha.x * re - alpha.y * im, alpha.x * im + alpha.y * re);
+    if (use_beta) {
+      z c0 = C[m * ldc + n];
+      out.x += beta.x * c0.x - beta.y * c0.y;
+      out.y += beta.x * c0.y + beta.y * c0.x;
+    }
+    C[m * ldc + n] = out;
+  }
 }
 
 }  // namespace
@@ -177,12 +215,35 @@ void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, cons
   FC_REQUIRE(batch <= 65535, FC_EARG, "zgemm: batch too large");
   const long tiles = ((N + BN - 1) / BN) * ((M + BM - 1) / BM);
   FC_REQUIRE(tiles < (1L << 31), FC_EARG, "zgemm: problem too large for one launch");
-  dim3 grid((unsigned)tiles, 1, (unsigned)batch);
+  // Split K when the tile grid cannot fill the chip (256 CUs): each split covers >= 8 BK steps,
+  // partials go to a workspace and are summed in split order, so results stay deterministic.
+  long ksplit = 1;
+  const long want = 1024;
+  if (batch == 1 && tiles < want && K >= 16 * BK) {
+    ksplit = std::min((want + tiles - 1) / tiles, K / (8 * BK));
+    const long cap = std::max(1L, (256L << 20) / (long)(sizeof(z) * M * N));
+    ksplit = std::max(1L, std::min({ksplit, cap, 4096L}));
+  }
+  g.kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
+  ksplit = (K + g.kchunk - 1) / g.kchunk;
+  g.part = nullptr;
+  DBuf work;
+  if (ksplit > 1) {
+    work = DBuf(ctx, sizeof(z) * (size_t)ksplit * M * N);
+    g.part = work.as<z>();
+  }
+  dim3 grid((unsigned)tiles, (unsigned)ksplit, (unsigned)batch);
   if (!ta && !tb) zgemm_f64_kernel<false, false><<<grid, NT, 0, ctx->stream>>>(g);
   else if (!ta && tb) zgemm_f64_kernel<false, true><<<grid, NT, 0, ctx->stream>>>(g);
   else if (ta && !tb) zgemm_f64_kernel<true, false><<<grid, NT, 0, ctx->stream>>>(g);
   else zgemm_f64_kernel<true, true><<<grid, NT, 0, ctx->stream>>>(g);
   FC_HIP(hipGetLastError());
+  if (ksplit > 1) {
+    const long MN = M * N;
+    unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 255) / 256));
+    k_splitk_reduce<<<nb, 256, 0, ctx->stream>>>(g.part, (int)ksplit, M, N, C, ldc, alpha, beta);
+    FC_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace fc

@@ -50,7 +50,7 @@ struct fc_ctx_s {
   size_t cached_bytes = 0;
   int verbose = 0;
   // per-stage timers (ms), filled when timing is enabled
-  int timing = 0;
+  int timing = 0;          // bit 0: per-stage timers (synchronising); bit 1: ladder events only
   std::map<std::string, double> stage_ms;
   std::map<std::string, long> stage_calls;
   // hipEvents bracketing ladder launches (measured on this context's stream)

@@ -60,7 +60,7 @@ void release_cache(fc_ctx ctx) {
 
 // ------------------------------------------------------------------------------ timers
 StageTimer::StageTimer(fc_ctx c, const char* n) : ctx(c), name(n) {
-  if (ctx->timing) {
+  if (ctx->timing & 1) {
     FC_HIP(hipEventCreate(&a));
     FC_HIP(hipEventCreate(&b));
     FC_HIP(hipEventRecord(a, ctx->stream));
