@@ -52,21 +52,24 @@ def intermediates(g: Blocks, t1, t2):
     return Fae, Fmi, Fme, Wmnij, Wmbej
 
 
-def ladder(g: Blocks, t1, t2):
+def ladder(g: Blocks, t1, t2, rows=None):
     """1/2 sum_ef tau_ij^ef W_abef, with
     W_abef = <ab||ef> - P(ab) sum_m t_m^b <am||ef> + 1/4 sum_mn tau_mn^ab <mn||ef>.
 
     W_abef is formed one leading virtual index a at a time; the <ab||ef> part
-    is rebuilt from the Cholesky vectors each call (Eq. 23).
+    is rebuilt from the Cholesky vectors each call (Eq. 23).  `rows` limits
+    the loop to some values of a (used only to time a sample).
     """
     _, tau = taus(t1, t2)
     o, v = t1.shape
     out = np.zeros((o, o, v, v), dtype=np.complex128)
-    for a in range(v):
+    has_t1 = bool(np.any(t1))
+    for a in (range(v) if rows is None else rows):
         W = g.vvvv_row(a)                                              # <ab||ef>, (b,e,f)
-        # - P(ab) sum_m t_m^b <am||ef> = - sum_m t_m^b <am||ef> + sum_m t_m^a <bm||ef>
-        W -= ein("mb,mef->bef", t1, g.vovv[a])
-        W += ein("m,bmef->bef", t1[:, a], g.vovv)
+        if has_t1:
+            # - P(ab) sum_m t_m^b <am||ef> = - sum_m t_m^b <am||ef> + sum_m t_m^a <bm||ef>
+            W -= ein("mb,mef->bef", t1, g.vovv[a])
+            W += ein("m,bmef->bef", t1[:, a], g.vovv)
         W += 0.25 * ein("mnb,mnef->bef", tau[:, :, a, :], g.oovv)
         out[:, :, a, :] = 0.5 * ein("ijef,bef->ijb", tau, W)
     return out

@@ -29,7 +29,7 @@ def full_antisym(L):
 
 
 class Blocks:
-    """The integral blocks the CCSD and IP-EOM equations use, built on demand.
+    """The integral blocks the CCSD and IP-EOM equations use, each built on first use.
 
     Blocks with at most two virtual indices are the ones the paper stores
     (Sec. 3); the three-virtual blocks here are plain full arrays (the
@@ -37,25 +37,27 @@ class Blocks:
     produced one leading index at a time by `vvvv_row`.
     """
 
+    _SLICES = {
+        "oooo": "OOOO", "ooov": "OOOV", "oovo": "OOVO", "oovv": "OOVV", "ovov": "OVOV",
+        "ovvo": "OVVO", "ovoo": "OVOO", "vvoo": "VVOO", "ovvv": "OVVV", "vovv": "VOVV",
+        "vvvo": "VVVO",
+    }
+
     def __init__(self, L, o):
         self.L = np.asarray(L, dtype=np.complex128)
         self.o = o
         self.n = self.L.shape[1]
         self.v = self.n - o
-        O, V = slice(0, o), slice(o, self.n)
-        self.O, self.V = O, V
-        g = lambda a, b, c, d: antisym(self.L, a, b, c, d)
-        self.oooo = g(O, O, O, O)
-        self.ooov = g(O, O, O, V)
-        self.oovo = g(O, O, V, O)
-        self.oovv = g(O, O, V, V)
-        self.ovov = g(O, V, O, V)
-        self.ovvo = g(O, V, V, O)
-        self.ovoo = g(O, V, O, O)
-        self.vvoo = g(V, V, O, O)
-        self.ovvv = g(O, V, V, V)
-        self.vovv = g(V, O, V, V)
-        self.vvvo = g(V, V, V, O)
+        self.O, self.V = slice(0, o), slice(o, self.n)
+
+    def __getattr__(self, name):
+        kinds = Blocks._SLICES.get(name)
+        if kinds is None:
+            raise AttributeError(name)
+        sl = [self.O if k == "O" else self.V for k in kinds]
+        block = antisym(self.L, *sl)
+        setattr(self, name, block)
+        return block
 
     def vvvv_row(self, a):
         """<ab||ef> for a fixed first virtual index a: shape (v, v, v) over (b, e, f)."""

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "fc_split.hpp"
 #include "fc_state.hpp"
 
 namespace fc {
@@ -104,6 +105,19 @@ __global__ void k_ladder_anti(const z* __restrict__ W, z* __restrict__ Wp, long 
     Wp[t] = make_double2(x.x - y.x, x.y - y.y);
   }
 }
+// transposed layout for the split-precision contraction: WpT[(a-a0)*nB + (b-b0)][pef]
+__global__ void k_ladder_anti_t(const z* __restrict__ W, z* __restrict__ WpT, long v, long nA, long nB,
+                                const int2* pv, long nv) {
+  const long nab = nA * nB, ldw = nB * v;
+  GRID_STRIDE(t, nv * nab) {
+    long pe = t % nv, ab = t / nv;
+    long a = ab / nB, b = ab % nB;
+    int2 ef = pv[pe];
+    z x = W[(a * v + ef.x) * ldw + b * v + ef.y];
+    z y = W[(a * v + ef.y) * ldw + b * v + ef.x];
+    WpT[t] = make_double2(x.x - y.x, x.y - y.y);
+  }
+}
 // R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][(a-a0)*nB + (b-b0)]
 __global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, long a0, long nA,
                                  long b0, long nB, const int2* po, long no, int diag) {
@@ -163,26 +177,31 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
   long T = (long)std::floor(std::sqrt(budget / (16.0 * (double)v * (double)v)));
   T = std::max(1L, std::min(T, v));
   DBuf W(ctx, sizeof(z) * T * v * T * v), Wp(ctx, sizeof(z) * nv * T * T), Rp(ctx, sizeof(z) * no * T * T);
+  const bool split = precision != FC_FP64;
+  SplitOp Ls, Ts;
+  if (split) {  // hi/lo planes of the dressed vectors and of tau, once per evaluation
+    Ls = split_operand(ctx, precision, Lb.p(), v * v, N, N);
+    Ts = split_operand(ctx, precision, taup.as<z>(), no, nv, nv);
+  }
   for (long a0 = 0; a0 < v; a0 += T) {
     const long nA = std::min(T, v - a0);
     for (long b0 = a0; b0 < v; b0 += T) {
       const long nB = std::min(T, v - b0);
-      // W[(a,e),(b,f)] = sum_P Lb[a,e,P] Lb[b,f,P]
-      if (precision == FC_FP64)
+      // W[(a,e),(b,f)] = sum_P Lb[a,e,P] Lb[b,f,P];  Rp[pij][ab] = sum_pef taup[pij][pef] Wp[pef][ab]
+      if (!split) {
         zgemm(ctx, 'N', 'T', nA * v, nB * v, N, one, Lb.p() + a0 * v * N, N, Lb.p() + b0 * v * N, N, zero,
               W.as<z>(), nB * v);
-      else
-        zgemm_split(ctx, precision, 'N', 'T', nA * v, nB * v, N, one, Lb.p() + a0 * v * N, N,
-                    Lb.p() + b0 * v * N, N, zero, W.as<z>(), nB * v);
-      hipLaunchKernelGGL(k_ladder_anti, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
-                         Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
-      // Rp[pij][ab] = sum_pef taup[pij][pef] Wp[pef][ab]
-      if (precision == FC_FP64)
+        hipLaunchKernelGGL(k_ladder_anti, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
+                           Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
         zgemm(ctx, 'N', 'N', no, nA * nB, nv, one, taup.as<z>(), nv, Wp.as<z>(), nA * nB, zero, Rp.as<z>(),
               nA * nB);
-      else
-        zgemm_split(ctx, precision, 'N', 'N', no, nA * nB, nv, one, taup.as<z>(), nv, Wp.as<z>(), nA * nB,
-                    zero, Rp.as<z>(), nA * nB);
+      } else {
+        gemm_split_nt(ctx, Ls, a0 * v, nA * v, Ls, b0 * v, nB * v, one, zero, W.as<z>(), nB * v);
+        hipLaunchKernelGGL(k_ladder_anti_t, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
+                           Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
+        SplitOp Ws = split_operand(ctx, precision, Wp.as<z>(), nA * nB, nv, nv);
+        gemm_split_nt(ctx, Ts, 0, no, Ws, 0, nA * nB, one, zero, Rp.as<z>(), nA * nB);
+      }
       hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nA * nB)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R,
                          o, v, a0, nA, b0, nB, po.as<int2>(), no, (int)(a0 == b0));
       FC_HIP(hipGetLastError());

@@ -1,0 +1,20 @@
+// Split-precision operands (hi/lo 16-bit planes) and the NT product on them.
+#pragma once
+#include "fc_internal.hpp"
+
+namespace fc {
+
+struct SplitOp {
+  DBuf buf;            // planes re_hi, re_lo, im_hi, im_lo, each [rows_pad][kp] (16-bit)
+  long rows = 0, rows_pad = 0, kp = 0;
+  double scale = 1.0;  // values stored as scale * x
+  int prec = FC_SPLIT_BF16;
+};
+
+// Split X[r * ldx + k] (r < rows, k < K), conjugated when conj.
+SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, bool conj = false);
+// C[m][n] = alpha sum_k A[a_row0 + m][k] B[b_row0 + n][k] + beta C[m][n]
+void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N, z alpha,
+                   z beta, z* C, long ldc);
+
+}  // namespace fc

@@ -1,0 +1,37 @@
+"""Frozen natural spinors on the GPU (Eq. 24-28) vs the FP64 oracle."""
+import numpy as np
+import pytest
+
+from paper_2506_06805_amd import synth
+from oracle import ccsd, eom, fns, integrals
+
+pytestmark = pytest.mark.gpu
+
+
+def _solve_oracle(L, eps, o, k):
+    e, t1, t2, _, conv = ccsd.solve(L, eps, o)
+    assert conv
+    w, _ = eom.dense_roots(eom.Hbar(integrals.Blocks(L, o), eps, t1, t2), k)
+    return e, w
+
+
+@pytest.mark.parametrize("thresh,gamma", [(0.0, None), (1e-5, 6.0), (1e-4, 6.0)])
+def test_fns_parity(gpu_ctx, thresh, gamma):
+    from paper_2506_06805_amd import fnscc
+    o, v, N, k = 5, 36, 50, 4
+    inst = synth.make_instance(o, v, N, seed=41, kappa=synth.kappa_for(v, N), fns_gamma=gamma)
+    L2, eps2, vp, occ_ref, _ = fns.truncate(inst.L, inst.eps, o, thresh)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    ints2, occ = fnscc.fns_truncate(gpu_ctx, ints, thresh)
+    assert ints2.v == vp
+    assert np.abs(occ - occ_ref).max() < 1e-12 * max(1.0, occ_ref.max())
+    if thresh > 0:
+        assert vp < v
+    e, _, amps = fnscc.ccsd_solve(gpu_ctx, ints2)
+    w, _ = fnscc.ipeom_davidson(gpu_ctx, ints2, amps, k)
+    e_ref, w_ref = _solve_oracle(L2, eps2, o, k)
+    assert abs(e - e_ref) < 1e-8
+    assert np.abs(w - w_ref).max() < 1e-8
+    if thresh == 0.0:
+        e_can, w_can = _solve_oracle(inst.L, inst.eps, o, k)
+        assert abs(e - e_can) < 1e-8 and np.abs(w - w_can).max() < 1e-8

@@ -1,0 +1,78 @@
+"""Split-precision ladder and Cholesky assembly (hi/lo BF16 or FP16 on MFMA, FP32 accumulation).
+
+Bounds: a split operand keeps ~16 (BF16) or ~22 (FP16) significant bits and each product drops only
+lo*lo, so one ladder evaluation carries a relative error of order 1e-5 (BF16) or 1e-7 (FP16) of its
+largest entry; the converged IPs must stay within 1e-5 Eh of the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_06805_amd import synth
+from oracle import ccsd, eom, integrals
+
+pytestmark = pytest.mark.gpu
+
+LADDER_TOL = {"split-bf16": 2e-4, "split-fp16": 2e-6}
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _tau(o, v, seed):
+    rng = np.random.default_rng(seed)
+    t = (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v))) * 0.05
+    t = t - t.transpose(1, 0, 2, 3)
+    return t - t.transpose(0, 1, 3, 2)
+
+
+@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
+@pytest.mark.parametrize("o,v,N", [(4, 10, 20), (9, 70, 45), (5, 131, 40)])
+def test_split_ladder_error_bound(gpu_ctx, prec, o, v, N):
+    from paper_2506_06805_amd import fnscc
+    inst = synth.make_instance(o, v, N, seed=51 + v, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    tau = _tau(o, v, 3)
+    R64 = fnscc.ladder(gpu_ctx, ints, _dev(tau), precision="fp64").cpu().numpy()
+    Rs = fnscc.ladder(gpu_ctx, ints, _dev(tau), precision=prec).cpu().numpy()
+    V = slice(o, o + v)
+    ref = 0.5 * np.einsum("ijef,abef->ijab", tau, integrals.antisym(inst.L, V, V, V, V), optimize=True)
+    scale = np.abs(ref).max()
+    assert np.abs(R64 - ref).max() < 1e-12 * scale
+    err = np.abs(Rs - ref).max() / scale
+    assert err < LADDER_TOL[prec], err
+    assert err > 1e-15        # the split path really ran
+
+
+@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
+def test_split_assembly_integrals(gpu_ctx, prec):
+    """Stored integrals assembled in split precision reproduce the FP64 residual at random T."""
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 6, 40, 60
+    inst = synth.make_instance(o, v, N, seed=61, kappa=0.5)
+    i64 = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision="fp64")
+    isp = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision=prec)
+    rng = np.random.default_rng(2)
+    t1 = _dev((rng.standard_normal((o, v)) + 0j) * 0.01)
+    t2 = _dev(_tau(o, v, 4) * 0.2)
+    a1, a2 = fnscc.ccsd_residual(gpu_ctx, i64, t1, t2)
+    b1, b2 = fnscc.ccsd_residual(gpu_ctx, isp, t1, t2)
+    s = max(a1.abs().max().item(), a2.abs().max().item())
+    err = max((a1 - b1).abs().max().item(), (a2 - b2).abs().max().item()) / s
+    assert 0 < err < LADDER_TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
+def test_mixed_solve_ip_error(gpu_ctx, prec):
+    from paper_2506_06805_amd import fnscc
+    o, v, N, k = 8, 32, 120, 4
+    inst = synth.make_instance(o, v, N, seed=1000, kappa=synth.kappa_for(v, N))
+    e_ref, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, o)
+    assert conv
+    w_ref, _ = eom.dense_roots(eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2), k)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision=prec)
+    e, _, amps = fnscc.ccsd_solve(gpu_ctx, ints, precision=prec)
+    w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, k)
+    assert np.abs(w - w_ref).max() < 1e-5
+    assert abs(e - e_ref) < 1e-4
