@@ -24,6 +24,7 @@ SOURCES = [
     "fc_tensor.hip",
     "fc_integrals.hip",
     "fc_ccsd.hip",
+    "fc_ladder.hip",
     "fc_eom.hip",
     "fc_mlp.hip",
     "fc_api.hip",

@@ -12,7 +12,6 @@
 #include <algorithm>
 #include <cmath>
 
-#include "fc_split.hpp"
 #include "fc_state.hpp"
 
 namespace fc {
@@ -82,136 +81,7 @@ __global__ void k_antisym_oooo(z* W, const z* X, long o) {
   }
 }
 
-// ---- ladder helpers
-// taup[pij][pef] = tau[i,j,e,f] for i<j, e<f
-__global__ void k_pack_tau(const z* __restrict__ tau, z* __restrict__ taup, long o, long v, const int2* po,
-                           const int2* pv, long no, long nv) {
-  GRID_STRIDE(t, no * nv) {
-    long pe = t % nv, pi = t / nv;
-    int2 ij = po[pi], ef = pv[pe];
-    taup[t] = tau[((ij.x * o + ij.y) * v + ef.x) * v + ef.y];
-  }
-}
-// Wp[pef][(a-a0)*nB + (b-b0)] = W[(a,e),(b,f)] - W[(a,f),(b,e)],  W row-major (nA*v) x (nB*v)
-__global__ void k_ladder_anti(const z* __restrict__ W, z* __restrict__ Wp, long v, long nA, long nB,
-                              const int2* pv, long nv) {
-  const long nab = nA * nB, ldw = nB * v;
-  GRID_STRIDE(t, nv * nab) {
-    long ab = t % nab, pe = t / nab;
-    long a = ab / nB, b = ab % nB;
-    int2 ef = pv[pe];
-    z x = W[(a * v + ef.x) * ldw + b * v + ef.y];
-    z y = W[(a * v + ef.y) * ldw + b * v + ef.x];
-    Wp[t] = make_double2(x.x - y.x, x.y - y.y);
-  }
-}
-// transposed layout for the split-precision contraction: WpT[(a-a0)*nB + (b-b0)][pef]
-__global__ void k_ladder_anti_t(const z* __restrict__ W, z* __restrict__ WpT, long v, long nA, long nB,
-                                const int2* pv, long nv) {
-  const long nab = nA * nB, ldw = nB * v;
-  GRID_STRIDE(t, nv * nab) {
-    long pe = t % nv, ab = t / nv;
-    long a = ab / nB, b = ab % nB;
-    int2 ef = pv[pe];
-    z x = W[(a * v + ef.x) * ldw + b * v + ef.y];
-    z y = W[(a * v + ef.y) * ldw + b * v + ef.x];
-    WpT[t] = make_double2(x.x - y.x, x.y - y.y);
-  }
-}
-// R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][(a-a0)*nB + (b-b0)]
-__global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, long a0, long nA,
-                                 long b0, long nB, const int2* po, long no, int diag) {
-  const long nab = nA * nB;
-  GRID_STRIDE(t, no * nab) {
-    long ab = t % nab, pi = t / nab;
-    long a = a0 + ab / nB, b = b0 + ab % nB;
-    if (diag && a >= b) continue;
-    int2 ij = po[pi];
-    z r = Rp[t], m = make_double2(-r.x, -r.y);
-    long i = ij.x, j = ij.y;
-    R[((i * o + j) * v + a) * v + b] = r;
-    R[((j * o + i) * v + a) * v + b] = m;
-    R[((i * o + j) * v + b) * v + a] = m;
-    R[((j * o + i) * v + b) * v + a] = r;
-  }
-}
 }  // namespace
-
-static DBuf pair_table(fc_ctx ctx, long n, long& np) {
-  std::vector<int2> h;
-  for (long i = 0; i < n; ++i)
-    for (long j = i + 1; j < n; ++j) h.push_back(make_int2((int)i, (int)j));
-  np = (long)h.size();
-  DBuf d(ctx, sizeof(int2) * std::max(1L, np));
-  if (np) FC_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(int2) * np, hipMemcpyHostToDevice, ctx->stream));
-  FC_HIP(hipStreamSynchronize(ctx->stream));
-  return d;
-}
-
-// R = sum_ef tau_ij^ef sum_P Lb^P_ae Lb^P_bf  (overwrites R)
-void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision) {
-  StageTimer st(ctx, "ladder");
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  if (ctx->timing & 2) {
-    FC_HIP(hipEventCreate(&ev0)); FC_HIP(hipEventCreate(&ev1));
-    FC_HIP(hipEventRecord(ev0, ctx->stream));
-  }
-  const long o = I->o, v = I->v, N = I->ncd;
-  const z one = make_double2(1, 0), zero = make_double2(0, 0);
-  // dressed Cholesky vectors
-  ZTensor Lb(ctx, {v, v, N});
-  FC_HIP(hipMemcpyAsync(Lb.p(), I->Lvv.p(), sizeof(z) * Lb.size(), hipMemcpyDeviceToDevice, ctx->stream));
-  if (t1dress) zein(ctx, "ma,meP->aeP", make_double2(-1, 0), ZT((z*)t1dress, {o, v}), I->Lov, one, Lb);
-  long no, nv;
-  DBuf po = pair_table(ctx, o, no), pv = pair_table(ctx, v, nv);
-  fill(ctx, R, o * o * v * v, zero);
-  if (no == 0 || nv == 0) {
-    if (ev0) { FC_HIP(hipEventRecord(ev1, ctx->stream)); ctx->ladder_events.emplace_back(ev0, ev1); }
-    return;
-  }
-  DBuf taup(ctx, sizeof(z) * no * nv);
-  hipLaunchKernelGGL(k_pack_tau, dim3(nblk(no * nv)), dim3(TPB), 0, ctx->stream, tau, taup.as<z>(), o, v,
-                     po.as<int2>(), pv.as<int2>(), no, nv);
-  // ab tile: W of nA*v x nB*v complex entries kept within a fixed budget
-  const double budget = 768.0 * 1024 * 1024;
-  long T = (long)std::floor(std::sqrt(budget / (16.0 * (double)v * (double)v)));
-  T = std::max(1L, std::min(T, v));
-  DBuf W(ctx, sizeof(z) * T * v * T * v), Wp(ctx, sizeof(z) * nv * T * T), Rp(ctx, sizeof(z) * no * T * T);
-  const bool split = precision != FC_FP64;
-  SplitOp Ls, Ts;
-  if (split) {  // hi/lo planes of the dressed vectors and of tau, once per evaluation
-    Ls = split_operand(ctx, precision, Lb.p(), v * v, N, N);
-    Ts = split_operand(ctx, precision, taup.as<z>(), no, nv, nv);
-  }
-  for (long a0 = 0; a0 < v; a0 += T) {
-    const long nA = std::min(T, v - a0);
-    for (long b0 = a0; b0 < v; b0 += T) {
-      const long nB = std::min(T, v - b0);
-      // W[(a,e),(b,f)] = sum_P Lb[a,e,P] Lb[b,f,P];  Rp[pij][ab] = sum_pef taup[pij][pef] Wp[pef][ab]
-      if (!split) {
-        zgemm(ctx, 'N', 'T', nA * v, nB * v, N, one, Lb.p() + a0 * v * N, N, Lb.p() + b0 * v * N, N, zero,
-              W.as<z>(), nB * v);
-        hipLaunchKernelGGL(k_ladder_anti, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
-                           Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
-        zgemm(ctx, 'N', 'N', no, nA * nB, nv, one, taup.as<z>(), nv, Wp.as<z>(), nA * nB, zero, Rp.as<z>(),
-              nA * nB);
-      } else {
-        gemm_split_nt(ctx, Ls, a0 * v, nA * v, Ls, b0 * v, nB * v, one, zero, W.as<z>(), nB * v);
-        hipLaunchKernelGGL(k_ladder_anti_t, dim3(nblk(nv * nA * nB)), dim3(TPB), 0, ctx->stream, W.as<z>(),
-                           Wp.as<z>(), v, nA, nB, pv.as<int2>(), nv);
-        SplitOp Ws = split_operand(ctx, precision, Wp.as<z>(), nA * nB, nv, nv);
-        gemm_split_nt(ctx, Ts, 0, no, Ws, 0, nA * nB, one, zero, Rp.as<z>(), nA * nB);
-      }
-      hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nA * nB)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R,
-                         o, v, a0, nA, b0, nB, po.as<int2>(), no, (int)(a0 == b0));
-      FC_HIP(hipGetLastError());
-    }
-  }
-  if (ev0) {
-    FC_HIP(hipEventRecord(ev1, ctx->stream));
-    ctx->ladder_events.emplace_back(ev0, ev1);
-  }
-}
 
 z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
   const long o = I->o, v = I->v;

@@ -1,0 +1,288 @@
+// Particle-particle ladder R_ij^ab = sum_ef tau_ij^ef sum_P Lb^P_ae Lb^P_bf (Eq. 21, 23), with the
+// four-virtual integrals rebuilt from the Cholesky vectors on every call and never stored whole.
+//
+// The unique outputs (i<j, a<b) are produced in chunks of (a,b) pairs:
+//  1. assembly: for a block pair (A, B), W[(a,e),(b,f)] = sum_P Lb[a,e,P] Lb[b,f,P] is one GEMM
+//     with K = N_CD whose epilogue writes W in [(a,b)][e][f] order (diagonal block pairs skip the
+//     output tiles with every a > every b);
+//  2. antisymmetrisation: Wp[ab][e<f] = W[ab][e][f] - W[ab][f][e], LDS-tiled so both the tile
+//     and its transpose are read coalesced (split precision: written directly as hi/lo planes);
+//  3. contraction: Rp[i<j][ab] = sum_{e<f} tau_ij^ef Wp[ab][ef], one GEMM per chunk with
+//     K = v(v-1)/2;
+//  4. scatter of Rp into R and its three antisymmetric images.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fc_split.hpp"
+#include "fc_state.hpp"
+
+namespace fc {
+namespace {
+constexpr int TPB = 256;
+inline unsigned nblk(long n) { return (unsigned)std::max(1L, std::min(1048576L, (n + TPB * 4 - 1) / (TPB * 4))); }
+#define GRID_STRIDE(i, n) for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
+typedef unsigned short u16;
+
+// taup[pij][pef] = tau[i,j,e,f] for i<j, e<f
+__global__ void k_pack_tau(const z* __restrict__ tau, z* __restrict__ taup, long o, long v, const int2* po,
+                           const int2* pv, long no, long nv) {
+  GRID_STRIDE(t, no * nv) {
+    long pe = t % nv, pi = t / nv;
+    int2 ij = po[pi], ef = pv[pe];
+    taup[t] = tau[((ij.x * o + ij.y) * v + ef.x) * v + ef.y];
+  }
+}
+
+__device__ inline long pair_index(long e, long f, long v) { return e * (2 * v - e - 1) / 2 + (f - e - 1); }
+
+// Wp[s][pef] = W[s][e][f] - W[s][f][e] for valid slots (a < b); one 32 x 32 block pair (E <= F) per
+// workgroup, both tiles staged in LDS.  T: double2 (FP64 path) or float2 (split path).
+template <class T>
+struct AntiOut;
+template <>
+struct AntiOut<double2> {
+  z* Wp;
+  long nv;
+  __device__ void put(long s, long pe, double re, double im) const { Wp[s * nv + pe] = make_double2(re, im); }
+};
+template <int PREC>
+__device__ inline u16 to16(float x) {
+  if constexpr (PREC == FC_SPLIT_BF16) return __builtin_bit_cast(u16, (__bf16)x);
+  else return __builtin_bit_cast(u16, (_Float16)x);
+}
+template <int PREC>
+__device__ inline double from16(u16 x) {
+  if constexpr (PREC == FC_SPLIT_BF16) return (double)(float)__builtin_bit_cast(__bf16, x);
+  else return (double)(float)__builtin_bit_cast(_Float16, x);
+}
+template <int PREC>
+struct SplitOut {
+  u16* planes;
+  long plane, kp;
+  double scale;
+  __device__ void put(long s, long pe, double re, double im) const {
+    re *= scale; im *= scale;
+    const u16 rh = to16<PREC>((float)re), ih = to16<PREC>((float)im);
+    const long off = s * kp + pe;
+    planes[off] = rh;
+    planes[plane + off] = to16<PREC>((float)(re - from16<PREC>(rh)));
+    planes[2 * plane + off] = ih;
+    planes[3 * plane + off] = to16<PREC>((float)(im - from16<PREC>(ih)));
+  }
+};
+
+template <class T, class Out>
+__global__ __launch_bounds__(256) void k_ladder_anti(const T* __restrict__ W, const int2* __restrict__ slots, long v,
+                                                    long nbv, Out out) {
+  __shared__ T X[32][33], Y[32][33];
+  const long s = blockIdx.y;
+  const int2 ab = slots[s];
+  if (ab.x >= ab.y) return;   // slot not needed (its Wp row is zero)
+  // block pair (E, F), E <= F, from the linear id
+  long q = blockIdx.x, E = 0;
+  while (q >= nbv - E) { q -= nbv - E; ++E; }
+  const long F = E + q;
+  const T* Ws = W + s * v * v;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    long e = E * 32 + r, f = F * 32 + tx;
+    X[r][tx] = (e < v && f < v) ? Ws[e * v + f] : T{};
+    long e2 = F * 32 + r, f2 = E * 32 + tx;
+    Y[r][tx] = (e2 < v && f2 < v) ? Ws[e2 * v + f2] : T{};
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    long e = E * 32 + r, f = F * 32 + tx;
+    if (e < f && f < v) {
+      T x = X[r][tx], y = Y[tx][r];
+      out.put(s, pair_index(e, f, v), (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+    }
+  }
+}
+
+__global__ void k_maxabs_slots(const float2* __restrict__ W, const int2* __restrict__ slots, long nslots, long vv,
+                               unsigned* out) {
+  __shared__ float sm[TPB];
+  float m = 0.f;
+  GRID_STRIDE(t, nslots * vv) {
+    const int2 ab = slots[t / vv];
+    if (ab.x < ab.y) m = fmaxf(m, fmaxf(fabsf(W[t].x), fabsf(W[t].y)));
+  }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = TPB / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  // the maximum of non-negative floats equals the maximum of their bit patterns
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(sm[0]));
+}
+
+// R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][slot]
+__global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, const int2* slots,
+                                 long nslots, const int2* po, long no) {
+  GRID_STRIDE(t, no * nslots) {
+    const long s = t % nslots, pi = t / nslots;
+    const int2 ab = slots[s];
+    if (ab.x >= ab.y) continue;
+    const int2 ij = po[pi];
+    const z r = Rp[t], m = make_double2(-r.x, -r.y);
+    const long i = ij.x, j = ij.y, a = ab.x, b = ab.y;
+    R[((i * o + j) * v + a) * v + b] = r;
+    R[((j * o + i) * v + a) * v + b] = m;
+    R[((i * o + j) * v + b) * v + a] = m;
+    R[((j * o + i) * v + b) * v + a] = r;
+  }
+}
+}  // namespace
+
+static DBuf pair_table(fc_ctx ctx, long n, long& np) {
+  std::vector<int2> h;
+  for (long i = 0; i < n; ++i)
+    for (long j = i + 1; j < n; ++j) h.push_back(make_int2((int)i, (int)j));
+  np = (long)h.size();
+  DBuf d(ctx, sizeof(int2) * std::max(1L, np));
+  if (np) FC_HIP(hipMemcpyAsync(d.p, h.data(), sizeof(int2) * np, hipMemcpyHostToDevice, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  return d;
+}
+
+// Memory for one chunk of the assembled W (bytes); the chunk covers as many (a,b) pairs as fit.
+static double ladder_budget_bytes() {
+  const char* s = getenv("FNSCC_LADDER_BUDGET_GB");
+  return (s ? atof(s) : 8.0) * 1e9;
+}
+
+void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision) {
+  StageTimer st(ctx, "ladder");
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (ctx->timing & 2) {
+    FC_HIP(hipEventCreate(&ev0));
+    FC_HIP(hipEventCreate(&ev1));
+    FC_HIP(hipEventRecord(ev0, ctx->stream));
+  }
+  const long o = I->o, v = I->v, N = I->ncd;
+  const z one = make_double2(1, 0), zero = make_double2(0, 0);
+  const bool split = precision != FC_FP64;
+  // dressed Cholesky vectors Lb^P_ae = L^P_ae - sum_m t_m^a L^P_me
+  ZTensor Lb(ctx, {v, v, N});
+  FC_HIP(hipMemcpyAsync(Lb.p(), I->Lvv.p(), sizeof(z) * Lb.size(), hipMemcpyDeviceToDevice, ctx->stream));
+  if (t1dress) zein(ctx, "ma,meP->aeP", make_double2(-1, 0), ZT((z*)t1dress, {o, v}), I->Lov, one, Lb);
+  long no, nv;
+  DBuf po = pair_table(ctx, o, no), pv = pair_table(ctx, v, nv);
+  fill(ctx, R, o * o * v * v, zero);
+  if (no > 0 && nv > 0) {
+    DBuf taup(ctx, sizeof(z) * no * nv);
+    hipLaunchKernelGGL(k_pack_tau, dim3(nblk(no * nv)), dim3(TPB), 0, ctx->stream, tau, taup.as<z>(), o, v,
+                       po.as<int2>(), pv.as<int2>(), no, nv);
+    // block size T (pairs per block pair T^2) and chunk capacity in (a,b) slots
+    const double esz = split ? 8.0 : 16.0;
+    const long cap_slots = std::max(1L, (long)(ladder_budget_bytes() / (esz * (double)v * (double)v)));
+    long T = std::max(1L, std::min({v, 64L, (long)std::floor(std::sqrt((double)cap_slots))}));
+    struct BP { long a0, nA, b0, nB; };
+    std::vector<BP> bps;
+    for (long a0 = 0; a0 < v; a0 += T)
+      for (long b0 = a0; b0 < v; b0 += T) bps.push_back({a0, std::min(T, v - a0), b0, std::min(T, v - b0)});
+    long max_slots = 0;
+    {  // size the chunk buffers for the largest chunk
+      long cur = 0;
+      for (auto& bp : bps) {
+        if (cur > 0 && cur + bp.nA * bp.nB > cap_slots) { max_slots = std::max(max_slots, cur); cur = 0; }
+        cur += bp.nA * bp.nB;
+      }
+      max_slots = std::max(max_slots, cur);
+    }
+    DBuf Wbuf(ctx, (size_t)esz * max_slots * v * v);
+    DBuf Rp(ctx, sizeof(z) * no * max_slots);
+    DBuf slots_d(ctx, sizeof(int2) * max_slots);
+    const long nbv = (v + 31) / 32, ntri = nbv * (nbv + 1) / 2;
+    SplitOp Ls, Ts, Wps;
+    DBuf Wp64;
+    if (split) {
+      Ls = split_operand(ctx, precision, Lb.p(), v * v, N, N);
+      Ts = split_operand(ctx, precision, taup.as<z>(), no, nv, nv);
+      Wps.prec = precision;
+      Wps.kp = Ts.kp;
+      Wps.rows_pad = (max_slots + 127) / 128 * 128 + 128;
+      Wps.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp);
+    } else {
+      Wp64 = DBuf(ctx, sizeof(z) * (size_t)max_slots * nv);
+    }
+    DBuf mx(ctx, sizeof(unsigned));
+    size_t next = 0;
+    while (next < bps.size()) {
+      // gather a chunk of block pairs and run their assembly GEMMs
+      std::vector<int2> hslots;
+      size_t first = next;
+      while (next < bps.size() && (hslots.empty() || (long)hslots.size() + bps[next].nA * bps[next].nB <= cap_slots)) {
+        const BP& bp = bps[next];
+        LadderEpilogue lep;
+        lep.v = v; lep.nB = bp.nB; lep.triangular = (bp.a0 == bp.b0);
+        const long base = (long)hslots.size();
+        if (!split)
+          zgemm_ladder(ctx, bp.nA * v, bp.nB * v, N, Lb.p() + bp.a0 * v * N, N, Lb.p() + bp.b0 * v * N, N,
+                       Wbuf.as<z>() + base * v * v, lep);
+        else
+          gemm_split_ladder(ctx, Ls, bp.a0 * v, bp.nA * v, Ls, bp.b0 * v, bp.nB * v,
+                            Wbuf.as<float2>() + base * v * v, lep);
+        for (long ia = 0; ia < bp.nA; ++ia)
+          for (long ib = 0; ib < bp.nB; ++ib) hslots.push_back(make_int2((int)(bp.a0 + ia), (int)(bp.b0 + ib)));
+        ++next;
+      }
+      (void)first;
+      const long ns = (long)hslots.size();
+      FC_HIP(hipMemcpyAsync(slots_d.p, hslots.data(), sizeof(int2) * ns, hipMemcpyHostToDevice, ctx->stream));
+      dim3 agrid((unsigned)ntri, (unsigned)ns);
+      FC_REQUIRE(ns <= 65535, FC_EARG, "ladder: chunk has too many (a,b) slots");
+      if (!split) {
+        FC_HIP(hipMemsetAsync(Wp64.p, 0, sizeof(z) * (size_t)ns * nv, ctx->stream));
+        AntiOut<double2> out{Wp64.as<z>(), nv};
+        k_ladder_anti<double2, AntiOut<double2>><<<agrid, 256, 0, ctx->stream>>>(Wbuf.as<double2>(),
+                                                                                 slots_d.as<int2>(), v, nbv, out);
+        FC_HIP(hipGetLastError());
+        zgemm(ctx, 'N', 'T', no, ns, nv, one, taup.as<z>(), nv, Wp64.as<z>(), nv, zero, Rp.as<z>(), ns);
+      } else {
+        Wps.scale = 1.0;
+        if (precision == FC_SPLIT_FP16) {
+          FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned), ctx->stream));
+          k_maxabs_slots<<<nblk(ns * v * v), TPB, 0, ctx->stream>>>(Wbuf.as<float2>(), slots_d.as<int2>(), ns, v * v,
+                                                                    mx.as<unsigned>());
+          FC_HIP(hipGetLastError());
+          unsigned hb = 0;
+          FC_HIP(hipMemcpyAsync(&hb, mx.p, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+          FC_HIP(hipStreamSynchronize(ctx->stream));
+          float m;
+          std::memcpy(&m, &hb, sizeof(m));
+          // differences are at most twice the largest entry; keep them below 2^14
+          if (m > 0) Wps.scale = std::ldexp(1.0, 12 - std::ilogb((double)m));
+        }
+        Wps.rows = ns;
+        FC_HIP(hipMemsetAsync(Wps.buf.p, 0, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp, ctx->stream));
+        const long plane = Wps.rows_pad * Wps.kp;
+        if (precision == FC_SPLIT_BF16) {
+          SplitOut<FC_SPLIT_BF16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
+          k_ladder_anti<float2, SplitOut<FC_SPLIT_BF16>><<<agrid, 256, 0, ctx->stream>>>(
+              Wbuf.as<float2>(), slots_d.as<int2>(), v, nbv, out);
+        } else {
+          SplitOut<FC_SPLIT_FP16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
+          k_ladder_anti<float2, SplitOut<FC_SPLIT_FP16>><<<agrid, 256, 0, ctx->stream>>>(
+              Wbuf.as<float2>(), slots_d.as<int2>(), v, nbv, out);
+        }
+        FC_HIP(hipGetLastError());
+        gemm_split_nt(ctx, Ts, 0, no, Wps, 0, ns, one, zero, Rp.as<z>(), ns);
+      }
+      hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * ns)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R, o, v,
+                         slots_d.as<int2>(), ns, po.as<int2>(), no);
+      FC_HIP(hipGetLastError());
+      // the slot table is rewritten by the next chunk: keep host and device in order
+      FC_HIP(hipStreamSynchronize(ctx->stream));
+    }
+  }
+  if (ev0) {
+    FC_HIP(hipEventRecord(ev1, ctx->stream));
+    ctx->ladder_events.emplace_back(ev0, ev1);
+  }
+}
+
+}  // namespace fc

@@ -84,6 +84,12 @@ struct SArgs {
   double inv_scale;
   long kchunk;
   z* part;
+  long tiles;
+  // ladder epilogue (EPI = 1): FP32 complex output W[((m / v) nB + n / v) v^2 + (m % v) v + n % v],
+  // tiles with every a = m / v above every b = n / v skipped when ltri is set
+  float2* W;
+  long lv, lnB;
+  int ltri;
 };
 
 template <int PREC>
@@ -97,14 +103,22 @@ __device__ inline f4 mma(const u16* a, const u16* b, f4 c) {
   }
 }
 
-template <int PREC>
+template <int PREC, int EPI>
 __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   __shared__ __attribute__((aligned(16))) u16 sA[4][TM][LDK];
   __shared__ __attribute__((aligned(16))) u16 sB[4][TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
   const long ntn = (g.N + TN - 1) / TN;
-  const long m0 = (blockIdx.x / ntn) * TM, n0 = (blockIdx.x % ntn) * TN;
+  // XCD x (= blockIdx.x % 8) walks the contiguous tiles [x * per, (x + 1) * per)
+  const long per = (g.tiles + 7) / 8;
+  const long tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= g.tiles) return;
+  const long m0 = (tile / ntn) * TM, n0 = (tile % ntn) * TN;
+  if (EPI == 1 && g.ltri) {
+    const long amin = m0 / g.lv, bmax = (n0 + TN - 1 < g.N ? n0 + TN - 1 : g.N - 1) / g.lv;
+    if (amin > bmax) return;
+  }
   const long klo = (long)blockIdx.y * g.kchunk;
   const long khi = klo + g.kchunk < g.kp ? klo + g.kchunk : g.kp;
   const u16* A = g.A + (g.a_row0 + m0) * g.kp;
@@ -186,6 +200,11 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
         long m = m0 + wm + 16 * i + orow + r, n = n0 + wn + 16 * j + ocol;
         if (m >= g.M || n >= g.N) continue;
         double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * g.inv_scale, imv = (double)im[i][j][r] * g.inv_scale;
+        if (EPI == 1) {
+          const long a = m / g.lv, e = m % g.lv, b = n / g.lv, f = n % g.lv;
+          g.W[((a * g.lnB + b) * g.lv + e) * g.lv + f] = make_float2((float)re, (float)imv);
+          continue;
+        }
         if (g.part) {
           g.part[((long)blockIdx.y * g.M + m) * g.N + n] = make_double2(re, imv);
           continue;
@@ -268,6 +287,8 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
   g.C = C; g.ldc = ldc; g.alpha = alpha; g.beta = beta;
   g.inv_scale = 1.0 / (A.scale * B.scale);
   const long tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  g.tiles = tiles;
+  g.W = nullptr; g.lv = 1; g.lnB = 1; g.ltri = 0;
   long ksplit = 1;
   const long nks = A.kp / TK;
   if (tiles < 512 && nks >= 16) {
@@ -283,9 +304,9 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
     work = DBuf(ctx, sizeof(z) * (size_t)ksplit * M * N);
     g.part = work.as<z>();
   }
-  dim3 grid((unsigned)tiles, (unsigned)ksplit);
-  if (A.prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16><<<grid, NT, 0, ctx->stream>>>(g);
-  else k_gemm_split<FC_SPLIT_FP16><<<grid, NT, 0, ctx->stream>>>(g);
+  dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit);
+  if (A.prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, 0><<<grid, NT, 0, ctx->stream>>>(g);
+  else k_gemm_split<FC_SPLIT_FP16, 0><<<grid, NT, 0, ctx->stream>>>(g);
   FC_HIP(hipGetLastError());
   if (ksplit > 1) {
     const long MN = M * N;
@@ -293,6 +314,28 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
     k_split_reduce<<<nb, 256, 0, ctx->stream>>>(g.part, (int)ksplit, M, N, C, ldc, alpha, beta);
     FC_HIP(hipGetLastError());
   }
+}
+
+void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N,
+                       float2* W, const LadderEpilogue& lep) {
+  if (M <= 0 || N <= 0) return;
+  FC_REQUIRE(A.prec == B.prec && A.kp == B.kp, FC_EARG, "gemm_split_ladder: operand mismatch");
+  FC_REQUIRE(a_row0 >= 0 && b_row0 >= 0 && a_row0 + M <= A.rows && b_row0 + N <= B.rows, FC_EARG,
+             "gemm_split_ladder: row range outside operand");
+  SArgs g;
+  g.A = A.buf.as<u16>(); g.a_plane = A.rows_pad * A.kp; g.a_row0 = a_row0;
+  g.B = B.buf.as<u16>(); g.b_plane = B.rows_pad * B.kp; g.b_row0 = b_row0;
+  g.M = M; g.N = N; g.kp = A.kp;
+  g.C = nullptr; g.ldc = 0; g.alpha = make_double2(1, 0); g.beta = make_double2(0, 0);
+  g.inv_scale = 1.0 / (A.scale * B.scale);
+  g.tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  g.kchunk = A.kp;
+  g.part = nullptr;
+  g.W = W; g.lv = lep.v; g.lnB = lep.nB; g.ltri = lep.triangular;
+  dim3 grid((unsigned)((g.tiles + 7) / 8 * 8), 1);
+  if (A.prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, 1><<<grid, NT, 0, ctx->stream>>>(g);
+  else k_gemm_split<FC_SPLIT_FP16, 1><<<grid, NT, 0, ctx->stream>>>(g);
+  FC_HIP(hipGetLastError());
 }
 
 // Generic entry: only the layout with both operands contraction-contiguous (opA 'N'/'R', opB 'T'/'C').

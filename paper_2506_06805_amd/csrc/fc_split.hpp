@@ -1,5 +1,6 @@
 // Split-precision operands (hi/lo 16-bit planes) and the NT product on them.
 #pragma once
+#include "fc_gemm.hpp"
 #include "fc_internal.hpp"
 
 namespace fc {
@@ -16,5 +17,9 @@ SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long 
 // C[m][n] = alpha sum_k A[a_row0 + m][k] B[b_row0 + n][k] + beta C[m][n]
 void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N, z alpha,
                    z beta, z* C, long ldc);
+
+// Ladder assembly in split precision: FP32 complex W in the ladder layout (see LadderEpilogue).
+void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N,
+                       float2* W, const LadderEpilogue& lep);
 
 }  // namespace fc
