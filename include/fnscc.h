@@ -77,10 +77,18 @@ void fc_free_ints(fc_ints ints);
 int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v_kept, double* occ,
                  void* U);
 
+/* Learned T2 update network (4 -> 64 -> 64 -> 2, tanh). Not part of the paper's method: a
+ * per-amplitude gain g with t_ij^ab += (Omega_ij^ab / D_ij^ab)(1 + g), features built from the
+ * dressed diagonal u = (F_aa + F_bb - F_ii - F_jj) / D and the residual ratio
+ * rho = Omega_k / Omega_{k-1} of the amplitude; Omega = 0 gives a zero step. */
+typedef struct fc_mlp_s* fc_mlp;
+
 /* Options of ccsd_solve. Jacobi update t += Omega/D with complex DIIS (FP64). Converged when
- * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol. learned = 1 uses the learned
- * preconditioned T2 step (weights from fc_mlp_*), falling back to Jacobi+DIIS when the residual
- * stalls. t1_init/t2_init: device, full layout, or NULL for t = 0. */
+ * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol. learned = 1 with mlp != NULL uses
+ * the learned T2 step (DIIS on top) until the residual fails to decrease for stall_window
+ * iterations, then plain Jacobi + DIIS. t1_init/t2_init: device, full layout, or NULL for t = 0.
+ * on_iter (may be NULL): called with the current iterate (device pointers, valid during the call)
+ * before each residual evaluation; precision: FC_* or -1 to inherit from the integral handle. */
 typedef struct {
   double e_tol, r_tol;
   int max_iter, diis_dim, learned, precision;
@@ -88,6 +96,8 @@ typedef struct {
   const void* t2_init;
   const void* mlp;  /* fc_mlp handle or NULL */
   int stall_window; /* iterations without residual decrease before falling back (learned) */
+  void (*on_iter)(int iter, const void* t1, const void* t2, void* user);
+  void* user;
 } fc_ccsd_opts;
 void fc_ccsd_default_opts(fc_ccsd_opts* opts);
 
@@ -127,6 +137,29 @@ void fc_eom_default_opts(fc_eom_opts* opts);
  * R_out: device, sum(nroots) x dim_b right eigenvectors (or NULL). iters: host, nb ints. */
 int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
                    const fc_eom_opts* opts, double* omega, void* R_out, int* iters);
+
+/* Learned update network. Parameters: one FP32 vector W1 (64x4), b1, W2 (64x64), b2, W3 (2x64),
+ * b3 (fc_mlp_num_params() entries). fc_mlp_create: params_host (host) or NULL for a seeded
+ * initialisation. Training minimises sum_s |r_s - q_s g_s|^2 / sum_s |q_s|^2 over a minibatch of
+ * B samples: X (device, B x 4 FP32 features), q (device, B complex64: Jacobi step Omega/D),
+ * r (device, B complex64: (t* - t) - q); fc_mlp_train_step does one Adam step (lr > 0) on FP32
+ * master weights and refreshes the BF16 copy used by the solver; fc_mlp_grad returns the
+ * gradient (host, FP32) without updating; fc_mlp_forward evaluates Y (device, B x 2) with the FP32
+ * (bf16_weights = 0) or BF16-rounded weights. loss: host float or NULL. */
+int fc_mlp_create(fc_ctx ctx, const float* params_host, unsigned long long seed, fc_mlp* out);
+void fc_mlp_free(fc_mlp mlp);
+long fc_mlp_num_params(void);
+int fc_mlp_get_params(fc_mlp mlp, float* host, int bf16_rounded);
+int fc_mlp_grad(fc_mlp mlp, const float* X, const float* q, const float* r, long B, float* grad_host, float* loss);
+int fc_mlp_train_step(fc_mlp mlp, const float* X, const float* q, const float* r, long B, float lr, float* loss);
+int fc_mlp_forward(fc_mlp mlp, const float* X, long B, float* Y, int bf16_weights);
+/* Training samples at the iterate (t1, t2) (device, full layout) of a solve whose converged
+ * doubles are t2_star, the previous iterate (t1prev, t2prev) giving the residual ratio (NULL: 0):
+ * nsamp unique amplitudes (i<j, a<b) drawn by a counter-based hash of seed; writes X (B x 4),
+ * q (B complex64) and r (B complex64) as defined above (device). */
+int fc_learn_samples(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, const void* t1prev,
+                     const void* t2prev, const void* t2_star, long nsamp, unsigned long long seed, float* X,
+                     float* q, float* r);
 
 /* Host FP64 dense eigensolvers used by the library (exported for testing; no GPU needed).
  * fc_host_zheev: Hermitian A (n x n complex128, row-major, host) -> ascending eigenvalues w and

@@ -13,8 +13,6 @@ namespace fc {
 void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype);
 void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2);
 int davidson_one(fc_ctx ctx, fc_ints I, fc_amps T, int k, const fc_eom_opts& op, z* omega, z* Rout, int* iters);
-int learned_step(fc_ctx ctx, fc_ints I, const void* mlp, const z* t1, const z* t2, const z* r1, const z* r2,
-                 z* o1, z* o2);
 
 namespace {
 constexpr int TPB = 256;
@@ -107,20 +105,56 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
   const double nuniq = (double)n1 + (double)(o * (o - 1) / 2) * (double)(v * (v - 1) / 2);
   int status = FC_ENOCONV, it;
   z e = e_old;
+  // learned step: used until the residual stops decreasing for stall_window iterations, then
+  // plain Jacobi (DIIS history restarted, since the iteration map changes)
   bool learned = op.learned && op.mlp;
+  DBuf fd(ctx, sizeof(z) * (o + v));
+  ZTensor tgood, rprev;
+  bool have_good = false, have_prev = false;
+  if (learned) { tgood = ZTensor(ctx, {nt}); rprev = ZTensor(ctx, {n2}); }
   double best_rms = INFINITY;
   int since_best = 0;
   for (it = 1; it <= op.max_iter; ++it) {
-    ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec);
+    if (op.on_iter) {
+      FC_HIP(hipStreamSynchronize(ctx->stream));
+      op.on_iter(it, t.p(), t.p() + n1, op.user);
+    }
+    ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec, learned ? fd.as<z>() : nullptr);
     z a = dotc(ctx, n1, r.p(), r.p()), b = dotc(ctx, n2, r.p() + n1, r.p() + n1);
-    const double rms = std::sqrt(std::max(0.0, (a.x + 0.25 * b.x) / std::max(1.0, nuniq)));
+    double rms = std::sqrt(std::max(0.0, (a.x + 0.25 * b.x) / std::max(1.0, nuniq)));
+    if (!std::isfinite(a.x + b.x) && learned && have_good) {
+      // the learned step produced a non-finite iterate: return to the last good one, go plain
+      FC_HIP(hipMemcpyAsync(t.p(), tgood.p(), sizeof(z) * nt, hipMemcpyDeviceToDevice, ctx->stream));
+      learned = false;
+      D.order.clear();
+      if (ctx->verbose) fprintf(stderr, "[ccsd] it %3d learned step not finite: back to the last good iterate\n", it);
+      ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec, nullptr);
+      a = dotc(ctx, n1, r.p(), r.p());
+      b = dotc(ctx, n2, r.p() + n1, r.p() + n1);
+      rms = std::sqrt(std::max(0.0, (a.x + 0.25 * b.x) / std::max(1.0, nuniq)));
+    }
     if (!std::isfinite(rms)) throw Error(FC_ENUMERIC, "ccsd_solve: residual is not finite");
     if (learned) {
-      if (rms < best_rms * 0.999) { best_rms = rms; since_best = 0; } else if (++since_best >= op.stall_window) learned = false;
+      FC_HIP(hipMemcpyAsync(tgood.p(), t.p(), sizeof(z) * nt, hipMemcpyDeviceToDevice, ctx->stream));
+      have_good = true;
+      if (rms < best_rms * 0.999) {
+        best_rms = rms;
+        since_best = 0;
+      } else if (++since_best >= std::max(1, op.stall_window)) {
+        learned = false;
+        D.order.clear();
+        if (ctx->verbose) fprintf(stderr, "[ccsd] it %3d learned step stalled: Jacobi + DIIS from here\n", it);
+      }
     }
-    if (learned) learned_step(ctx, I, op.mlp, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
-    else jacobi_step(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
-    if (op.diis_dim > 1 && !learned) {
+    if (learned) {
+      learned_step(ctx, I, op.mlp, t.p(), t.p() + n1, r.p(), r.p() + n1, have_prev ? rprev.p() : nullptr, fd.as<z>(),
+                   tn.p(), tn.p() + n1);
+      FC_HIP(hipMemcpyAsync(rprev.p(), r.p() + n1, sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
+      have_prev = true;
+    } else {
+      jacobi_step(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
+    }
+    if (op.diis_dim > 1) {
       diis_push_extrapolate(ctx, D, tn.p(), t.p(), tx.p());
       std::swap(t, tx);
     } else {
@@ -395,6 +429,25 @@ int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, i
   if (!ctx || !I || !tau || !R) return FC_EARG;
   FC_TRY(ctx, {
     ladder_dev(ctx, I, (const z*)tau, (const z*)t1, (z*)R, precision < 0 ? I->precision : precision);
+    return FC_OK;
+  })
+}
+
+int fc_learn_samples(fc_ctx ctx, fc_ints I, const void* t1, const void* t2, const void* t1prev, const void* t2prev,
+                     const void* t2_star, long nsamp, unsigned long long seed, float* X, float* q, float* r) {
+  if (!ctx || !I || !t1 || !t2 || !t2_star || nsamp < 1 || !X || !q || !r) return FC_EARG;
+  FC_TRY(ctx, {
+    const long o = I->o, v = I->v;
+    ZTensor r1(ctx, {o, v}), r2(ctx, {o, o, v, v}), p2;
+    DBuf fd(ctx, sizeof(z) * (o + v));
+    if (t1prev && t2prev) {
+      p2 = ZTensor(ctx, {o, o, v, v});
+      ccsd_residual_dev(ctx, I, (const z*)t1prev, (const z*)t2prev, r1.p(), p2.p(), I->precision, nullptr);
+    }
+    ccsd_residual_dev(ctx, I, (const z*)t1, (const z*)t2, r1.p(), r2.p(), I->precision, fd.as<z>());
+    learn_samples(ctx, I, (const z*)t2, r2.p(), p2.size() ? p2.p() : nullptr, (const z*)t2_star, fd.as<z>(), nsamp,
+                  seed, X, q, r);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
     return FC_OK;
   })
 }

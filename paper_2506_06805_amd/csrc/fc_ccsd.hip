@@ -73,6 +73,10 @@ __global__ void k_jacobi2(const z* t, const z* r, z* out, const double* eps, lon
   }
 }
 // X[m,n,i,j] -> X - X^(i<->j) added into W (o^4)
+// out[k] = F[k * n + k]
+__global__ void k_diag_copy(const z* F, long n, z* out) {
+  GRID_STRIDE(k, n) { out[k] = F[k * n + k]; }
+}
 __global__ void k_antisym_oooo(z* W, const z* X, long o) {
   GRID_STRIDE(t, o * o * o * o) {
     long j = t % o, i = (t / o) % o, mn = t / (o * o);
@@ -91,7 +95,7 @@ z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
   return make_double2(0.25 * e.x, 0.25 * e.y);
 }
 
-void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p, z* r2p, int precision) {
+void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p, z* r2p, int precision, z* fdiag) {
   StageTimer st(ctx, "residual");
   const long o = I->o, v = I->v, N = I->ncd;
   const z one = make_double2(1, 0), zero = make_double2(0, 0), half = make_double2(0.5, 0),
@@ -164,6 +168,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     zein(ctx, "mb,me->be", mhalf, T1, Fme, one, Fp);
     zein(ctx, "ijae,be->ijab", one, T2, Fp, zero, x);
     antisym_add(ctx, r2p, x.p(), o, v, 1, one);
+    if (fdiag) hipLaunchKernelGGL(k_diag_copy, dim3(1), dim3(TPB), 0, ctx->stream, Fp.p(), v, fdiag + o);
   }
   {  // -P(ij) sum_m t_im^ab (F_mj + 1/2 sum_e t_j^e F_me)
     ZTensor Fp(ctx, {o, o});
@@ -171,6 +176,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     zein(ctx, "je,me->mj", half, T1, Fme, one, Fp);
     zein(ctx, "imab,mj->ijab", one, T2, Fp, zero, x);
     antisym_add(ctx, r2p, x.p(), o, v, 2, mone);
+    if (fdiag) hipLaunchKernelGGL(k_diag_copy, dim3(1), dim3(TPB), 0, ctx->stream, Fp.p(), o, fdiag);
   }
   zein(ctx, "mnab,mnij->ijab", half, tau, W0, one, R2);
   zein(ctx, "mnab,ijmn->ijab", quarter, T2, X, one, R2);

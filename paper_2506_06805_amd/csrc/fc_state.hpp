@@ -32,10 +32,18 @@ struct fc_amps_s {
 
 namespace fc {
 // fc_ccsd.hip
-void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, z* r1, z* r2, int precision);
+// fdiag (optional, o + v entries): diagonals of the F_mi and F_ae intermediates that multiply
+// t_ij^ab in the T2 residual (F_mi + 1/2 t_j^e F_me and F_ae - 1/2 t_m^b F_me).
+void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, z* r1, z* r2, int precision,
+                       z* fdiag = nullptr);
 void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision);
 z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2);
 void assemble_integrals(fc_ctx ctx, fc_ints I);
+// fc_mlp.hip
+int learned_step(fc_ctx ctx, fc_ints I, const void* mlp, const z* t1, const z* t2, const z* r1, const z* r2,
+                 const z* r2prev, const z* fdiag, z* o1, z* o2);
+void learn_samples(fc_ctx ctx, fc_ints I, const z* t2, const z* r2, const z* r2prev, const z* t2s, const z* fdiag,
+                   long nsamp, unsigned long long seed, float* X, float* q, float* r);
 // fc_eom.hip
 void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T);
 void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S);

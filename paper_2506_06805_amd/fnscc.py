@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import pathlib
+import weakref
 
 import numpy as np
 
@@ -23,12 +24,13 @@ PRECISION = {"fp64": FC_FP64, "split-bf16": FC_SPLIT_BF16, "split-fp16": FC_SPLI
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+ON_ITER_FN = C.CFUNCTYPE(None, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p)
 
 
 class CcsdOpts(C.Structure):
     _fields_ = [("e_tol", C.c_double), ("r_tol", C.c_double), ("max_iter", C.c_int), ("diis_dim", C.c_int),
                 ("learned", C.c_int), ("precision", C.c_int), ("t1_init", C.c_void_p), ("t2_init", C.c_void_p),
-                ("mlp", C.c_void_p), ("stall_window", C.c_int)]
+                ("mlp", C.c_void_p), ("stall_window", C.c_int), ("on_iter", ON_ITER_FN), ("user", C.c_void_p)]
 
 
 class EomOpts(C.Structure):
@@ -57,6 +59,14 @@ _sig = {
     "ipeom_sigma": (C.c_int, [P, P, P, C.c_int, P, P]),
     "fc_eom_default_opts": (None, [C.POINTER(EomOpts)]),
     "ipeom_davidson": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P), P, C.POINTER(EomOpts), P, P, P]),
+    "fc_mlp_create": (C.c_int, [P, P, C.c_ulonglong, C.POINTER(P)]),
+    "fc_mlp_free": (None, [P]),
+    "fc_mlp_num_params": (C.c_long, []),
+    "fc_mlp_get_params": (C.c_int, [P, P, C.c_int]),
+    "fc_mlp_grad": (C.c_int, [P, P, P, P, C.c_long, P, P]),
+    "fc_mlp_train_step": (C.c_int, [P, P, P, P, C.c_long, C.c_float, P]),
+    "fc_mlp_forward": (C.c_int, [P, P, C.c_long, P, C.c_int]),
+    "fc_learn_samples": (C.c_int, [P, P, P, P, P, P, P, C.c_long, C.c_ulonglong, P, P, P]),
     "fc_host_zheev": (C.c_int, [C.c_int, P, P]),
     "fc_host_zgeev": (C.c_int, [C.c_int, P, P, P]),
 }
@@ -117,7 +127,7 @@ class Context:
         self.torch = torch
         self.device = device
         self.stream = stream or torch.cuda.current_stream(device)
-        self._live = {}
+        self._children = weakref.WeakSet()   # handles that must be freed before the context
         if use_torch_allocator:
             def _alloc(nbytes, _stream, _user):
                 try:
@@ -144,8 +154,14 @@ class Context:
         if rc not in (FC_OK,):
             raise FcError(rc, f"{what}: {lib.fc_last_error(self.h).decode()}")
 
+    def adopt(self, child):
+        self._children.add(child)
+        return child
+
     def close(self):
         if getattr(self, "h", None):
+            for child in list(self._children):
+                child.free()
             lib.fc_destroy(self.h)
             self.h = None
 
@@ -169,28 +185,41 @@ class Context:
         return out
 
 
-class Ints:
-    def __init__(self, ctx: Context, h, o, v, ncd):
-        self.ctx, self.h, self.o, self.v, self.ncd = ctx, h, o, v, ncd
+class _Handle:
+    """Library handle owned by a context; freed before the context is destroyed."""
+
+    _free_fn = None
+
+    def free(self):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
+            type(self)._free_fn(self.h)
+        self.h = None
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib.fc_free_ints(self.h)
-            self.h = None
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Ints(_Handle):
+    _free_fn = staticmethod(lambda h: lib.fc_free_ints(h))
+
+    def __init__(self, ctx: Context, h, o, v, ncd):
+        self.ctx, self.h, self.o, self.v, self.ncd = ctx, h, o, v, ncd
+        ctx.adopt(self)
 
     @property
     def dim(self):
         return self.o + self.o * (self.o - 1) // 2 * self.v
 
 
-class Amps:
+class Amps(_Handle):
+    _free_fn = staticmethod(lambda h: lib.fc_free_amps(h))
+
     def __init__(self, ctx: Context, ints: Ints, h):
         self.ctx, self.ints, self.h = ctx, ints, h
-
-    def __del__(self):
-        if getattr(self, "h", None):
-            lib.fc_free_amps(self.h)
-            self.h = None
+        ctx.adopt(self)
 
     def read(self):
         torch = self.ctx.torch
@@ -237,6 +266,12 @@ def ccsd_opts(**kw):
     for k, val in kw.items():
         if k == "precision":
             val = PRECISION.get(val, val)
+        elif k == "mlp":
+            val = val.h if val is not None else None
+            if val is not None:
+                op.learned = 1
+        elif k == "on_iter":
+            val = ON_ITER_FN(val)
         setattr(op, k, val)
     return op
 
@@ -251,7 +286,9 @@ def ccsd_solve(ctx: Context, ints, allow_noconv=False, **kw):
     e = np.zeros(2 * nb)
     it = np.zeros(nb, dtype=np.int32)
     op = ccsd_opts(**kw)
+    keep = op.on_iter  # the C callback must outlive the call
     rc = lib.ccsd_solve(ctx.h, nb, arr, C.byref(op), outs, e.ctypes.data, it.ctypes.data)
+    del keep
     if rc == FC_ENOCONV and allow_noconv:
         rc = FC_OK
     amps = [Amps(ctx, x, P(outs[b])) for b, x in enumerate(lst)]
@@ -331,3 +368,81 @@ def ipeom_davidson(ctx: Context, ints, amps, nroots, want_vectors=False, allow_n
         vecs = Rout.view(nr[0], il[0].dim) if want_vectors else None
         return (w, int(its[0]), vecs) if want_vectors else (w, int(its[0]))
     return (w, its, Rout) if want_vectors else (w, its)
+
+
+# ------------------------------------------------------------------------------ learned update
+class Mlp(_Handle):
+    """Handle of the learned T2-update network (FP32 master weights, BF16 copy for the solver)."""
+
+    _free_fn = staticmethod(lambda h: lib.fc_mlp_free(h))
+
+    def __init__(self, ctx: Context, params=None, seed=0):
+        self.ctx = ctx
+        h = P()
+        arr = None
+        if params is not None:
+            arr = np.ascontiguousarray(params, dtype=np.float32)
+            assert arr.size == lib.fc_mlp_num_params()
+        rc = lib.fc_mlp_create(ctx.h, arr.ctypes.data if arr is not None else None, seed, C.byref(h))
+        ctx.check(rc, "fc_mlp_create")
+        self.h = h
+        ctx.adopt(self)
+
+    @staticmethod
+    def num_params():
+        return int(lib.fc_mlp_num_params())
+
+    def params(self, bf16=False):
+        out = np.zeros(self.num_params(), dtype=np.float32)
+        self.ctx.check(lib.fc_mlp_get_params(self.h, out.ctypes.data, int(bf16)), "fc_mlp_get_params")
+        return out
+
+    def grad(self, X, q, r):
+        g = np.zeros(self.num_params(), dtype=np.float32)
+        loss = C.c_float()
+        self.ctx.check(lib.fc_mlp_grad(self.h, _ptr(X), _ptr(q), _ptr(r), X.shape[0], g.ctypes.data, C.byref(loss)),
+                       "fc_mlp_grad")
+        return g, float(loss.value)
+
+    def train_step(self, X, q, r, lr):
+        loss = C.c_float()
+        self.ctx.check(lib.fc_mlp_train_step(self.h, _ptr(X), _ptr(q), _ptr(r), X.shape[0], float(lr),
+                                             C.byref(loss)), "fc_mlp_train_step")
+        return float(loss.value)
+
+    def forward(self, X, bf16=False):
+        torch = self.ctx.torch
+        Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
+        self.ctx.check(lib.fc_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y), int(bf16)), "fc_mlp_forward")
+        return Y
+
+
+def learn_samples(ctx: Context, ints: Ints, t1_ptr, t2_ptr, t2_star, nsamp, seed, out=None, offset=0, prev=None):
+    """Training samples at an iterate; t1_ptr/t2_ptr are device addresses or tensors, prev the
+    previous iterate (t1, t2) tensors or None."""
+    torch = ctx.torch
+    if out is None:
+        dev = f"cuda:{ctx.device}"
+        out = (torch.empty((nsamp, 4), dtype=torch.float32, device=dev),
+               torch.empty((nsamp, 2), dtype=torch.float32, device=dev),
+               torch.empty((nsamp, 2), dtype=torch.float32, device=dev))
+        offset = 0
+    X, q, r = out
+    a1 = t1_ptr if isinstance(t1_ptr, int) else _ptr(t1_ptr)
+    a2 = t2_ptr if isinstance(t2_ptr, int) else _ptr(t2_ptr)
+    p1, p2 = (None, None) if prev is None else (_ptr(prev[0]), _ptr(prev[1]))
+    rc = lib.fc_learn_samples(ctx.h, ints.h, a1, a2, p1, p2, _ptr(t2_star), nsamp, seed,
+                              X.data_ptr() + 16 * offset, q.data_ptr() + 8 * offset, r.data_ptr() + 8 * offset)
+    ctx.check(rc, "fc_learn_samples")
+    return out
+
+
+def device_copy(ctx: Context, ptr, shape):
+    """complex128 tensor copied from a device address (an iterate handed to a callback)."""
+    torch = ctx.torch
+
+    class _View:
+        __cuda_array_interface__ = {"shape": tuple(shape), "typestr": "<c16", "data": (int(ptr), False),
+                                    "version": 2, "strides": None}
+
+    return torch.as_tensor(_View(), device=f"cuda:{ctx.device}").clone()

@@ -199,3 +199,29 @@ def test_p12_davidson_equals_dense():
     M = eom.dense_matrix(h)
     for k in range(4):
         assert np.linalg.norm(M @ X[k] - wv[k] * X[k]) < 1e-8
+
+
+# --------------------------------------------------------------------------- network reference
+def test_mlp_oracle_closed_forms():
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(3)
+    B = 50
+    X = rng.standard_normal((B, 4))
+    q = rng.standard_normal(B) + 1j * rng.standard_normal(B)
+    r = rng.standard_normal(B) + 1j * rng.standard_normal(B)
+    p = np.zeros(sum(omlp.sizes()))
+    g0 = 0.3 - 0.2j
+    p[-2:] = [g0.real, g0.imag]                   # only the output bias: g = b3 for every sample
+    assert np.allclose(omlp.forward(p, X), [[g0.real, g0.imag]] * B)
+    assert abs(omlp.loss(p, X, q, r) - np.sum(np.abs(r - q * g0) ** 2) / np.sum(np.abs(q) ** 2)) < 1e-12
+    # the best constant gain is the weighted least-squares solution; the loss is minimal there
+    gstar = np.sum(q.conj() * r) / np.sum(np.abs(q) ** 2)
+    p[-2:] = [gstar.real, gstar.imag]
+    l0 = omlp.loss(p, X, q, r)
+    for d in (1e-3, -1e-3, 1e-3j):
+        p2 = p.copy()
+        p2[-2:] += [d.real, d.imag] if isinstance(d, complex) else [d, 0]
+        assert omlp.loss(p2, X, q, r) > l0
+    # finite differences of the bias are the analytic derivative of the quadratic
+    fd = omlp.fd_grad(p, X, q, r, idx=[p.size - 2, p.size - 1])
+    assert abs(fd[p.size - 2]) < 1e-8 and abs(fd[p.size - 1]) < 1e-8
