@@ -55,6 +55,15 @@ int fc_set_timing(fc_ctx ctx, int flags);
 /* Writes "name=ms;...;ladder_events=n;ladder_event_ms=ms;calls_name=n;..." into buf (truncated
  * to len) and clears the timers. */
 int fc_take_timings(fc_ctx ctx, char* buf, size_t len);
+/* GEMM tile autotuning. When on, the first complex GEMM of each shape bucket (operand layouts,
+ * sizes rounded up to powers of two, batching, epilogue) times every tile configuration once on a
+ * scratch output and keeps the fastest for the bucket; later calls reuse the choice. The table can
+ * be saved to and loaded from a text file (one "bucket config ms" line per bucket). Off by
+ * default (a size heuristic is used). fc_autotune_size returns the number of tuned buckets. */
+int fc_set_autotune(fc_ctx ctx, int on);
+int fc_autotune_save(fc_ctx ctx, const char* path);
+int fc_autotune_load(fc_ctx ctx, const char* path);
+int fc_autotune_size(fc_ctx ctx);
 
 /* cd_integrals - stage the Cholesky vectors (Eq. 22) and assemble the stored antisymmetrised
  * integrals with at most two virtual indices (Eq. 23 and the storage rule of Sec. 3:

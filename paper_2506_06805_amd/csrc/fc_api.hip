@@ -331,6 +331,36 @@ int fc_take_timings(fc_ctx ctx, char* buf, size_t len) {
   })
 }
 
+int fc_set_autotune(fc_ctx ctx, int on) {
+  if (!ctx) return FC_EARG;
+  ctx->autotune = on;
+  return FC_OK;
+}
+
+int fc_autotune_save(fc_ctx ctx, const char* path) {
+  if (!ctx || !path) return FC_EARG;
+  FILE* f = fopen(path, "w");
+  if (!f) { ctx->last_error = std::string("cannot write ") + path; return FC_EARG; }
+  for (auto& kv : ctx->tune) fprintf(f, "%s %d %.6f\n", kv.first.c_str(), kv.second.first, kv.second.second);
+  fclose(f);
+  return FC_OK;
+}
+
+int fc_autotune_load(fc_ctx ctx, const char* path) {
+  if (!ctx || !path) return FC_EARG;
+  FILE* f = fopen(path, "r");
+  if (!f) { ctx->last_error = std::string("cannot read ") + path; return FC_EARG; }
+  char key[128];
+  int cfg;
+  float ms;
+  while (fscanf(f, "%127s %d %f", key, &cfg, &ms) == 3)
+    if (cfg >= 0 && cfg < 3) ctx->tune[key] = {cfg, ms};
+  fclose(f);
+  return FC_OK;
+}
+
+int fc_autotune_size(fc_ctx ctx) { return ctx ? (int)ctx->tune.size() : 0; }
+
 int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const void* L, int l_dtype, int l_on_device,
                  int precision, fc_ints* out) {
   if (!ctx || !out) return FC_EARG;

@@ -222,9 +222,76 @@ void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
   else zgemm_f64_kernel<BM, BN, WGM, WGN, true, true, EPI><<<grid, NT, 0, s>>>(g);
 }
 
+// Tile configurations: 0 = 64 x 64 (4 waves), 1 = 128 x 64 (4 waves), 2 = 128 x 128 (8 waves).
+constexpr int NCFG = 3;
+constexpr int CFG_BM[NCFG] = {64, 128, 128}, CFG_BN[NCFG] = {64, 64, 128};
+
+// Launch one configuration (split-K decided inside for configurations whose grid cannot fill the chip).
+void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+               const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
+               const LadderEpilogue* lep);
+
+// Shape bucket: operand layouts, sizes rounded to powers of two, batching and epilogue kind.
+std::string bucket(char opA, char opB, long M, long N, long K, int batch, const LadderEpilogue* lep) {
+  auto lg = [](long x) { int b = 0; while ((1L << b) < x) ++b; return b; };
+  char buf[96];
+  snprintf(buf, sizeof(buf), "%c%c_m%d_n%d_k%d_b%d_e%d", opA, opB, lg(M), lg(N), lg(K), batch > 1,
+           lep ? 1 + lep->triangular : 0);
+  return buf;
+}
+
+int heuristic_cfg(long M, long N, int batch) {
+  const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * (long)batch >= 512;
+  return big ? 2 : 0;
+}
+
 void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B,
                 long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC, const LadderEpilogue* lep) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
+  FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
+  int cfg = heuristic_cfg(M, N, batch);
+  if (ctx->autotune && K > 0) {
+    const std::string key = bucket(opA, opB, M, N, K, batch, lep);
+    auto it = ctx->tune.find(key);
+    if (it != ctx->tune.end()) {
+      cfg = it->second.first;
+    } else {
+      // time every configuration once (after one warm-up launch) on a scratch copy of C, keep the fastest
+      const long csz = lep ? (M / lep->v) * lep->nB * lep->v * lep->v
+                           : ((long)(batch - 1) * sC + (M - 1) * ldc + N);
+      DBuf scratch(ctx, sizeof(z) * (size_t)std::max(1L, csz));
+      hipEvent_t e0, e1;
+      FC_HIP(hipEventCreate(&e0));
+      FC_HIP(hipEventCreate(&e1));
+      float best = 1e30f;
+      int bestc = cfg;
+      for (int c = 0; c < NCFG; ++c) {
+        if (CFG_BM[c] > 64 && M < 128) continue;
+        if (CFG_BN[c] > 64 && N < 128) continue;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+          if (!lep && (beta.x != 0.0 || beta.y != 0.0))
+            FC_HIP(hipMemcpyAsync(scratch.p, C, sizeof(z) * csz, hipMemcpyDeviceToDevice, ctx->stream));
+          FC_HIP(hipEventRecord(e0, ctx->stream));
+          zgemm_run(ctx, c, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, scratch.as<z>(), ldc, batch, sA, sB, sC, lep);
+          FC_HIP(hipEventRecord(e1, ctx->stream));
+          FC_HIP(hipEventSynchronize(e1));
+          FC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        }
+        if (ms < best) { best = ms; bestc = c; }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      ctx->tune[key] = {bestc, best};
+      cfg = bestc;
+    }
+  }
+  zgemm_run(ctx, cfg, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, lep);
+}
+
+void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+               const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
+               const LadderEpilogue* lep) {
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   if (K <= 0) {  // C = beta C
     FC_REQUIRE(!lep, FC_EARG, "zgemm: empty ladder product");
@@ -246,9 +313,8 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
   const bool ta = (opA == 'T' || opA == 'C');
   const bool tb = (opB == 'T' || opB == 'C');
   FC_REQUIRE(batch <= 65535, FC_EARG, "zgemm: batch too large");
-  // large products take 128 x 128 tiles when that still leaves >= 2 workgroups per CU
-  const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * (long)batch >= 512;
-  const long bm = big ? 128 : 64, bn = big ? 128 : 64;
+  FC_REQUIRE(cfg >= 0 && cfg < NCFG, FC_EARG, "zgemm: bad tile configuration");
+  const long bm = CFG_BM[cfg], bn = CFG_BN[cfg];
   const long tiles = ((N + bn - 1) / bn) * ((M + bm - 1) / bm);
   FC_REQUIRE(tiles < (1L << 30), FC_EARG, "zgemm: problem too large for one launch");
   g.tiles = tiles;
@@ -271,10 +337,12 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit, (unsigned)batch);
   if (lep) {
-    if (big) launch<128, 128, 2, 4, 1>(g, ta, tb, grid, ctx->stream);
+    if (cfg == 2) launch<128, 128, 2, 4, 1>(g, ta, tb, grid, ctx->stream);
+    else if (cfg == 1) launch<128, 64, 2, 2, 1>(g, ta, tb, grid, ctx->stream);
     else launch<64, 64, 2, 2, 1>(g, ta, tb, grid, ctx->stream);
   } else {
-    if (big) launch<128, 128, 2, 4, 0>(g, ta, tb, grid, ctx->stream);
+    if (cfg == 2) launch<128, 128, 2, 4, 0>(g, ta, tb, grid, ctx->stream);
+    else if (cfg == 1) launch<128, 64, 2, 2, 0>(g, ta, tb, grid, ctx->stream);
     else launch<64, 64, 2, 2, 0>(g, ta, tb, grid, ctx->stream);
   }
   FC_HIP(hipGetLastError());

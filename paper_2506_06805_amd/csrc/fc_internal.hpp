@@ -55,6 +55,9 @@ struct fc_ctx_s {
   std::map<std::string, long> stage_calls;
   // hipEvents bracketing ladder launches (measured on this context's stream)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ladder_events;
+  // GEMM autotuning: shape bucket -> chosen configuration (and its measured time in ms)
+  int autotune = 0;
+  std::map<std::string, std::pair<int, float>> tune;
 };
 
 namespace fc {

@@ -73,12 +73,12 @@ struct SplitOut {
 };
 
 template <class T, class Out>
-__global__ __launch_bounds__(256) void k_ladder_anti(const T* __restrict__ W, const int2* __restrict__ slots, long v,
+__global__ __launch_bounds__(256) void k_ladder_anti(const T* __restrict__ W, const int* __restrict__ compact, long v,
                                                     long nbv, Out out) {
   __shared__ T X[32][33], Y[32][33];
   const long s = blockIdx.y;
-  const int2 ab = slots[s];
-  if (ab.x >= ab.y) return;   // slot not needed (its Wp row is zero)
+  const int c = compact[s];   // row of the valid pair (a < b) in Wp, or -1
+  if (c < 0) return;
   // block pair (E, F), E <= F, from the linear id
   long q = blockIdx.x, E = 0;
   while (q >= nbv - E) { q -= nbv - E; ++E; }
@@ -96,18 +96,17 @@ __global__ __launch_bounds__(256) void k_ladder_anti(const T* __restrict__ W, co
     long e = E * 32 + r, f = F * 32 + tx;
     if (e < f && f < v) {
       T x = X[r][tx], y = Y[tx][r];
-      out.put(s, pair_index(e, f, v), (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+      out.put(c, pair_index(e, f, v), (double)x.x - (double)y.x, (double)x.y - (double)y.y);
     }
   }
 }
 
-__global__ void k_maxabs_slots(const float2* __restrict__ W, const int2* __restrict__ slots, long nslots, long vv,
+__global__ void k_maxabs_slots(const float2* __restrict__ W, const int* __restrict__ compact, long nslots, long vv,
                                unsigned* out) {
   __shared__ float sm[TPB];
   float m = 0.f;
   GRID_STRIDE(t, nslots * vv) {
-    const int2 ab = slots[t / vv];
-    if (ab.x < ab.y) m = fmaxf(m, fmaxf(fabsf(W[t].x), fabsf(W[t].y)));
+    if (compact[t / vv] >= 0) m = fmaxf(m, fmaxf(fabsf(W[t].x), fabsf(W[t].y)));
   }
   sm[threadIdx.x] = m;
   __syncthreads();
@@ -119,13 +118,12 @@ __global__ void k_maxabs_slots(const float2* __restrict__ W, const int2* __restr
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(sm[0]));
 }
 
-// R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][slot]
-__global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, const int2* slots,
-                                 long nslots, const int2* po, long no) {
-  GRID_STRIDE(t, no * nslots) {
-    const long s = t % nslots, pi = t / nslots;
-    const int2 ab = slots[s];
-    if (ab.x >= ab.y) continue;
+// R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][c], c indexing the valid pairs a < b
+__global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, const int2* pairs,
+                                 long npairs, const int2* po, long no) {
+  GRID_STRIDE(t, no * npairs) {
+    const long s = t % npairs, pi = t / npairs;
+    const int2 ab = pairs[s];
     const int2 ij = po[pi];
     const z r = Rp[t], m = make_double2(-r.x, -r.y);
     const long i = ij.x, j = ij.y, a = ab.x, b = ab.y;
@@ -195,7 +193,7 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
     }
     DBuf Wbuf(ctx, (size_t)esz * max_slots * v * v);
     DBuf Rp(ctx, sizeof(z) * no * max_slots);
-    DBuf slots_d(ctx, sizeof(int2) * max_slots);
+    DBuf slots_d(ctx, sizeof(int2) * max_slots), compact_d(ctx, sizeof(int) * max_slots);
     const long nbv = (v + 31) / 32, ntri = nbv * (nbv + 1) / 2;
     SplitOp Ls, Ts, Wps;
     DBuf Wp64;
@@ -206,6 +204,8 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
       Wps.kp = Ts.kp;
       Wps.rows_pad = (max_slots + 127) / 128 * 128 + 128;
       Wps.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp);
+      // the contraction padding (pef >= nv) is never written by the chunks: clear it once
+      FC_HIP(hipMemsetAsync(Wps.buf.p, 0, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp, ctx->stream));
     } else {
       Wp64 = DBuf(ctx, sizeof(z) * (size_t)max_slots * nv);
     }
@@ -232,21 +232,33 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
       }
       (void)first;
       const long ns = (long)hslots.size();
-      FC_HIP(hipMemcpyAsync(slots_d.p, hslots.data(), sizeof(int2) * ns, hipMemcpyHostToDevice, ctx->stream));
+      // valid pairs (a < b) get consecutive rows of Wp; the others (below-diagonal slots of diagonal
+      // block pairs) are skipped by the antisymmetrisation, the contraction and the scatter
+      std::vector<int> hcompact(ns, -1);
+      std::vector<int2> hpairs;
+      for (long s = 0; s < ns; ++s)
+        if (hslots[s].x < hslots[s].y) { hcompact[s] = (int)hpairs.size(); hpairs.push_back(hslots[s]); }
+      const long nvalid = (long)hpairs.size();
+      if (nvalid > 0)
+        FC_HIP(hipMemcpyAsync(slots_d.p, hpairs.data(), sizeof(int2) * nvalid, hipMemcpyHostToDevice, ctx->stream));
+      FC_HIP(hipMemcpyAsync(compact_d.p, hcompact.data(), sizeof(int) * ns, hipMemcpyHostToDevice, ctx->stream));
       dim3 agrid((unsigned)ntri, (unsigned)ns);
       FC_REQUIRE(ns <= 65535, FC_EARG, "ladder: chunk has too many (a,b) slots");
+      if (nvalid == 0) {   // only below-diagonal slots in this chunk
+        FC_HIP(hipStreamSynchronize(ctx->stream));
+        continue;
+      }
       if (!split) {
-        FC_HIP(hipMemsetAsync(Wp64.p, 0, sizeof(z) * (size_t)ns * nv, ctx->stream));
         AntiOut<double2> out{Wp64.as<z>(), nv};
         k_ladder_anti<double2, AntiOut<double2>><<<agrid, 256, 0, ctx->stream>>>(Wbuf.as<double2>(),
-                                                                                 slots_d.as<int2>(), v, nbv, out);
+                                                                                 compact_d.as<int>(), v, nbv, out);
         FC_HIP(hipGetLastError());
-        zgemm(ctx, 'N', 'T', no, ns, nv, one, taup.as<z>(), nv, Wp64.as<z>(), nv, zero, Rp.as<z>(), ns);
+        zgemm(ctx, 'N', 'T', no, nvalid, nv, one, taup.as<z>(), nv, Wp64.as<z>(), nv, zero, Rp.as<z>(), nvalid);
       } else {
         Wps.scale = 1.0;
         if (precision == FC_SPLIT_FP16) {
           FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned), ctx->stream));
-          k_maxabs_slots<<<nblk(ns * v * v), TPB, 0, ctx->stream>>>(Wbuf.as<float2>(), slots_d.as<int2>(), ns, v * v,
+          k_maxabs_slots<<<nblk(ns * v * v), TPB, 0, ctx->stream>>>(Wbuf.as<float2>(), compact_d.as<int>(), ns, v * v,
                                                                     mx.as<unsigned>());
           FC_HIP(hipGetLastError());
           unsigned hb = 0;
@@ -257,23 +269,22 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
           // differences are at most twice the largest entry; keep them below 2^14
           if (m > 0) Wps.scale = std::ldexp(1.0, 12 - std::ilogb((double)m));
         }
-        Wps.rows = ns;
-        FC_HIP(hipMemsetAsync(Wps.buf.p, 0, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp, ctx->stream));
+        Wps.rows = nvalid;
         const long plane = Wps.rows_pad * Wps.kp;
         if (precision == FC_SPLIT_BF16) {
           SplitOut<FC_SPLIT_BF16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
           k_ladder_anti<float2, SplitOut<FC_SPLIT_BF16>><<<agrid, 256, 0, ctx->stream>>>(
-              Wbuf.as<float2>(), slots_d.as<int2>(), v, nbv, out);
+              Wbuf.as<float2>(), compact_d.as<int>(), v, nbv, out);
         } else {
           SplitOut<FC_SPLIT_FP16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
           k_ladder_anti<float2, SplitOut<FC_SPLIT_FP16>><<<agrid, 256, 0, ctx->stream>>>(
-              Wbuf.as<float2>(), slots_d.as<int2>(), v, nbv, out);
+              Wbuf.as<float2>(), compact_d.as<int>(), v, nbv, out);
         }
         FC_HIP(hipGetLastError());
-        gemm_split_nt(ctx, Ts, 0, no, Wps, 0, ns, one, zero, Rp.as<z>(), ns);
+        gemm_split_nt(ctx, Ts, 0, no, Wps, 0, nvalid, one, zero, Rp.as<z>(), nvalid);
       }
-      hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * ns)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R, o, v,
-                         slots_d.as<int2>(), ns, po.as<int2>(), no);
+      hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nvalid)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R, o, v,
+                         slots_d.as<int2>(), nvalid, po.as<int2>(), no);
       FC_HIP(hipGetLastError());
       // the slot table is rewritten by the next chunk: keep host and device in order
       FC_HIP(hipStreamSynchronize(ctx->stream));

@@ -45,6 +45,10 @@ _sig = {
     "fc_last_error": (C.c_char_p, [P]),
     "fc_set_timing": (C.c_int, [P, C.c_int]),
     "fc_take_timings": (C.c_int, [P, C.c_char_p, C.c_size_t]),
+    "fc_set_autotune": (C.c_int, [P, C.c_int]),
+    "fc_autotune_save": (C.c_int, [P, C.c_char_p]),
+    "fc_autotune_load": (C.c_int, [P, C.c_char_p]),
+    "fc_autotune_size": (C.c_int, [P]),
     "cd_integrals": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(P)]),
     "fc_ints_info": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "fc_free_ints": (None, [P]),
@@ -173,6 +177,18 @@ class Context:
 
     def set_timing(self, on=True):
         lib.fc_set_timing(self.h, int(on))
+
+    def set_autotune(self, on=True):
+        self.check(lib.fc_set_autotune(self.h, int(on)), "fc_set_autotune")
+
+    def autotune_save(self, path):
+        self.check(lib.fc_autotune_save(self.h, str(path).encode()), "fc_autotune_save")
+
+    def autotune_load(self, path):
+        self.check(lib.fc_autotune_load(self.h, str(path).encode()), "fc_autotune_load")
+
+    def autotune_size(self):
+        return int(lib.fc_autotune_size(self.h))
 
     def take_timings(self):
         buf = C.create_string_buffer(1 << 16)

@@ -1,0 +1,70 @@
+"""GEMM autotuning and the chunked ladder paths: results must not depend on tile choices or on how
+the (a,b) pairs are chunked."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ccsd, integrals
+from paper_2506_06805_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _tau(o, v, seed):
+    rng = np.random.default_rng(seed)
+    t = (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v))) * 0.05
+    t = t - t.transpose(1, 0, 2, 3)
+    return t - t.transpose(0, 1, 3, 2)
+
+
+def _ladder_ref(inst, tau):
+    o, v = inst.o, inst.v
+    V = slice(o, o + v)
+    return 0.5 * np.einsum("ijef,abef->ijab", tau, integrals.antisym(inst.L, V, V, V, V), optimize=True)
+
+
+@pytest.mark.parametrize("o,v,N", [(3, 65, 20), (4, 129, 16)])
+@pytest.mark.parametrize("budget_gb", ["8", "0.0004"])
+def test_ladder_chunking(gpu_ctx, o, v, N, budget_gb, monkeypatch):
+    from paper_2506_06805_amd import fnscc
+    monkeypatch.setenv("FNSCC_LADDER_BUDGET_GB", budget_gb)
+    inst = synth.make_instance(o, v, N, seed=5 + v, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    tau = _tau(o, v, 1)
+    ref = _ladder_ref(inst, tau)
+    for prec, tol in (("fp64", 1e-11), ("split-bf16", 2e-4), ("split-fp16", 2e-6)):
+        R = fnscc.ladder(gpu_ctx, ints, _dev(tau), precision=prec).cpu().numpy()
+        assert np.abs(R - ref).max() / np.abs(ref).max() < tol, prec
+
+
+def test_autotune_keeps_results_and_roundtrips(gpu_ctx, tmp_path):
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 7, 90, 60
+    inst = synth.make_instance(o, v, N, seed=17, kappa=0.5)
+    rng = np.random.default_rng(3)
+    t1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * 0.02
+    t2 = _tau(o, v, 2) * 0.3
+    ref1, ref2 = ccsd.residuals(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    ctx = fnscc.Context(0)
+    try:
+        ctx.set_autotune(True)
+        ints = fnscc.cd_integrals(ctx, inst.eps, inst.L, o)
+        r1, r2 = fnscc.ccsd_residual(ctx, ints, _dev(t1), _dev(t2))
+        assert ctx.autotune_size() > 5
+        for a, b in ((r1, ref1), (r2, ref2)):
+            a = a.cpu().numpy()
+            assert np.abs(a - b).max() / np.abs(b).max() < 1e-11
+        path = tmp_path / "tune.txt"
+        ctx.autotune_save(path)
+        ctx2 = fnscc.Context(0)
+        ctx2.autotune_load(path)
+        assert ctx2.autotune_size() == ctx.autotune_size()
+        ctx2.close()
+    finally:
+        ctx.close()
