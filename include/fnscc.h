@@ -135,13 +135,18 @@ void fc_free_amps(fc_amps t);
  * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3). */
 int ipeom_sigma(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* R, void* S);
 
+/* graph: 1 (default) captures the sigma launches of all instances once into a HIP graph and
+ * replays it for every Davidson iteration; 0 launches them directly (same results bit for bit). */
 typedef struct {
   double r_tol, w_tol;
   int max_iter, max_subspace, guess_per_root;
+  int graph;
 } fc_eom_opts;
 void fc_eom_default_opts(fc_eom_opts* opts);
 /* ipeom_davidson - lowest-nroots (by real part) eigenvalues omega_k of the IP-EOM-CCSD matrix
  * (Eq. 18) by non-Hermitian Davidson; subspace eigenproblem in FP64 on the host.
+ * nb > 1 solves uneven instances together: every Davidson step is one launch for the whole
+ * batch and the sigma products of all new trial vectors of all instances are one graph replay.
  * omega: host, sum(nroots) x 2 doubles (re, im), ascending real part per instance.
  * R_out: device, sum(nroots) x dim_b right eigenvectors (or NULL). iters: host, nb ints. */
 int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,

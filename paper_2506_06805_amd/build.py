@@ -25,6 +25,7 @@ SOURCES = [
     "fc_integrals.hip",
     "fc_ccsd.hip",
     "fc_ladder.hip",
+    "fc_sigma.hip",
     "fc_eom.hip",
     "fc_mlp.hip",
     "fc_api.hip",

@@ -12,7 +12,8 @@
 namespace fc {
 void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype);
 void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2);
-int davidson_one(fc_ctx ctx, fc_ints I, fc_amps T, int k, const fc_eom_opts& op, z* omega, z* Rout, int* iters);
+int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
+                   const fc_eom_opts& op, z* omega, z* Rout, int* iters);
 
 namespace {
 constexpr int TPB = 256;
@@ -528,6 +529,7 @@ void fc_eom_default_opts(fc_eom_opts* op) {
   op->max_iter = 200;
   op->max_subspace = 0;  // 0 = 20 x roots
   op->guess_per_root = 2;
+  op->graph = 1;
 }
 
 int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
@@ -536,25 +538,17 @@ int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, co
   FC_TRY(ctx, {
     fc_eom_opts op;
     if (opts) op = *opts; else fc_eom_default_opts(&op);
-    int status = FC_OK;
-    long off = 0, roff = 0;
+    FC_REQUIRE(op.max_iter >= 1, FC_EARG, "ipeom_davidson: max_iter must be >= 1");
+    long total = 0;
     for (int b = 0; b < nb; ++b) {
-      FC_REQUIRE(ints[b] && t[b] && t[b]->ints == ints[b], FC_EARG, "ipeom_davidson: bad handles");
-      const int k = nroots[b];
-      fc_eom_opts ob = op;
-      if (ob.max_subspace <= 0) ob.max_subspace = 20 * k;
-      std::vector<z> w(k);
-      const long o = ints[b]->o, v = ints[b]->v, dim = o + o * (o - 1) / 2 * v;
-      z* rout = R_out ? (z*)R_out + roff : nullptr;
-      int itb = 0;
-      int s = davidson_one(ctx, ints[b], t[b], k, ob, w.data(), rout, &itb);
-      for (int r = 0; r < k; ++r) { omega[2 * (off + r)] = w[r].x; omega[2 * (off + r) + 1] = w[r].y; }
-      if (iters) iters[b] = itb;
-      off += k;
-      roff += (long)k * dim;
-      if (s != FC_OK) status = s;
+      FC_REQUIRE(nroots[b] >= 1, FC_EARG, "ipeom_davidson: nroots must be >= 1");
+      total += nroots[b];
     }
-    return status;
+    std::vector<z> w(total);
+    const int s = davidson_batch(ctx, nb, ints, t, nroots, op, w.data(), (z*)R_out, iters);
+    for (long r = 0; r < total; ++r) { omega[2 * r] = w[r].x; omega[2 * r + 1] = w[r].y; }
+    if (s == FC_ENOCONV) ctx->last_error = "ipeom_davidson: not converged within max_iter";
+    return s;
   })
 }
 

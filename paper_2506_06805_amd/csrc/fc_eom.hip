@@ -5,11 +5,13 @@
 // sigma_ij^a = -W_maij r_m + F_ae r_ij^e - P(ij) F_mi r_mj^a + 1/2 W_mnij r_mn^a
 //              + P(ij) W_maej r_im^e + X_e t_ij^ae,   X_e = 1/2 <mn||ef> r_mn^f
 // The only three-virtual piece, 1/2 sum_ef <mb||ef> tau_ij^ef inside W_mbij, is formed once from
-// the Cholesky vectors in occupied-index chunks, never stored whole.
+// the Cholesky vectors in occupied-index chunks, never stored whole.  The sigma products
+// themselves are evaluated as matrix products over the packed vector layout (fc_sigma.hip).
 #include <algorithm>
 #include <cmath>
+#include <complex>
 
-#include "fc_state.hpp"
+#include "fc_sigma.hpp"
 
 namespace fc {
 void jacobi_step(fc_ctx, fc_ints, const z*, const z*, const z*, const z*, z*, z*);
@@ -46,49 +48,6 @@ __global__ void k_antisym_last2(z* W, const z* x, long outer, long o, z alpha) {
 // add eps on the diagonal of an n x n block
 __global__ void k_add_diag(z* F, const double* e, long n) {
   GRID_STRIDE(i, n) { F[i * n + i].x += e[i]; }
-}
-// [k][i][j][a] += alpha (x - x^(i<->j))
-__global__ void k_antisym_ij_k(z* S, const z* x, long nk, long o, long v, z alpha) {
-  GRID_STRIDE(t, nk * o * o * v) {
-    long a = t % v, j = (t / v) % o, i = (t / (v * o)) % o, k = t / (v * o * o);
-    z p = x[t], q = x[((k * o + j) * o + i) * v + a];
-    z r = cmul(alpha, make_double2(p.x - q.x, p.y - q.y));
-    S[t].x += r.x; S[t].y += r.y;
-  }
-}
-// packed R [k][dim] -> r1 [k][o], r2 [k][o][o][v] (antisymmetric in ij)
-__global__ void k_unpack(const z* R, z* r1, z* r2, long nk, long o, long v, long dim, const int2* po, long no) {
-  GRID_STRIDE(t, nk * o * o * v) {
-    long b = t % v, j = (t / v) % o, i = (t / (v * o)) % o, k = t / (v * o * o);
-    z val = make_double2(0, 0);
-    if (i != j) {
-      long lo = i < j ? i : j, hi = i < j ? j : i;
-      long p = lo * o - lo * (lo + 1) / 2 + (hi - lo - 1);  // index of pair (lo, hi)
-      val = R[k * dim + o + p * v + b];
-      if (i > j) { val.x = -val.x; val.y = -val.y; }
-    }
-    r2[t] = val;
-    if (j == 0 && b == 0) r1[k * o + i] = R[k * dim + i];
-  }
-}
-__global__ void k_pack(const z* s1, const z* s2, z* S, long nk, long o, long v, long dim, const int2* po, long no) {
-  GRID_STRIDE(t, nk * dim) {
-    long x = t % dim, k = t / dim;
-    if (x < o) { S[t] = s1[k * o + x]; continue; }
-    long q = x - o, b = q % v, p = q / v;
-    int2 ij = po[p];
-    S[t] = s2[((k * o + ij.x) * o + ij.y) * v + b];
-  }
-}
-// delta_j = r_j / (theta_j - diag), guarded
-__global__ void k_precond(const z* Rs, z* out, const z* diag, z theta, long dim) {
-  GRID_STRIDE(x, dim) {
-    double dr = theta.x - diag[x].x, di = theta.y - diag[x].y;
-    double m = dr * dr + di * di;
-    if (m < 1e-16) { dr = 1e-8; di = 0; m = 1e-16; }
-    z r = Rs[x];
-    out[x] = make_double2((r.x * dr + r.y * di) / m, (r.y * dr - r.x * di) / m);
-  }
 }
 __global__ void k_diag(const z* Fmi, const z* Fae, z* d, long o, long v, long dim, const int2* po) {
   GRID_STRIDE(x, dim) {
@@ -188,45 +147,60 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
 }
 
 void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S) {
-  StageTimer st(ctx, "sigma");
-  if (!T->hb.ready) build_hbar(ctx, I, T);
-  HbarBlocks& H = T->hb;
-  const long o = I->o, v = I->v, k = nvec;
-  const long no = o * (o - 1) / 2, dim = o + no * v;
-  const z one = make_double2(1, 0), zero = make_double2(0, 0), half = make_double2(0.5, 0),
-          mone = make_double2(-1, 0), mhalf = make_double2(-0.5, 0);
-  if (k <= 0) return;
-  std::vector<int2> hp;
-  for (int i = 0; i < o; ++i) for (int j = i + 1; j < o; ++j) hp.push_back(make_int2(i, j));
-  DBuf po(ctx, sizeof(int2) * std::max(1L, no));
-  if (no) FC_HIP(hipMemcpyAsync(po.p, hp.data(), sizeof(int2) * no, hipMemcpyHostToDevice, ctx->stream));
-  ZTensor r1(ctx, {k, o}), r2(ctx, {k, o, o, v}), s1(ctx, {k, o}), s2(ctx, {k, o, o, v}), x(ctx, {k, o, o, v});
-  hipLaunchKernelGGL(k_unpack, dim3(nblk(r2.size())), dim3(TPB), 0, ctx->stream, R, r1.p(), r2.p(), k, o, v, dim,
-                     po.as<int2>(), no);
-  // sigma_i
-  zein(ctx, "mi,km->ki", mone, H.Fmi, r1, zero, s1);
-  zein(ctx, "me,kime->ki", one, H.Fme, r2, one, s1);
-  zein(ctx, "mnie,kmne->ki", mhalf, H.Wmnie, r2, one, s1);
-  // sigma_ij^a
-  zein(ctx, "maij,km->kija", mone, H.Wmbij, r1, zero, s2);
-  zein(ctx, "ae,kije->kija", one, H.Fae, r2, one, s2);
-  zein(ctx, "mi,kmja->kija", one, H.Fmi, r2, zero, x);
-  hipLaunchKernelGGL(k_antisym_ij_k, dim3(nblk(x.size())), dim3(TPB), 0, ctx->stream, s2.p(), x.p(), k, o, v, mone);
-  zein(ctx, "mnij,kmna->kija", half, H.Wmnij, r2, one, s2);
-  zein(ctx, "maej,kime->kija", one, H.Wmbej, r2, zero, x);
-  hipLaunchKernelGGL(k_antisym_ij_k, dim3(nblk(x.size())), dim3(TPB), 0, ctx->stream, s2.p(), x.p(), k, o, v, one);
-  {
-    ZTensor X(ctx, {k, v});
-    zein(ctx, "mnef,kmnf->ke", half, I->oovv, r2, zero, X);
-    zein(ctx, "ke,ijae->kija", one, X, ZT(T->t2.p(), {o, o, v, v}), one, s2);
-  }
-  hipLaunchKernelGGL(k_pack, dim3(nblk(k * dim)), dim3(TPB), 0, ctx->stream, s1.p(), s2.p(), S, k, o, v, dim,
-                     po.as<int2>(), no);
-  FC_HIP(hipGetLastError());
+  if (nvec <= 0) return;
+  const long k = nvec;
+  SigmaBatch sb(ctx, 1, &I, &T, &k, false);
+  sb.run(&R, &S, &k);
 }
 
 // ------------------------------------------------------------------------------------ Davidson
-static void lowest_by_real(const std::vector<z>& w, int k, std::vector<int>& idx) {
+// All instances advance in lockstep: every step below is one launch (or one transfer) for the
+// whole batch, and the sigma products of all new trial vectors are one replay of a captured graph.
+namespace {
+struct RowJob {
+  const z* X;        // source row
+  z* R;              // destination row
+  const z* diag;
+  z theta;
+  long dim, out;
+};
+// R -= theta X and |R|^2, one workgroup per row, summed in a fixed order
+__global__ void k_resid_norm(const RowJob* __restrict__ jobs, double* __restrict__ nrm) {
+  const RowJob j = jobs[blockIdx.x];
+  double acc = 0;
+  for (long x = threadIdx.x; x < j.dim; x += blockDim.x) {
+    z r = j.R[x];
+    const z xv = j.X[x];
+    r.x -= j.theta.x * xv.x - j.theta.y * xv.y;
+    r.y -= j.theta.x * xv.y + j.theta.y * xv.x;
+    j.R[x] = r;
+    acc += r.x * r.x + r.y * r.y;
+  }
+  __shared__ double sh[TPB];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) nrm[j.out] = sh[0];
+}
+// correction vector R = X / (theta - diag), guarded against a vanishing denominator
+__global__ void k_precond_rows(const RowJob* __restrict__ jobs) {
+  const RowJob j = jobs[blockIdx.y];
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < j.dim; x += (long)gridDim.x * blockDim.x) {
+    double dr = j.theta.x - j.diag[x].x, di = j.theta.y - j.diag[x].y;
+    double m = dr * dr + di * di;
+    if (m < 1e-16) { dr = 1e-8; di = 0; m = 1e-16; }
+    const z r = j.X[x];
+    j.R[x] = make_double2((r.x * dr + r.y * di) / m, (r.y * dr - r.x * di) / m);
+  }
+}
+__global__ void k_set_units(z* V, long dim, const long* idx, long n) {
+  GRID_STRIDE(t, n) { V[t * dim + idx[t]] = make_double2(1.0, 0.0); }
+}
+
+void lowest_by_real(const std::vector<z>& w, int k, std::vector<int>& idx) {
   idx.resize(w.size());
   for (size_t i = 0; i < w.size(); ++i) idx[i] = (int)i;
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
@@ -236,102 +210,293 @@ static void lowest_by_real(const std::vector<z>& w, int k, std::vector<int>& idx
   idx.resize(std::min<size_t>(k, w.size()));
 }
 
-int davidson_one(fc_ctx ctx, fc_ints I, fc_amps T, int k, const fc_eom_opts& op, z* omega, z* Rout, int* iters) {
+// Pinned host buffer mirrored by a device buffer of the same size.
+struct Mirror {
+  fc_ctx ctx = nullptr;
+  char* h = nullptr;
+  DBuf d;
+  size_t bytes = 0;
+  Mirror(fc_ctx c, size_t n) : ctx(c), d(c, std::max<size_t>(n, 64)), bytes(std::max<size_t>(n, 64)) {
+    FC_HIP(hipHostMalloc((void**)&h, bytes, hipHostMallocDefault));
+  }
+  ~Mirror() { if (h) (void)hipHostFree(h); }
+  template <class T> T* host(size_t off) const { return reinterpret_cast<T*>(h + off); }
+  template <class T> T* dev(size_t off) const { return reinterpret_cast<T*>(d.as<char>() + off); }
+  void up(size_t off, size_t n) {
+    if (n) FC_HIP(hipMemcpyAsync(d.as<char>() + off, h + off, n, hipMemcpyHostToDevice, ctx->stream));
+  }
+  void down(size_t off, size_t n) {
+    if (n) FC_HIP(hipMemcpyAsync(h + off, d.as<char>() + off, n, hipMemcpyDeviceToHost, ctx->stream));
+  }
+};
+
+struct Inst {
+  fc_ints I;
+  fc_amps T;
+  int k = 0, nguess = 0, maxsub = 0;
+  long o = 0, v = 0, dim = 0;
+  DBuf V, S, X, Rr, D, D2, diag;
+  int m = 0, gold = 0;            // vectors with sigma; leading block of G already known
+  std::vector<z> G;               // maxsub x maxsub, row-major
+  std::vector<z> Y, w;            // eigenvectors / values of the current subspace matrix
+  std::vector<int> sel;
+  std::vector<z> theta, theta_old;
+  std::vector<double> rn;
+  bool active = true;
+  int iters = 0, status = FC_OK;
+  // byte offsets in the staging mirror: this iteration's new G blocks and Ritz coefficients
+  // (packed per iteration), projection coefficients, Gram matrix, orthonormalising
+  // coefficients and residual norms (fixed)
+  size_t off_g = 0, off_y = 0, off_c = 0, off_gram = 0, off_cc = 0, off_n = 0;
+  int nnew = 0, added = 0;
+  std::vector<int> roots;        // roots that get a correction vector this iteration
+};
+
+// split-K partial sums (complex elements) of one product under tiling `tl`
+size_t split_elems(long M, long N, long K, const GroupTiling& tl) {
+  if (K <= tl.kchunk) return 0;
+  return (size_t)((K + tl.kchunk - 1) / tl.kchunk + 1) * M * N;
+}
+}  // namespace
+
+int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
+                   const fc_eom_opts& op, z* omega, z* Rout, int* iters) {
   StageTimer st(ctx, "davidson");
-  if (!T->hb.ready) build_hbar(ctx, I, T);
-  const long o = I->o, v = I->v, no = o * (o - 1) / 2, dim = o + no * v;
-  FC_REQUIRE(k >= 1 && k <= dim, FC_EARG, "ipeom_davidson: nroots out of range");
   const z one = make_double2(1, 0), zero = make_double2(0, 0), mone = make_double2(-1, 0);
-  const int nguess = (int)std::min<long>(dim, std::max(k, op.guess_per_root * k));
-  const int maxsub = (int)std::min<long>(dim, std::max<long>(op.max_subspace, nguess + k));
-  // diagonal
-  std::vector<int2> hp;
-  for (int i = 0; i < o; ++i) for (int j = i + 1; j < o; ++j) hp.push_back(make_int2(i, j));
-  DBuf po(ctx, sizeof(int2) * std::max(1L, no));
-  if (no) FC_HIP(hipMemcpyAsync(po.p, hp.data(), sizeof(int2) * no, hipMemcpyHostToDevice, ctx->stream));
-  DBuf diag(ctx, sizeof(z) * dim);
-  hipLaunchKernelGGL(k_diag, dim3(nblk(dim)), dim3(TPB), 0, ctx->stream, T->hb.Fmi.p(), T->hb.Fae.p(), diag.as<z>(),
-                     o, v, dim, po.as<int2>());
-  std::vector<z> hdiag(dim);
-  FC_HIP(hipMemcpyAsync(hdiag.data(), diag.p, sizeof(z) * dim, hipMemcpyDeviceToHost, ctx->stream));
-  FC_HIP(hipStreamSynchronize(ctx->stream));
-  std::vector<int> order(dim);
-  for (long i = 0; i < dim; ++i) order[i] = (int)i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hdiag[a].x < hdiag[b].x; });
-  DBuf Vb(ctx, sizeof(z) * (size_t)maxsub * dim), Sb(ctx, sizeof(z) * (size_t)maxsub * dim);
-  z* V = Vb.as<z>();
-  z* S = Sb.as<z>();
-  fill(ctx, V, (long)nguess * dim, zero);
-  for (int g = 0; g < nguess; ++g)
-    FC_HIP(hipMemcpyAsync(V + (size_t)g * dim + order[g], &one, sizeof(z), hipMemcpyHostToDevice, ctx->stream));
-  FC_HIP(hipStreamSynchronize(ctx->stream));
-  int m = nguess;
-  sigma_dev(ctx, I, T, m, V, S);
-  std::vector<z> theta_old;
-  DBuf Xb(ctx, sizeof(z) * (size_t)k * dim), Rb(ctx, sizeof(z) * (size_t)k * dim), Db(ctx, sizeof(z) * (size_t)k * dim);
-  DBuf Yd(ctx, sizeof(z) * (size_t)maxsub * std::max(k, 2 * k)), Cd(ctx, sizeof(z) * (size_t)maxsub * k);
+  const GroupTiling tl{0, 1024};
+  std::vector<Inst> in(nb);
+  size_t wmax = 0, gcap = 0, ycap = 0;
+  long rows_total = 0;
+  for (int b = 0; b < nb; ++b) {
+    Inst& s = in[b];
+    s.I = ints[b];
+    s.T = amps[b];
+    FC_REQUIRE(s.I && s.T && s.T->ints == s.I, FC_EARG, "ipeom_davidson: bad handles");
+    if (!s.T->hb.ready) build_hbar(ctx, s.I, s.T);
+    s.o = s.I->o; s.v = s.I->v;
+    const long no = s.o * (s.o - 1) / 2;
+    s.dim = s.o + no * s.v;
+    s.k = nroots[b];
+    FC_REQUIRE(s.k >= 1 && s.k <= s.dim, FC_EARG, "ipeom_davidson: nroots out of range");
+    s.nguess = (int)std::min<long>(s.dim, std::max(s.k, op.guess_per_root * s.k));
+    const long msub = op.max_subspace > 0 ? op.max_subspace : 20L * s.k;
+    s.maxsub = (int)std::min<long>(s.dim, std::max<long>(msub, s.nguess + s.k));
+    s.V = DBuf(ctx, sizeof(z) * (size_t)s.maxsub * s.dim);
+    s.S = DBuf(ctx, sizeof(z) * (size_t)s.maxsub * s.dim);
+    s.X = DBuf(ctx, sizeof(z) * (size_t)s.k * s.dim);
+    s.Rr = DBuf(ctx, sizeof(z) * (size_t)s.k * s.dim);
+    s.D = DBuf(ctx, sizeof(z) * (size_t)s.k * s.dim);
+    s.D2 = DBuf(ctx, sizeof(z) * (size_t)s.k * s.dim);
+    s.diag = DBuf(ctx, sizeof(z) * s.dim);
+    s.G.assign((size_t)s.maxsub * s.maxsub, zero);
+    gcap += (size_t)s.maxsub * s.maxsub;
+    ycap += (size_t)s.maxsub * s.k;
+    rows_total += s.k;
+    // split-K workspace of one iteration (upper bound): G blocks, Ritz vectors, two rounds of
+    // two projections, Gram matrices and transforms
+    const long ms = s.maxsub, k = s.k, d = s.dim;
+    wmax += 2 * split_elems(ms, ms, d, tl) + 2 * split_elems(k, d, ms, tl) +
+            4 * (split_elems(ms, k, d, tl) + split_elems(k, d, ms, tl)) + 2 * split_elems(k, k, d, tl) +
+            2 * split_elems(k, d, k, tl);
+  }
+  // staging mirror, one contiguous range per kind so each transfer moves one range
+  size_t moff = 0;
+  auto take = [&](size_t n) { size_t a = moff; moff += (n + 255) / 256 * 256; return a; };
+  const size_t rg_g = take(sizeof(z) * gcap), rg_y = take(sizeof(z) * ycap);
+  const size_t rg_n = moff;
+  for (Inst& s : in) s.off_n = take(sizeof(double) * s.k);
+  const size_t rg_n_end = moff;
+  for (Inst& s : in) s.off_gram = take(sizeof(z) * s.k * s.k);
+  const size_t rg_gram_end = moff;
+  const size_t rg_cc = moff;
+  for (Inst& s : in) s.off_cc = take(sizeof(z) * s.k * s.k);
+  const size_t rg_cc_end = moff;
+  for (Inst& s : in) s.off_c = take(sizeof(z) * (size_t)s.maxsub * s.k);
+  const size_t off_jobs = take(sizeof(RowJob) * rows_total);
+  Mirror mir(ctx, moff);
+  GroupArena arena(ctx, 64 * 1024 + (size_t)nb * 48 * 256, wmax);
+
+  // diagonal guesses: unit vectors on the nguess smallest diagonal elements (by real part)
+  for (Inst& s : in) {
+    const long no = s.o * (s.o - 1) / 2;
+    std::vector<int2> hp;
+    for (int i = 0; i < s.o; ++i)
+      for (int j = i + 1; j < s.o; ++j) hp.push_back(make_int2(i, j));
+    DBuf pd(ctx, sizeof(int2) * std::max(1L, no));
+    if (no) FC_HIP(hipMemcpyAsync(pd.p, hp.data(), sizeof(int2) * no, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_diag, dim3(nblk(s.dim)), dim3(TPB), 0, ctx->stream, s.T->hb.Fmi.p(), s.T->hb.Fae.p(),
+                       s.diag.as<z>(), s.o, s.v, s.dim, pd.as<int2>());
+    std::vector<z> hd(s.dim);
+    FC_HIP(hipMemcpyAsync(hd.data(), s.diag.p, sizeof(z) * s.dim, hipMemcpyDeviceToHost, ctx->stream));
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<long> order(s.dim);
+    for (long i = 0; i < s.dim; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](long a, long c) { return hd[a].x < hd[c].x; });
+    order.resize(s.nguess);
+    DBuf id(ctx, sizeof(long) * s.nguess);
+    FC_HIP(hipMemcpyAsync(id.p, order.data(), sizeof(long) * s.nguess, hipMemcpyHostToDevice, ctx->stream));
+    fill(ctx, s.V.as<z>(), (long)s.nguess * s.dim, zero);
+    hipLaunchKernelGGL(k_set_units, dim3(nblk(s.nguess)), dim3(TPB), 0, ctx->stream, s.V.as<z>(), s.dim,
+                       id.as<long>(), (long)s.nguess);
+    FC_HIP(hipGetLastError());
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+  }
+
+  std::vector<long> kmax(nb), nv(nb);
+  std::vector<const z*> Rp(nb);
+  std::vector<z*> Sp(nb);
+  for (int b = 0; b < nb; ++b) kmax[b] = std::max(in[b].nguess, in[b].k);
+  SigmaBatch sb(ctx, nb, ints, amps, kmax.data(), op.graph != 0);
+  for (int b = 0; b < nb; ++b) {
+    nv[b] = in[b].nguess;
+    Rp[b] = in[b].V.as<z>();
+    Sp[b] = in[b].S.as<z>();
+    in[b].m = in[b].nguess;
+  }
+  sb.run(Rp.data(), Sp.data(), nv.data());
+
+  std::vector<GroupGemm> g;
   int it;
   for (it = 1; it <= op.max_iter; ++it) {
-    // subspace matrix G = V^H S  (G[p][q] = <v_p | H v_q>)
-    DBuf Gd(ctx, sizeof(z) * (size_t)m * m);
-    zgemm(ctx, 'R', 'T', m, m, dim, one, V, dim, S, dim, zero, Gd.as<z>(), m);
-    std::vector<z> G(m * (size_t)m), w, Y;
-    FC_HIP(hipMemcpyAsync(G.data(), Gd.p, sizeof(z) * m * m, hipMemcpyDeviceToHost, ctx->stream));
+    bool any = false;
+    for (const Inst& s : in) any = any || s.active;
+    if (!any) break;
+    // the arena's pinned plans of the previous iteration must have been consumed
     FC_HIP(hipStreamSynchronize(ctx->stream));
-    gen_eig(m, G, w, Y);
-    std::vector<int> sel;
-    lowest_by_real(w, k, sel);
-    // Yk (m x k), Ritz vectors X = Yk^T V, residuals R = Yk^T S - theta X
-    std::vector<z> Yk(m * (size_t)k);
-    for (int p = 0; p < m; ++p)
-      for (int r = 0; r < k; ++r) Yk[p * (size_t)k + r] = Y[p * (size_t)m + sel[r]];
-    FC_HIP(hipMemcpyAsync(Yd.p, Yk.data(), sizeof(z) * m * k, hipMemcpyHostToDevice, ctx->stream));
-    zgemm(ctx, 'T', 'N', k, dim, m, one, Yd.as<z>(), k, V, dim, zero, Xb.as<z>(), dim);
-    zgemm(ctx, 'T', 'N', k, dim, m, one, Yd.as<z>(), k, S, dim, zero, Rb.as<z>(), dim);
-    std::vector<double> rn(k);
-    double rmax = 0;
-    for (int r = 0; r < k; ++r) {
-      axpy(ctx, dim, make_double2(-w[sel[r]].x, -w[sel[r]].y), Xb.as<z>() + (size_t)r * dim, Rb.as<z>() + (size_t)r * dim);
-      z nn = dotc(ctx, dim, Rb.as<z>() + (size_t)r * dim, Rb.as<z>() + (size_t)r * dim);
-      rn[r] = std::sqrt(std::max(0.0, nn.x));
-      rmax = std::max(rmax, rn[r]);
+    arena.reset();
+    // (1) new blocks of G = V^H S, packed back to back
+    g.clear();
+    size_t gused = 0;
+    for (Inst& s : in) {
+      if (!s.active || s.gold == s.m) continue;
+      const int nn = s.m - s.gold;
+      s.off_g = rg_g + sizeof(z) * gused;
+      gused += (size_t)s.m * nn + (size_t)nn * s.gold;
+      z* gd = mir.dev<z>(s.off_g);
+      GroupGemm p;
+      p.opA = 'R'; p.opB = 'T'; p.M = s.m; p.N = nn; p.K = s.dim;
+      p.A = s.V.as<z>(); p.lda = s.dim; p.B = s.S.as<z>() + (size_t)s.gold * s.dim; p.ldb = s.dim;
+      p.C = gd; p.ldc = nn;
+      g.push_back(p);
+      if (s.gold > 0) {
+        p = GroupGemm{};
+        p.opA = 'R'; p.opB = 'T'; p.M = nn; p.N = s.gold; p.K = s.dim;
+        p.A = s.V.as<z>() + (size_t)s.gold * s.dim; p.lda = s.dim; p.B = s.S.as<z>(); p.ldb = s.dim;
+        p.C = gd + (size_t)s.m * nn; p.ldc = s.gold;
+        g.push_back(p);
+      }
     }
-    double dw = INFINITY;
-    if (!theta_old.empty()) {
-      dw = 0;
-      for (int r = 0; r < k; ++r)
-        dw = std::max(dw, std::hypot(w[sel[r]].x - theta_old[r].x, w[sel[r]].y - theta_old[r].y));
+    arena.run(g, tl);
+    mir.down(rg_g, sizeof(z) * gused);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    // (2) subspace eigenproblems on the host; Ritz coefficients up
+    size_t yused = 0;
+    for (Inst& s : in) {
+      if (!s.active) continue;
+      const int nn = s.m - s.gold;
+      const z* gh = mir.host<z>(s.off_g);
+      for (int p = 0; p < s.m; ++p)
+        for (int c = 0; c < nn; ++c) s.G[(size_t)p * s.maxsub + s.gold + c] = gh[(size_t)p * nn + c];
+      for (int r = 0; r < nn; ++r)
+        for (int q = 0; q < s.gold; ++q)
+          s.G[(size_t)(s.gold + r) * s.maxsub + q] = gh[(size_t)s.m * nn + (size_t)r * s.gold + q];
+      s.gold = s.m;
+      std::vector<z> Gm((size_t)s.m * s.m);
+      for (int p = 0; p < s.m; ++p)
+        for (int q = 0; q < s.m; ++q) Gm[(size_t)p * s.m + q] = s.G[(size_t)p * s.maxsub + q];
+      gen_eig(s.m, Gm, s.w, s.Y);
+      lowest_by_real(s.w, s.k, s.sel);
+      s.off_y = rg_y + sizeof(z) * yused;
+      yused += (size_t)s.m * s.k;
+      z* yk = mir.host<z>(s.off_y);
+      for (int p = 0; p < s.m; ++p)
+        for (int r = 0; r < s.k; ++r) yk[(size_t)p * s.k + r] = s.Y[(size_t)p * s.m + s.sel[r]];
+      s.theta.assign(s.k, zero);
+      for (int r = 0; r < s.k; ++r) s.theta[r] = s.w[s.sel[r]];
     }
-    theta_old.assign(k, zero);
-    for (int r = 0; r < k; ++r) theta_old[r] = w[sel[r]];
-    if (ctx->verbose) {
-      fprintf(stderr, "[davidson] it %d m %d rmax %.3e dw %.3e w0 %.10f\n", it, m, rmax, dw, w[sel[0]].x);
+    mir.up(rg_y, sizeof(z) * yused);
+    // (3) Ritz vectors X = Yk^T V and residuals R = Yk^T S - theta X with their norms
+    g.clear();
+    long nj = 0;
+    RowJob* jobs = mir.host<RowJob>(off_jobs);
+    for (Inst& s : in) {
+      if (!s.active) continue;
+      GroupGemm p;
+      p.opA = 'T'; p.M = s.k; p.N = s.dim; p.K = s.m;
+      p.A = mir.dev<z>(s.off_y); p.lda = s.k; p.B = s.V.as<z>(); p.ldb = s.dim;
+      p.C = s.X.as<z>(); p.ldc = s.dim;
+      g.push_back(p);
+      p.B = s.S.as<z>(); p.C = s.Rr.as<z>();
+      g.push_back(p);
+      for (int r = 0; r < s.k; ++r)
+        jobs[nj++] = RowJob{s.X.as<z>() + (size_t)r * s.dim, s.Rr.as<z>() + (size_t)r * s.dim, nullptr,
+                            s.theta[r], s.dim, (long)(s.off_n / sizeof(double)) + r};
     }
-    if (rmax < op.r_tol && dw < op.w_tol) break;
-    // correction vectors
-    int nnew = 0;
-    for (int r = 0; r < k; ++r) {
-      if (rn[r] < op.r_tol) continue;
-      hipLaunchKernelGGL(k_precond, dim3(nblk(dim)), dim3(TPB), 0, ctx->stream, Rb.as<z>() + (size_t)r * dim,
-                         Db.as<z>() + (size_t)nnew * dim, diag.as<z>(), w[sel[r]], dim);
-      ++nnew;
+    arena.run(g, tl);
+    mir.up(off_jobs, sizeof(RowJob) * nj);
+    if (nj) {
+      hipLaunchKernelGGL(k_resid_norm, dim3((unsigned)nj), dim3(TPB), 0, ctx->stream, mir.dev<RowJob>(off_jobs),
+                         mir.dev<double>(0));
+      FC_HIP(hipGetLastError());
     }
-    if (nnew == 0) break;
-    // collapse onto the lowest Ritz vectors when the subspace would overflow
-    if (m + nnew > maxsub) {
-      int keep = std::min(m, 2 * k);
+    mir.down(rg_n, rg_n_end - rg_n);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    // (4) convergence, restarts and the correction vectors
+    nj = 0;
+    std::vector<Inst*> restart;
+    for (Inst& s : in) {
+      if (!s.active) continue;
+      s.iters = it;
+      const double* nh = mir.host<double>(s.off_n);
+      s.rn.assign(s.k, 0.0);
+      double rmax = 0;
+      for (int r = 0; r < s.k; ++r) {
+        s.rn[r] = std::sqrt(std::max(0.0, nh[r]));
+        rmax = std::max(rmax, s.rn[r]);
+      }
+      double dw = INFINITY;
+      if (!s.theta_old.empty()) {
+        dw = 0;
+        for (int r = 0; r < s.k; ++r)
+          dw = std::max(dw, std::hypot(s.theta[r].x - s.theta_old[r].x, s.theta[r].y - s.theta_old[r].y));
+      }
+      s.theta_old = s.theta;
+      if (ctx->verbose)
+        fprintf(stderr, "[davidson] it %d m %d rmax %.3e dw %.3e w0 %.10f\n", it, s.m, rmax, dw, s.theta[0].x);
+      if (rmax < op.r_tol && dw < op.w_tol) { s.active = false; continue; }
+      s.roots.clear();
+      for (int r = 0; r < s.k; ++r)
+        if (s.rn[r] >= op.r_tol) s.roots.push_back(r);
+      s.nnew = (int)s.roots.size();
+      if (s.nnew == 0) { s.active = false; continue; }
+      for (int j = 0; j < s.nnew; ++j)
+        jobs[nj++] = RowJob{s.Rr.as<z>() + (size_t)s.roots[j] * s.dim, s.D.as<z>() + (size_t)j * s.dim,
+                            s.diag.as<z>(), s.theta[s.roots[j]], s.dim, 0};
+      if (s.m + s.nnew > s.maxsub) restart.push_back(&s);
+    }
+    if (nj) {
+      // the previous job table has been read: the norms above were synchronised after it
+      mir.up(off_jobs, sizeof(RowJob) * nj);
+      hipLaunchKernelGGL(k_precond_rows, dim3(64, (unsigned)nj), dim3(TPB), 0, ctx->stream,
+                         mir.dev<RowJob>(off_jobs));
+      FC_HIP(hipGetLastError());
+    }
+    // (5) restart: collapse V and S onto the lowest Ritz vectors (orthonormalised combinations),
+    // leaving room for this iteration's correction vectors
+    for (Inst* sp : restart) {
+      Inst& s = *sp;
+      const int keep = std::min({s.m, 2 * s.k, s.maxsub - s.nnew});
       std::vector<int> sel2;
-      lowest_by_real(w, keep, sel2);
-      // orthonormalise the coefficient columns (V orthonormal => Ritz combinations orthonormal)
+      lowest_by_real(s.w, keep, sel2);
       std::vector<std::vector<std::complex<double>>> cols;
       for (int c = 0; c < keep; ++c) {
-        std::vector<std::complex<double>> col(m);
-        for (int p = 0; p < m; ++p) col[p] = {Y[p * (size_t)m + sel2[c]].x, Y[p * (size_t)m + sel2[c]].y};
+        std::vector<std::complex<double>> col(s.m);
+        for (int p = 0; p < s.m; ++p) col[p] = {s.Y[(size_t)p * s.m + sel2[c]].x, s.Y[(size_t)p * s.m + sel2[c]].y};
         for (int pass = 0; pass < 2; ++pass)
           for (auto& q : cols) {
             std::complex<double> d = 0;
-            for (int p = 0; p < m; ++p) d += std::conj(q[p]) * col[p];
-            for (int p = 0; p < m; ++p) col[p] -= d * q[p];
+            for (int p = 0; p < s.m; ++p) d += std::conj(q[p]) * col[p];
+            for (int p = 0; p < s.m; ++p) col[p] -= d * q[p];
           }
         double nr = 0;
         for (auto& x : col) nr += std::norm(x);
@@ -340,50 +505,150 @@ int davidson_one(fc_ctx ctx, fc_ints I, fc_amps T, int k, const fc_eom_opts& op,
         for (auto& x : col) x /= nr;
         cols.push_back(col);
       }
-      int nk2 = (int)cols.size();
-      std::vector<z> Yc(m * (size_t)nk2);
-      for (int p = 0; p < m; ++p)
-        for (int c = 0; c < nk2; ++c) Yc[p * (size_t)nk2 + c] = make_double2(cols[c][p].real(), cols[c][p].imag());
-      DBuf Ycd(ctx, sizeof(z) * m * nk2), Vn(ctx, sizeof(z) * (size_t)nk2 * dim), Sn(ctx, sizeof(z) * (size_t)nk2 * dim);
-      FC_HIP(hipMemcpyAsync(Ycd.p, Yc.data(), sizeof(z) * m * nk2, hipMemcpyHostToDevice, ctx->stream));
-      zgemm(ctx, 'T', 'N', nk2, dim, m, one, Ycd.as<z>(), nk2, V, dim, zero, Vn.as<z>(), dim);
-      zgemm(ctx, 'T', 'N', nk2, dim, m, one, Ycd.as<z>(), nk2, S, dim, zero, Sn.as<z>(), dim);
-      FC_HIP(hipMemcpyAsync(V, Vn.p, sizeof(z) * nk2 * dim, hipMemcpyDeviceToDevice, ctx->stream));
-      FC_HIP(hipMemcpyAsync(S, Sn.p, sizeof(z) * nk2 * dim, hipMemcpyDeviceToDevice, ctx->stream));
-      m = nk2;
+      const int nk2 = (int)cols.size();
+      std::vector<z> Yc((size_t)s.m * nk2);
+      for (int p = 0; p < s.m; ++p)
+        for (int c = 0; c < nk2; ++c) Yc[(size_t)p * nk2 + c] = make_double2(cols[c][p].real(), cols[c][p].imag());
+      DBuf Ycd(ctx, sizeof(z) * s.m * nk2), Vn(ctx, sizeof(z) * (size_t)nk2 * s.dim),
+          Sn(ctx, sizeof(z) * (size_t)nk2 * s.dim);
+      FC_HIP(hipMemcpyAsync(Ycd.p, Yc.data(), sizeof(z) * s.m * nk2, hipMemcpyHostToDevice, ctx->stream));
+      zgemm(ctx, 'T', 'N', nk2, s.dim, s.m, one, Ycd.as<z>(), nk2, s.V.as<z>(), s.dim, zero, Vn.as<z>(), s.dim);
+      zgemm(ctx, 'T', 'N', nk2, s.dim, s.m, one, Ycd.as<z>(), nk2, s.S.as<z>(), s.dim, zero, Sn.as<z>(), s.dim);
+      FC_HIP(hipMemcpyAsync(s.V.p, Vn.p, sizeof(z) * nk2 * s.dim, hipMemcpyDeviceToDevice, ctx->stream));
+      FC_HIP(hipMemcpyAsync(s.S.p, Sn.p, sizeof(z) * nk2 * s.dim, hipMemcpyDeviceToDevice, ctx->stream));
+      FC_HIP(hipStreamSynchronize(ctx->stream));
+      s.m = nk2;
+      s.gold = 0;   // recompute the (small) subspace matrix from the collapsed vectors
     }
-    // orthogonalise the new block against V twice (classical Gram-Schmidt via GEMM), then among itself
-    z* Dn = Db.as<z>();
-    for (int pass = 0; pass < 2; ++pass) {
-      zgemm(ctx, 'R', 'T', m, nnew, dim, one, V, dim, Dn, dim, zero, Cd.as<z>(), nnew);
-      zgemm(ctx, 'T', 'N', nnew, dim, m, mone, Cd.as<z>(), nnew, V, dim, one, Dn, dim);
+    // (6) orthonormalise the correction vectors: project out V twice, then a Gram-matrix
+    // (Loewdin) step; a second round when that Gram matrix was badly conditioned
+    std::vector<Inst*> work;
+    for (Inst& s : in) {
+      s.added = 0;
+      if (s.active && s.nnew > 0) work.push_back(&s);
     }
-    int added = 0;
-    for (int j = 0; j < nnew; ++j) {
-      z* x = Dn + (size_t)j * dim;
-      for (int pass = 0; pass < 2; ++pass)
-        for (int q = 0; q < added; ++q) {
-          z* y = V + (size_t)(m + q) * dim;
-          z d = dotc(ctx, dim, y, x);
-          axpy(ctx, dim, make_double2(-d.x, -d.y), y, x);
+    std::vector<z*> src(nb, nullptr);
+    for (Inst* sp : work) src[sp - in.data()] = sp->D.as<z>();
+    for (int round = 0; round < 2 && !work.empty(); ++round) {
+      for (int pass = 0; pass < 2; ++pass) {
+        g.clear();
+        for (Inst* sp : work) {
+          Inst& s = *sp;
+          GroupGemm p;
+          p.opA = 'R'; p.opB = 'T'; p.M = s.m; p.N = s.nnew; p.K = s.dim;
+          p.A = s.V.as<z>(); p.lda = s.dim; p.B = src[sp - in.data()]; p.ldb = s.dim;
+          p.C = mir.dev<z>(s.off_c); p.ldc = s.nnew;
+          g.push_back(p);
         }
-      z nn = dotc(ctx, dim, x, x);
-      double nr = std::sqrt(std::max(0.0, nn.x));
-      if (nr < 1e-10) continue;
-      z* dst = V + (size_t)(m + added) * dim;
-      FC_HIP(hipMemcpyAsync(dst, x, sizeof(z) * dim, hipMemcpyDeviceToDevice, ctx->stream));
-      scale(ctx, dst, dim, make_double2(1.0 / nr, 0));
-      ++added;
+        arena.run(g, tl);
+        g.clear();
+        for (Inst* sp : work) {
+          Inst& s = *sp;
+          GroupGemm p;
+          p.opA = 'T'; p.M = s.nnew; p.N = s.dim; p.K = s.m; p.alpha = mone;
+          p.A = mir.dev<z>(s.off_c); p.lda = s.nnew; p.B = s.V.as<z>(); p.ldb = s.dim;
+          p.beta = one; p.C = src[sp - in.data()]; p.ldc = s.dim;
+          g.push_back(p);
+        }
+        arena.run(g, tl);
+      }
+      g.clear();
+      for (Inst* sp : work) {
+        Inst& s = *sp;
+        GroupGemm p;
+        p.opA = 'R'; p.opB = 'T'; p.M = s.nnew; p.N = s.nnew; p.K = s.dim;
+        p.A = src[sp - in.data()]; p.lda = s.dim; p.B = src[sp - in.data()]; p.ldb = s.dim;
+        p.C = mir.dev<z>(s.off_gram); p.ldc = s.nnew;
+        g.push_back(p);
+      }
+      arena.run(g, tl);
+      mir.down(rg_n_end, rg_gram_end - rg_n_end);
+      FC_HIP(hipStreamSynchronize(ctx->stream));
+      std::vector<Inst*> again;
+      g.clear();
+      for (Inst* sp : work) {
+        Inst& s = *sp;
+        const int n = s.nnew;
+        const z* gh = mir.host<z>(s.off_gram);
+        // drop vectors that vanished under the projection, scale the rest to unit norm
+        std::vector<double> sc(n, 0.0);
+        for (int j = 0; j < n; ++j) {
+          const double d = gh[(size_t)j * n + j].x;
+          sc[j] = d > 1e-20 ? 1.0 / std::sqrt(d) : 0.0;
+        }
+        std::vector<z> A((size_t)n * n);
+        for (int j = 0; j < n; ++j)
+          for (int l = 0; l < n; ++l) {
+            const z u = gh[(size_t)j * n + l];
+            A[(size_t)j * n + l] = make_double2(u.x * sc[j] * sc[l], u.y * sc[j] * sc[l]);
+          }
+        std::vector<double> lam;
+        herm_eig(n, A, lam);
+        std::vector<int> kept;
+        for (int c = n - 1; c >= 0; --c)
+          if (lam[c] > 1e-8) kept.push_back(c);
+        const int na = (int)kept.size();
+        if (na == 0) continue;
+        z* cc = mir.host<z>(s.off_cc);
+        double lmin = INFINITY;
+        for (int c = 0; c < na; ++c) {
+          const double f = 1.0 / std::sqrt(lam[kept[c]]);
+          lmin = std::min(lmin, lam[kept[c]]);
+          for (int j = 0; j < n; ++j) {
+            const z u = A[(size_t)j * n + kept[c]];
+            cc[(size_t)j * na + c] = make_double2(u.x * sc[j] * f, u.y * sc[j] * f);
+          }
+        }
+        const bool redo = round == 0 && lmin < 1e-3;
+        z* dst = redo ? s.D2.as<z>() : s.V.as<z>() + (size_t)s.m * s.dim;
+        GroupGemm p;
+        p.opA = 'T'; p.M = na; p.N = s.dim; p.K = n;
+        p.A = mir.dev<z>(s.off_cc); p.lda = na; p.B = src[sp - in.data()]; p.ldb = s.dim;
+        p.C = dst; p.ldc = s.dim;
+        g.push_back(p);
+        if (redo) {
+          src[sp - in.data()] = dst;
+          s.nnew = na;
+          again.push_back(sp);
+        } else {
+          s.added = na;
+        }
+      }
+      mir.up(rg_cc, rg_cc_end - rg_cc);
+      arena.run(g, tl);
+      work.swap(again);
     }
-    if (added == 0) break;
-    sigma_dev(ctx, I, T, added, V + (size_t)m * dim, S + (size_t)m * dim);
-    m += added;
+    // (7) sigma of every new trial vector, all instances in one graph replay
+    bool anyadd = false;
+    for (int b = 0; b < nb; ++b) {
+      Inst& s = in[b];
+      nv[b] = 0;
+      if (!s.active) continue;
+      if (s.added == 0) { s.active = false; continue; }
+      nv[b] = s.added;
+      Rp[b] = s.V.as<z>() + (size_t)s.m * s.dim;
+      Sp[b] = s.S.as<z>() + (size_t)s.m * s.dim;
+      anyadd = true;
+    }
+    if (anyadd) sb.run(Rp.data(), Sp.data(), nv.data());
+    for (Inst& s : in)
+      if (s.active) s.m += s.added;
   }
-  for (int r = 0; r < k; ++r) omega[r] = theta_old[r];
-  if (Rout) FC_HIP(hipMemcpyAsync(Rout, Xb.p, sizeof(z) * (size_t)k * dim, hipMemcpyDeviceToDevice, ctx->stream));
+  int status = FC_OK;
+  long off = 0, roff = 0;
+  for (int b = 0; b < nb; ++b) {
+    Inst& s = in[b];
+    if (s.active) { s.status = FC_ENOCONV; s.iters = op.max_iter; }
+    for (int r = 0; r < s.k; ++r) omega[off + r] = s.theta_old.empty() ? zero : s.theta_old[r];
+    if (Rout) FC_HIP(hipMemcpyAsync(Rout + roff, s.X.p, sizeof(z) * (size_t)s.k * s.dim, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    if (iters) iters[b] = s.iters;
+    off += s.k;
+    roff += (long)s.k * s.dim;
+    if (s.status != FC_OK) status = s.status;
+  }
   FC_HIP(hipStreamSynchronize(ctx->stream));
-  if (iters) *iters = std::min(it, op.max_iter);
-  return it > op.max_iter ? FC_ENOCONV : FC_OK;
+  return status;
 }
 
 }  // namespace fc

@@ -49,33 +49,44 @@ __device__ inline long xcd_tile(long bid, long tiles) {
   return (bid & 7) * per + (bid >> 3);
 }
 
+template <int BM, int BN>
+struct TileSmem {
+  double Ar[2][BK][BM + PAD], Ai[2][BK][BM + PAD];
+  double Br[2][BK][BN + PAD], Bi[2][BK][BN + PAD];
+};
+
+// One output tile [m0, m0 + BM) x [n0, n0 + BN) of one product over the K range [klo, khi).
+struct TileJob {
+  long M, N;
+  const z* A; long lda;
+  const z* B; long ldb;
+  z* C; long ldc;
+  z alpha, beta;
+  int conjA, conjB;
+  long m0, n0, klo, khi;
+  z* part;        // split-K: raw sums over this K range as [M][N] (nullptr: write C)
+  long lv, lnB;   // ladder epilogue (EPI == 1)
+};
+
+// Computes one tile with the whole workgroup.  The LDS buffers are free again on return.
 template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
+__device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN>& sm) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
   constexpr int FI = WTM / 16, FJ = WTN / 16;             // MFMA tiles per wave
   constexpr int LA = BM * BK / NT, LB = BN * BK / NT;     // staged complex elements per thread
-  __shared__ double sAr[2][BK][BM + PAD], sAi[2][BK][BM + PAD];
-  __shared__ double sBr[2][BK][BN + PAD], sBi[2][BK][BN + PAD];
-
-  const long tile = xcd_tile(blockIdx.x, g.tiles);   // the grid is padded to a multiple of 8
-  if (tile >= g.tiles) return;
+  auto& sAr = sm.Ar;
+  auto& sAi = sm.Ai;
+  auto& sBr = sm.Br;
+  auto& sBi = sm.Bi;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / WGN) * WTM, wn = (wave % WGN) * WTN;
-  const long ntn = (g.N + BN - 1) / BN;
-  const long m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
-  if (EPI == 1 && g.ltri) {
-    // diagonal ab block: skip tiles whose smallest a exceeds their largest b
-    const long amin = m0 / g.lv, bmax = (n0 + BN - 1 < g.N ? n0 + BN - 1 : g.N - 1) / g.lv;
-    if (amin > bmax) return;
-  }
-  const z* __restrict__ A = g.A + (long)blockIdx.z * g.sA;
-  const z* __restrict__ B = g.B + (long)blockIdx.z * g.sB;
-  z* __restrict__ C = g.C + (long)blockIdx.z * g.sC;
+  const long m0 = g.m0, n0 = g.n0, klo = g.klo, khi = g.khi;
+  const z* __restrict__ A = g.A;
+  const z* __restrict__ B = g.B;
+  z* __restrict__ C = g.C;
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
-  const long klo = (long)blockIdx.y * g.kchunk;
-  const long khi = klo + g.kchunk < g.K ? klo + g.kchunk : g.K;
 
   z ra[LA], rb[LB];
 #define FC_LOAD_TILE(k0)                                                                 \
@@ -174,7 +185,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
         if (m >= g.M || n >= g.N) continue;
         const double re = cr[i][j][r], im = ci[i][j][r];
         if (g.part) {  // split-K: raw partial sums, reduced in a fixed order afterwards
-          g.part[((long)blockIdx.y * g.M + m) * g.N + n] = make_double2(re, im);
+          g.part[m * g.N + n] = make_double2(re, im);
           continue;
         }
         long off;
@@ -192,6 +203,33 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
         }
         C[off] = out;
       }
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
+  __shared__ TileSmem<BM, BN> sm;
+  const long tile = xcd_tile(blockIdx.x, g.tiles);   // the grid is padded to a multiple of 8
+  if (tile >= g.tiles) return;
+  const long ntn = (g.N + BN - 1) / BN;
+  const long m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+  if (EPI == 1 && g.ltri) {
+    // diagonal ab block: skip tiles whose smallest a exceeds their largest b
+    const long amin = m0 / g.lv, bmax = (n0 + BN - 1 < g.N ? n0 + BN - 1 : g.N - 1) / g.lv;
+    if (amin > bmax) return;
+  }
+  TileJob j;
+  j.M = g.M; j.N = g.N;
+  j.A = g.A + (long)blockIdx.z * g.sA; j.lda = g.lda;
+  j.B = g.B + (long)blockIdx.z * g.sB; j.ldb = g.ldb;
+  j.C = g.C + (long)blockIdx.z * g.sC; j.ldc = g.ldc;
+  j.alpha = g.alpha; j.beta = g.beta;
+  j.conjA = g.conjA; j.conjB = g.conjB;
+  j.m0 = m0; j.n0 = n0;
+  j.klo = (long)blockIdx.y * g.kchunk;
+  j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
+  j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
+  j.lv = g.lv; j.lnB = g.lnB;
+  gemm_tile<BM, BN, WGM, WGN, TA, TB, EPI>(j, sm);
 }
 
 // C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic)
@@ -353,7 +391,217 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
     FC_HIP(hipGetLastError());
   }
 }
+
+// ------------------------------------------------------------------------------------------------
+// Grouped products: one persistent launch walks the output tiles of many independent products
+// (different shapes, operands and layouts) listed in a device-resident plan.  The plan is read at
+// run time, so a captured graph replays with whatever products the plan holds at that moment.
+struct GroupHeader {
+  long nprob, total_tiles, total_elems, pad;
+};
+struct GroupDesc {
+  long M, N, K;
+  const z* A; long lda, sA;
+  const z* B; long ldb, sB;
+  z* C; long ldc, sC;
+  z alpha, beta;
+  int ta, tb, conjA, conjB;
+  long batch, ksplit, kchunk, tn, tiles;   // tiles: output tiles of one (split, batch) slice
+  long tile0, elem0;                       // first global tile, first reduced element
+  z* part;                                 // split-K partials [ksplit][batch][M][N]
+};
+constexpr size_t PLAN_HDR = 64;
+
+// index of the last entry whose key field is <= x (keys non-decreasing; the entry holding x)
+template <long GroupDesc::*F>
+__device__ inline long group_find(const GroupDesc* d, long np, long x) {
+  long lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const long mid = (lo + hi + 1) >> 1;
+    if (d[mid].*F <= x) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int BM, int BN, int WGM, int WGN>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm(const char* __restrict__ plan) {
+  __shared__ TileSmem<BM, BN> sm;
+  const GroupHeader* h = reinterpret_cast<const GroupHeader*>(plan);
+  const GroupDesc* d = reinterpret_cast<const GroupDesc*>(plan + PLAN_HDR);
+  const long total = h->total_tiles, np = h->nprob;
+  const long span = (total + 7) / 8 * 8;
+  // the grid is a multiple of 8, so virtual tile vt runs on XCD vt % 8 and each XCD walks a
+  // contiguous band of tiles
+  for (long vt = blockIdx.x; vt < span; vt += gridDim.x) {
+    const long t = xcd_tile(vt, total);
+    if (t >= total) continue;
+    const GroupDesc g = d[group_find<&GroupDesc::tile0>(d, np, t)];
+    const long loc = t - g.tile0;
+    const long tt = loc % g.tiles, r = loc / g.tiles;
+    const long b = r % g.batch, s = r / g.batch;
+    TileJob j;
+    j.M = g.M; j.N = g.N;
+    j.A = g.A + b * g.sA; j.lda = g.lda;
+    j.B = g.B + b * g.sB; j.ldb = g.ldb;
+    j.C = g.C + b * g.sC; j.ldc = g.ldc;
+    j.alpha = g.alpha; j.beta = g.beta;
+    j.conjA = g.conjA; j.conjB = g.conjB;
+    j.m0 = (tt / g.tn) * BM; j.n0 = (tt % g.tn) * BN;
+    j.klo = s * g.kchunk;
+    j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
+    j.part = g.ksplit > 1 ? g.part + (s * g.batch + b) * g.M * g.N : nullptr;
+    j.lv = 1; j.lnB = 1;
+    if (g.ta) {
+      if (g.tb) gemm_tile<BM, BN, WGM, WGN, true, true, 0>(j, sm);
+      else gemm_tile<BM, BN, WGM, WGN, true, false, 0>(j, sm);
+    } else {
+      if (g.tb) gemm_tile<BM, BN, WGM, WGN, false, true, 0>(j, sm);
+      else gemm_tile<BM, BN, WGM, WGN, false, false, 0>(j, sm);
+    }
+  }
+}
+
+// C = alpha * sum_s part[s] + beta * C for every split product of the plan, in split order.
+__global__ void k_group_reduce(const char* __restrict__ plan) {
+  const GroupHeader* h = reinterpret_cast<const GroupHeader*>(plan);
+  const GroupDesc* d = reinterpret_cast<const GroupDesc*>(plan + PLAN_HDR);
+  const long total = h->total_elems, np = h->nprob;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    const GroupDesc& g = d[group_find<&GroupDesc::elem0>(d, np, e)];
+    const long MN = g.M * g.N, loc = e - g.elem0;
+    const long b = loc / MN, mn = loc % MN, m = mn / g.N, n = mn % g.N;
+    double re = 0, im = 0;
+    for (long s = 0; s < g.ksplit; ++s) {
+      const z p = g.part[(s * g.batch + b) * MN + mn];
+      re += p.x; im += p.y;
+    }
+    z out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+    z* c = g.C + b * g.sC + m * g.ldc + n;
+    if (g.beta.x != 0.0 || g.beta.y != 0.0) {
+      const z c0 = *c;
+      out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+      out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+    }
+    *c = out;
+  }
+}
 }  // namespace
+
+constexpr int GROUP_NCFG = 2;
+constexpr long GROUP_BM[GROUP_NCFG] = {64, 128}, GROUP_BN[GROUP_NCFG] = {64, 64};
+
+GroupCounts group_encode(const std::vector<GroupGemm>& probs, const GroupTiling& tl, void* host_plan,
+                         size_t plan_cap, z* work, size_t work_cap) {
+  FC_REQUIRE(tl.cfg >= 0 && tl.cfg < GROUP_NCFG, FC_EARG, "grouped gemm: bad tile configuration");
+  FC_REQUIRE(tl.kchunk >= BK, FC_EARG, "grouped gemm: K chunk below one K slice");
+  const long bm = GROUP_BM[tl.cfg], bn = GROUP_BN[tl.cfg];
+  GroupCounts c;
+  c.plan_bytes = PLAN_HDR + sizeof(GroupDesc) * probs.size();
+  GroupDesc* d = host_plan ? reinterpret_cast<GroupDesc*>((char*)host_plan + PLAN_HDR) : nullptr;
+  if (host_plan) FC_REQUIRE(c.plan_bytes <= plan_cap, FC_EARG, "grouped gemm: plan buffer too small");
+  for (size_t i = 0; i < probs.size(); ++i) {
+    const GroupGemm& p = probs[i];
+    FC_REQUIRE(strchr("NTCR", p.opA) && strchr("NTCR", p.opB), FC_EARG, "grouped gemm: bad op");
+    FC_REQUIRE(p.M >= 0 && p.N >= 0 && p.K >= 0 && p.batch >= 0, FC_EARG, "grouped gemm: negative size");
+    GroupDesc g{};
+    g.M = p.M; g.N = p.N; g.K = p.K;
+    g.A = p.A; g.lda = p.lda; g.sA = p.sA;
+    g.B = p.B; g.ldb = p.ldb; g.sB = p.sB;
+    g.C = p.C; g.ldc = p.ldc; g.sC = p.sC;
+    g.alpha = p.alpha; g.beta = p.beta;
+    g.ta = (p.opA == 'T' || p.opA == 'C');
+    g.tb = (p.opB == 'T' || p.opB == 'C');
+    g.conjA = (p.opA == 'C' || p.opA == 'R');
+    g.conjB = (p.opB == 'C' || p.opB == 'R');
+    g.batch = p.batch;
+    const long tm = (p.M + bm - 1) / bm;
+    g.tn = std::max(1L, (p.N + bn - 1) / bn);
+    g.tiles = std::max(1L, tm * ((p.N + bn - 1) / bn));
+    if (p.K > tl.kchunk) {
+      const long ks = (p.K + tl.kchunk - 1) / tl.kchunk;
+      g.kchunk = ((p.K + ks - 1) / ks + BK - 1) / BK * BK;
+      g.ksplit = (p.K + g.kchunk - 1) / g.kchunk;
+    } else {
+      g.kchunk = std::max<long>(p.K, 1);
+      g.ksplit = 1;
+    }
+    const bool empty = p.M == 0 || p.N == 0 || p.batch == 0;
+    g.tile0 = c.tiles;
+    g.elem0 = c.elems;
+    g.part = nullptr;
+    if (!empty) {
+      c.tiles += g.ksplit * g.batch * g.tiles;
+      if (g.ksplit > 1) {
+        g.part = work ? work + c.work : nullptr;
+        c.work += (size_t)(g.ksplit * g.batch * p.M * p.N);
+        c.elems += g.batch * p.M * p.N;
+      }
+    } else {
+      g.batch = 1; g.ksplit = 1;   // never visited: no tiles, no reduced elements
+    }
+    if (d) d[i] = g;
+  }
+  if (host_plan) {
+    FC_REQUIRE(!work || c.work <= work_cap, FC_EARG, "grouped gemm: split-K workspace too small");
+    FC_REQUIRE(work || c.work == 0, FC_EARG, "grouped gemm: split-K workspace missing");
+    GroupHeader* h = reinterpret_cast<GroupHeader*>(host_plan);
+    h->nprob = (long)probs.size();
+    h->total_tiles = c.tiles;
+    h->total_elems = c.elems;
+    h->pad = 0;
+  }
+  return c;
+}
+
+void group_launch(fc_ctx ctx, int cfg, const void* dplan, long max_tiles, long max_elems) {
+  const char* p = static_cast<const char*>(dplan);
+  // persistent grid: at most 4 workgroups per CU of 256 CUs, a multiple of 8
+  const long g1 = std::max(8L, std::min(1024L, (max_tiles + 7) / 8 * 8));
+  if (cfg == 1) k_group_gemm<128, 64, 2, 2><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  else k_group_gemm<64, 64, 2, 2><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  FC_HIP(hipGetLastError());
+  if (max_elems > 0) {
+    const long g2 = std::max(1L, std::min(2048L, (max_elems + 255) / 256));
+    k_group_reduce<<<(unsigned)g2, 256, 0, ctx->stream>>>(p);
+    FC_HIP(hipGetLastError());
+  }
+}
+
+void group_gemm(fc_ctx ctx, const std::vector<GroupGemm>& probs, const GroupTiling& tl) {
+  if (probs.empty()) return;
+  const GroupCounts c = group_encode(probs, tl, nullptr, 0, nullptr, 0);
+  if (c.tiles == 0) return;
+  std::vector<char> host(c.plan_bytes);
+  DBuf work(ctx, sizeof(z) * c.work), dplan(ctx, c.plan_bytes);
+  group_encode(probs, tl, host.data(), host.size(), work.as<z>(), c.work);
+  FC_HIP(hipMemcpyAsync(dplan.p, host.data(), c.plan_bytes, hipMemcpyHostToDevice, ctx->stream));
+  group_launch(ctx, tl.cfg, dplan.p, c.tiles, c.elems);
+  // the host plan must outlive the copy
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+GroupArena::GroupArena(fc_ctx c, size_t plan_bytes, size_t work_elems)
+    : ctx(c), dev(c, plan_bytes), work(c, sizeof(z) * work_elems), cap(plan_bytes), wcap(work_elems) {
+  FC_HIP(hipHostMalloc((void**)&host, plan_bytes, hipHostMallocDefault));
+}
+
+GroupArena::~GroupArena() {
+  if (host) (void)hipHostFree(host);
+}
+
+void GroupArena::run(const std::vector<GroupGemm>& probs, const GroupTiling& tl) {
+  if (probs.empty()) return;
+  const GroupCounts c0 = group_encode(probs, tl, nullptr, 0, nullptr, 0);
+  if (c0.tiles == 0) return;
+  const size_t at = (off + 255) / 256 * 256;
+  FC_REQUIRE(at + c0.plan_bytes <= cap, FC_EARG, "grouped gemm: plan arena exhausted");
+  FC_REQUIRE(woff + c0.work <= wcap, FC_EARG, "grouped gemm: workspace arena exhausted");
+  group_encode(probs, tl, host + at, cap - at, work.as<z>() + woff, wcap - woff);
+  FC_HIP(hipMemcpyAsync(dev.as<char>() + at, host + at, c0.plan_bytes, hipMemcpyHostToDevice, ctx->stream));
+  group_launch(ctx, tl.cfg, dev.as<char>() + at, c0.tiles, c0.elems);
+  off = at + c0.plan_bytes;
+  woff += c0.work;
+}
 
 void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B, long ldb,
            z beta, z* C, long ldc, int batch, long sA, long sB, long sC) {

@@ -23,11 +23,25 @@ struct HbarBlocks {
   bool ready = false;
 };
 
+// The sigma products rewritten as matrices over the packed 1h + 2h1p layout (r_i, then r_ij^a for
+// i < j with a fastest), formed once from the H-bar blocks.  p = (i, j) and q = (m, n) run over
+// occupied pairs with first < second, in lexicographic order.
+struct SigmaOps {
+  fc::ZTensor B1;    // [dim][o]: sigma_i = sum_x R[x] B1[x][i]  (F_mi, F_me and W_mnie terms)
+  fc::ZTensor Xop;   // [(q, f)][e] = <mn||ef>: X_e = sum R[(q, f)] Xop[(q, f)][e]
+  fc::ZTensor Wt;    // [(m, e)][(j, a)] = W_maej: the ring term over the unpacked r_im^e
+  fc::ZTensor Mp;    // [p][q]: W_mnij and the P(ij) F_mi term, both mixing occupied pairs only
+  fc::ZTensor B2;    // [o + v][(p, a)]: rows m: -W_maij; rows o + e: t_ij^ae
+  fc::DBuf pairs;    // int2 (i, j) of each pair index
+  bool ready = false;
+};
+
 struct fc_amps_s {
   fc_ctx ctx = nullptr;
   fc_ints ints = nullptr;
   fc::ZTensor t1, t2;   // [i][a], [i][j][a][b]
   HbarBlocks hb;
+  SigmaOps so;
 };
 
 namespace fc {

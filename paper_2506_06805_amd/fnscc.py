@@ -35,7 +35,7 @@ class CcsdOpts(C.Structure):
 
 class EomOpts(C.Structure):
     _fields_ = [("r_tol", C.c_double), ("w_tol", C.c_double), ("max_iter", C.c_int), ("max_subspace", C.c_int),
-                ("guess_per_root", C.c_int)]
+                ("guess_per_root", C.c_int), ("graph", C.c_int)]
 
 
 P = C.c_void_p
