@@ -125,6 +125,13 @@ int ccsd_residual(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, void
  * replaced by L_ae - sum_m t_m^a L_me on both factors. */
 int fc_ladder(fc_ctx ctx, fc_ints ints, const void* tau, const void* dress_t1, void* R,
               int precision);
+/* fc_zgemm - the library's complex FP64 matrix product on the matrix cores (every contraction of
+ * Eq. 12-18 and 23 reduces to it): C = alpha op(A) op(B) + beta C, row-major, device pointers to
+ * interleaved complex128. opA: 'N' A[m*lda+k], 'T' A[k*lda+m], 'C' conj(A[k*lda+m]),
+ * 'R' conj(A[m*lda+k]); opB: 'N' B[k*ldb+n], 'T' B[n*ldb+k], 'C' conj(B[n*ldb+k]),
+ * 'R' conj(B[k*ldb+n]). alpha, beta: host (re, im). Stream-ordered; returns before completion. */
+int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
+             long lda, const void* B, long ldb, const double* beta, void* C, long ldc);
 /* Amplitude handles: create from device arrays (copied), read back into device arrays. */
 int fc_amps_create(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, fc_amps* out);
 int fc_amps_read(fc_amps t, void* t1, void* t2);

@@ -7,6 +7,7 @@
 #include <memory>
 #include <sstream>
 
+#include "fc_gemm.hpp"
 #include "fc_state.hpp"
 
 namespace fc {
@@ -354,8 +355,13 @@ int fc_autotune_load(fc_ctx ctx, const char* path) {
   char key[128];
   int cfg;
   float ms;
-  while (fscanf(f, "%127s %d %f", key, &cfg, &ms) == 3)
-    if (cfg >= 0 && cfg < 3) ctx->tune[key] = {cfg, ms};
+  while (fscanf(f, "%127s %d %f", key, &cfg, &ms) == 3) {
+    // GEMM entries name a tile configuration; sigma entries pack (configuration, log2 K chunk)
+    const bool sigma = std::strncmp(key, "sigma_", 6) == 0;
+    const bool ok = sigma ? (cfg >> 5) >= 0 && (cfg >> 5) < 2 && (cfg & 31) >= 4 && (cfg & 31) <= 20
+                          : cfg >= 0 && cfg < gemm_num_configs();
+    if (ok) ctx->tune[key] = {cfg, ms};
+  }
   fclose(f);
   return FC_OK;
 }
@@ -460,6 +466,18 @@ int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, i
   if (!ctx || !I || !tau || !R) return FC_EARG;
   FC_TRY(ctx, {
     ladder_dev(ctx, I, (const z*)tau, (const z*)t1, (z*)R, precision < 0 ? I->precision : precision);
+    return FC_OK;
+  })
+}
+
+int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
+             long lda, const void* B, long ldb, const double* beta, void* C, long ldc) {
+  if (!ctx || !alpha || !beta || M < 0 || N < 0 || K < 0) return FC_EARG;
+  if (M == 0 || N == 0) return FC_OK;
+  if (!C || (K > 0 && (!A || !B))) return FC_EARG;
+  FC_TRY(ctx, {
+    zgemm(ctx, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B, ldb,
+          make_double2(beta[0], beta[1]), (z*)C, ldc);
     return FC_OK;
   })
 }

@@ -6,9 +6,10 @@
 // with their real and imaginary parts in separate planes, conjugation applied at staging time,
 // double-buffered so the next K slice loads while the current one feeds the matrix cores.
 //
-// Two tile shapes: 64 x 64 (4 waves of 32 x 32) for small products and 128 x 128 (8 waves of
-// 64 x 32) for large ones.  Workgroups are numbered so that each of the 8 XCDs walks a
-// contiguous band of output tiles (consecutive tiles share a row of A in that XCD's L2).
+// Tile shapes 64 x 64 (4 waves of 32 x 32), 128 x 64 (4 waves of 64 x 32) and 128 x 128 (8 waves
+// of 64 x 32), with K slices of 8 or 16 per pipeline step; a heuristic or the autotuner picks one
+// per product shape.  Workgroups are numbered so that each of the 8 XCDs walks a contiguous band
+// of output tiles (consecutive tiles share a row of A in that XCD's L2).
 //
 // MFMA f64 16x16x4 lane layout (lane l of a 64-wide wave):
 //   A fragment: A[row = l % 16][k = l / 16];  B fragment: B[k = l / 16][col = l % 16];
@@ -24,7 +25,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 8;      // K slice (complex elements)
+constexpr int KQ = 16;     // K chunks of split products are multiples of this (and of every K slice)
 constexpr int PAD = 16;    // LDS row padding (doubles): consecutive K rows land 32 banks apart
 
 struct GemmArgs {
@@ -34,7 +35,7 @@ struct GemmArgs {
   z* C; long ldc; long sC;
   z alpha, beta;
   int conjA, conjB;
-  long kchunk;        // K range per split (multiple of BK); blockIdx.y selects the split
+  long kchunk;        // K range per split (multiple of KQ); blockIdx.y selects the split
   z* part;            // split-K partial products [split][M][N] (nullptr: write C directly)
   long tiles;         // number of output tiles
   // ladder epilogue: C row m = (a - a0) v + e, column n = (b - b0) v + f is written to
@@ -49,7 +50,8 @@ __device__ inline long xcd_tile(long bid, long tiles) {
   return (bid & 7) * per + (bid >> 3);
 }
 
-template <int BM, int BN>
+// K slice BK (complex elements) staged per step, double-buffered
+template <int BM, int BN, int BK>
 struct TileSmem {
   double Ar[2][BK][BM + PAD], Ai[2][BK][BM + PAD];
   double Br[2][BK][BN + PAD], Bi[2][BK][BN + PAD];
@@ -69,8 +71,8 @@ struct TileJob {
 };
 
 // Computes one tile with the whole workgroup.  The LDS buffers are free again on return.
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI>
-__device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN>& sm) {
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI>
+__device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>& sm) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
   constexpr int FI = WTM / 16, FJ = WTN / 16;             // MFMA tiles per wave
@@ -205,13 +207,20 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN>& sm
       }
 }
 
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
-  __shared__ TileSmem<BM, BN> sm;
+  __shared__ TileSmem<BM, BN, BK> sm;
   const long tile = xcd_tile(blockIdx.x, g.tiles);   // the grid is padded to a multiple of 8
   if (tile >= g.tiles) return;
   const long ntn = (g.N + BN - 1) / BN;
-  const long m0 = (tile / ntn) * BM, n0 = (tile % ntn) * BN;
+  long mi = tile / ntn;
+  if (EPI == 1 && g.ltri) {
+    // triangular launches: fold the tile rows (0, tm-1, 1, tm-2, ...) so that every XCD's band
+    // mixes rows with many and with few live tiles
+    const long tm = g.tiles / ntn;
+    mi = (mi & 1) ? tm - 1 - (mi >> 1) : (mi >> 1);
+  }
+  const long m0 = mi * BM, n0 = (tile % ntn) * BN;
   if (EPI == 1 && g.ltri) {
     // diagonal ab block: skip tiles whose smallest a exceeds their largest b
     const long amin = m0 / g.lv, bmax = (n0 + BN - 1 < g.N ? n0 + BN - 1 : g.N - 1) / g.lv;
@@ -229,7 +238,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
   j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
   j.lv = g.lv; j.lnB = g.lnB;
-  gemm_tile<BM, BN, WGM, WGN, TA, TB, EPI>(j, sm);
+  gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI>(j, sm);
 }
 
 // C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic)
@@ -251,18 +260,31 @@ __global__ void k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N,
   }
 }
 
-template <int BM, int BN, int WGM, int WGN, int EPI>
+template <int BM, int BN, int WGM, int WGN, int BK, int EPI>
 void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
   constexpr int NT = WGM * WGN * 64;
-  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, false, false, EPI><<<grid, NT, 0, s>>>(g);
-  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, false, true, EPI><<<grid, NT, 0, s>>>(g);
-  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, true, false, EPI><<<grid, NT, 0, s>>>(g);
-  else zgemm_f64_kernel<BM, BN, WGM, WGN, true, true, EPI><<<grid, NT, 0, s>>>(g);
+  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, false, EPI><<<grid, NT, 0, s>>>(g);
+  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, true, EPI><<<grid, NT, 0, s>>>(g);
+  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, false, EPI><<<grid, NT, 0, s>>>(g);
+  else zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, true, EPI><<<grid, NT, 0, s>>>(g);
 }
 
-// Tile configurations: 0 = 64 x 64 (4 waves), 1 = 128 x 64 (4 waves), 2 = 128 x 128 (8 waves).
-constexpr int NCFG = 3;
-constexpr int CFG_BM[NCFG] = {64, 128, 128}, CFG_BN[NCFG] = {64, 64, 128};
+// Tile configurations: 64 x 64 (4 waves), 128 x 64 (4 waves) and 128 x 128 (8 waves), each with
+// K slices of 8 (configurations 0-2) or 16 (3-5) complex elements per pipeline step.
+constexpr int NCFG = 6;
+constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128}, CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128};
+
+template <int EPI>
+void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
+  switch (cfg) {
+    case 0: launch<64, 64, 2, 2, 8, EPI>(g, ta, tb, grid, s); break;
+    case 1: launch<128, 64, 2, 2, 8, EPI>(g, ta, tb, grid, s); break;
+    case 2: launch<128, 128, 2, 4, 8, EPI>(g, ta, tb, grid, s); break;
+    case 3: launch<64, 64, 2, 2, 16, EPI>(g, ta, tb, grid, s); break;
+    case 4: launch<128, 64, 2, 2, 16, EPI>(g, ta, tb, grid, s); break;
+    default: launch<128, 128, 2, 4, 16, EPI>(g, ta, tb, grid, s); break;
+  }
+}
 
 // Launch one configuration (split-K decided inside for configurations whose grid cannot fill the chip).
 void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
@@ -288,7 +310,13 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
   if (M <= 0 || N <= 0 || batch <= 0) return;
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   int cfg = heuristic_cfg(M, N, batch);
-  if (ctx->autotune && K > 0) {
+  static const int forced = [] {
+    const char* e = getenv("FNSCC_GEMM_CFG");   // tuning override: one configuration for every product
+    return e ? atoi(e) : -1;
+  }();
+  if (forced >= 0 && forced < NCFG && (CFG_BM[forced] == 64 || M >= 128) && (CFG_BN[forced] == 64 || N >= 128)) {
+    cfg = forced;
+  } else if (ctx->autotune && K > 0) {
     const std::string key = bucket(opA, opB, M, N, K, batch, lep);
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) {
@@ -356,16 +384,16 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   const long tiles = ((N + bn - 1) / bn) * ((M + bm - 1) / bm);
   FC_REQUIRE(tiles < (1L << 30), FC_EARG, "zgemm: problem too large for one launch");
   g.tiles = tiles;
-  // Split K when the tile grid cannot fill the chip (256 CUs): each split covers >= 8 BK steps,
+  // Split K when the tile grid cannot fill the chip (256 CUs): each split covers >= 4 KQ elements,
   // partials go to a workspace and are summed in split order, so results stay deterministic.
   long ksplit = 1;
   const long want = 1024;
-  if (!lep && batch == 1 && tiles < want && K >= 16 * BK) {
-    ksplit = std::min((want + tiles - 1) / tiles, K / (8 * BK));
+  if (!lep && batch == 1 && tiles < want && K >= 8 * KQ) {
+    ksplit = std::min((want + tiles - 1) / tiles, K / (4 * KQ));
     const long cap = std::max(1L, (256L << 20) / (long)(sizeof(z) * M * N));
     ksplit = std::max(1L, std::min({ksplit, cap, 4096L}));
   }
-  g.kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
+  g.kchunk = ((K + ksplit - 1) / ksplit + KQ - 1) / KQ * KQ;
   ksplit = (K + g.kchunk - 1) / g.kchunk;
   g.part = nullptr;
   DBuf work;
@@ -374,15 +402,8 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
     g.part = work.as<z>();
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit, (unsigned)batch);
-  if (lep) {
-    if (cfg == 2) launch<128, 128, 2, 4, 1>(g, ta, tb, grid, ctx->stream);
-    else if (cfg == 1) launch<128, 64, 2, 2, 1>(g, ta, tb, grid, ctx->stream);
-    else launch<64, 64, 2, 2, 1>(g, ta, tb, grid, ctx->stream);
-  } else {
-    if (cfg == 2) launch<128, 128, 2, 4, 0>(g, ta, tb, grid, ctx->stream);
-    else if (cfg == 1) launch<128, 64, 2, 2, 0>(g, ta, tb, grid, ctx->stream);
-    else launch<64, 64, 2, 2, 0>(g, ta, tb, grid, ctx->stream);
-  }
+  if (lep) launch_cfg<1>(cfg, g, ta, tb, grid, ctx->stream);
+  else launch_cfg<0>(cfg, g, ta, tb, grid, ctx->stream);
   FC_HIP(hipGetLastError());
   if (ksplit > 1) {
     const long MN = M * N;
@@ -423,9 +444,9 @@ __device__ inline long group_find(const GroupDesc* d, long np, long x) {
   return lo;
 }
 
-template <int BM, int BN, int WGM, int WGN>
+template <int BM, int BN, int WGM, int WGN, int BK>
 __global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm(const char* __restrict__ plan) {
-  __shared__ TileSmem<BM, BN> sm;
+  __shared__ TileSmem<BM, BN, BK> sm;
   const GroupHeader* h = reinterpret_cast<const GroupHeader*>(plan);
   const GroupDesc* d = reinterpret_cast<const GroupDesc*>(plan + PLAN_HDR);
   const long total = h->total_tiles, np = h->nprob;
@@ -452,11 +473,11 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm(const char* __res
     j.part = g.ksplit > 1 ? g.part + (s * g.batch + b) * g.M * g.N : nullptr;
     j.lv = 1; j.lnB = 1;
     if (g.ta) {
-      if (g.tb) gemm_tile<BM, BN, WGM, WGN, true, true, 0>(j, sm);
-      else gemm_tile<BM, BN, WGM, WGN, true, false, 0>(j, sm);
+      if (g.tb) gemm_tile<BM, BN, WGM, WGN, BK, true, true, 0>(j, sm);
+      else gemm_tile<BM, BN, WGM, WGN, BK, true, false, 0>(j, sm);
     } else {
-      if (g.tb) gemm_tile<BM, BN, WGM, WGN, false, true, 0>(j, sm);
-      else gemm_tile<BM, BN, WGM, WGN, false, false, 0>(j, sm);
+      if (g.tb) gemm_tile<BM, BN, WGM, WGN, BK, false, true, 0>(j, sm);
+      else gemm_tile<BM, BN, WGM, WGN, BK, false, false, 0>(j, sm);
     }
   }
 }
@@ -493,7 +514,7 @@ constexpr long GROUP_BM[GROUP_NCFG] = {64, 128}, GROUP_BN[GROUP_NCFG] = {64, 64}
 GroupCounts group_encode(const std::vector<GroupGemm>& probs, const GroupTiling& tl, void* host_plan,
                          size_t plan_cap, z* work, size_t work_cap) {
   FC_REQUIRE(tl.cfg >= 0 && tl.cfg < GROUP_NCFG, FC_EARG, "grouped gemm: bad tile configuration");
-  FC_REQUIRE(tl.kchunk >= BK, FC_EARG, "grouped gemm: K chunk below one K slice");
+  FC_REQUIRE(tl.kchunk >= KQ, FC_EARG, "grouped gemm: K chunk below one K slice");
   const long bm = GROUP_BM[tl.cfg], bn = GROUP_BN[tl.cfg];
   GroupCounts c;
   c.plan_bytes = PLAN_HDR + sizeof(GroupDesc) * probs.size();
@@ -519,7 +540,7 @@ GroupCounts group_encode(const std::vector<GroupGemm>& probs, const GroupTiling&
     g.tiles = std::max(1L, tm * ((p.N + bn - 1) / bn));
     if (p.K > tl.kchunk) {
       const long ks = (p.K + tl.kchunk - 1) / tl.kchunk;
-      g.kchunk = ((p.K + ks - 1) / ks + BK - 1) / BK * BK;
+      g.kchunk = ((p.K + ks - 1) / ks + KQ - 1) / KQ * KQ;
       g.ksplit = (p.K + g.kchunk - 1) / g.kchunk;
     } else {
       g.kchunk = std::max<long>(p.K, 1);
@@ -557,8 +578,8 @@ void group_launch(fc_ctx ctx, int cfg, const void* dplan, long max_tiles, long m
   const char* p = static_cast<const char*>(dplan);
   // persistent grid: at most 4 workgroups per CU of 256 CUs, a multiple of 8
   const long g1 = std::max(8L, std::min(1024L, (max_tiles + 7) / 8 * 8));
-  if (cfg == 1) k_group_gemm<128, 64, 2, 2><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
-  else k_group_gemm<64, 64, 2, 2><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  if (cfg == 1) k_group_gemm<128, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  else k_group_gemm<64, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
   FC_HIP(hipGetLastError());
   if (max_elems > 0) {
     const long g2 = std::max(1L, std::min(2048L, (max_elems + 255) / 256));
@@ -602,6 +623,8 @@ void GroupArena::run(const std::vector<GroupGemm>& probs, const GroupTiling& tl)
   off = at + c0.plan_bytes;
   woff += c0.work;
 }
+
+int gemm_num_configs() { return NCFG; }
 
 void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B, long ldb,
            z beta, z* C, long ldc, int batch, long sA, long sB, long sC) {

@@ -13,6 +13,9 @@ struct LadderEpilogue {
   int triangular = 0;
 };
 
+// Number of tile configurations the FP64 product kernels offer (autotuner table entries).
+int gemm_num_configs();
+
 // W = A B^T in the ladder layout, FP64 (A[m * lda + k], B[n * ldb + k]).
 void zgemm_ladder(fc_ctx ctx, long M, long N, long K, const z* A, long lda, const z* B, long ldb, z* W,
                   const LadderEpilogue& lep);

@@ -57,6 +57,8 @@ _sig = {
     "ccsd_solve": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(CcsdOpts), C.POINTER(P), P, P]),
     "ccsd_residual": (C.c_int, [P, P, P, P, P, P, C.c_int]),
     "fc_ladder": (C.c_int, [P, P, P, P, P, C.c_int]),
+    "fc_zgemm": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P, C.c_long,
+                           P, P, C.c_long]),
     "fc_amps_create": (C.c_int, [P, P, P, P, C.POINTER(P)]),
     "fc_amps_read": (C.c_int, [P, P, P]),
     "fc_free_amps": (None, [P]),
@@ -330,6 +332,21 @@ def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
     ctx.check(lib.fc_ladder(ctx.h, ints.h, _ptr(tau), _ptr(t1), _ptr(R), PRECISION.get(precision, precision)),
               "fc_ladder")
     return R
+
+
+def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None):
+    """C = alpha op(A) op(B) + beta C on the library's FP64 complex GEMM (2-D contiguous tensors)."""
+    torch = ctx.torch
+    tA, tB = opA in "TC", opB in "TC"
+    M, K = (A.shape[1], A.shape[0]) if tA else (A.shape[0], A.shape[1])
+    N = B.shape[0] if tB else B.shape[1]
+    if C is None:
+        C = torch.zeros((M, N), dtype=torch.complex128, device=A.device)
+    al = np.array([complex(alpha).real, complex(alpha).imag])
+    be = np.array([complex(beta).real, complex(beta).imag])
+    ctx.check(lib.fc_zgemm(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
+                           _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1]), "fc_zgemm")
+    return C
 
 
 def amps_create(ctx: Context, ints: Ints, t1, t2):

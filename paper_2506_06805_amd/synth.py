@@ -136,12 +136,24 @@ WORKLOADS = {
 }
 
 
+# uneven batches solved together: instance shapes drawn by batch_shapes(count, seed)
+BATCHES = {
+    "batch64": dict(count=64, roots=6, seed=4000),
+}
+
+
 def batch_shapes(count: int, seed: int):
     """Uneven batch: o ~ U{6..24}, v ~ U{30..200}, N = 4 v (inclusive ranges)."""
     rng = np.random.default_rng(seed)
     os_ = rng.integers(6, 25, count)
     vs = rng.integers(30, 201, count)
     return [(int(o), int(v), int(4 * v)) for o, v in zip(os_, vs)]
+
+
+def make_batch(count: int, seed: int, dtype=np.complex64):
+    """The instances of an uneven batch, each with the coupling rule's kappa for its shape."""
+    return [make_instance(o, v, N, seed=seed + 1 + i, kappa=kappa_for(v, N), dtype=dtype)
+            for i, (o, v, N) in enumerate(batch_shapes(count, seed))]
 
 
 def make_ao_eri(nao: int, rank: int, seed: int) -> np.ndarray:
