@@ -40,8 +40,10 @@ enum { FC_OK = 0, FC_EARG = 1, FC_EHIP = 2, FC_ENOMEM = 3, FC_ENOCONV = 4, FC_EN
 enum { FC_C128 = 0, FC_C64 = 1 };
 /* Precision of the ladder and of the Cholesky assembly GEMMs. FC_FP64: FP64 MFMA throughout.
  * FC_SPLIT_BF16 / FC_SPLIT_FP16: each FP64 operand is split into a hi and a lo part of the
- * 16-bit type, the three products hi*hi + hi*lo + lo*hi run on MFMA with FP32 accumulation. */
-enum { FC_FP64 = 0, FC_SPLIT_BF16 = 1, FC_SPLIT_FP16 = 2 };
+ * 16-bit type, the three products hi*hi + hi*lo + lo*hi run on MFMA with FP32 accumulation; all
+ * other products of the CCSD residual then run in FP32 arithmetic (FP64 storage).
+ * FC_FP32 is accepted by fc_zgemm only: FP32 arithmetic on FP64 operands and result. */
+enum { FC_FP64 = 0, FC_SPLIT_BF16 = 1, FC_SPLIT_FP16 = 2, FC_FP32 = 3 };
 
 /* Create a context on `device`, ordering all work on `hip_stream` (a hipStream_t; NULL = the
  * default stream). alloc/release may be NULL (then hipMalloc/hipFree are used). */
@@ -129,9 +131,10 @@ int fc_ladder(fc_ctx ctx, fc_ints ints, const void* tau, const void* dress_t1, v
  * Eq. 12-18 and 23 reduces to it): C = alpha op(A) op(B) + beta C, row-major, device pointers to
  * interleaved complex128. opA: 'N' A[m*lda+k], 'T' A[k*lda+m], 'C' conj(A[k*lda+m]),
  * 'R' conj(A[m*lda+k]); opB: 'N' B[k*ldb+n], 'T' B[n*ldb+k], 'C' conj(B[n*ldb+k]),
- * 'R' conj(B[k*ldb+n]). alpha, beta: host (re, im). Stream-ordered; returns before completion. */
+ * 'R' conj(B[k*ldb+n]). alpha, beta: host (re, im). precision: FC_FP64 or FC_FP32 (FP32 products
+ * and sums). Stream-ordered; returns before completion. */
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
-             long lda, const void* B, long ldb, const double* beta, void* C, long ldc);
+             long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision);
 /* Amplitude handles: create from device arrays (copied), read back into device arrays. */
 int fc_amps_create(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, fc_amps* out);
 int fc_amps_read(fc_amps t, void* t1, void* t2);

@@ -471,11 +471,13 @@ int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, i
 }
 
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
-             long lda, const void* B, long ldb, const double* beta, void* C, long ldc) {
+             long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision) {
   if (!ctx || !alpha || !beta || M < 0 || N < 0 || K < 0) return FC_EARG;
+  if (precision != FC_FP64 && precision != FC_FP32) return FC_EARG;
   if (M == 0 || N == 0) return FC_OK;
   if (!C || (K > 0 && (!A || !B))) return FC_EARG;
   FC_TRY(ctx, {
+    Fp32Gemms fp32(ctx, precision == FC_FP32);
     zgemm(ctx, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B, ldb,
           make_double2(beta[0], beta[1]), (z*)C, ldc);
     return FC_OK;

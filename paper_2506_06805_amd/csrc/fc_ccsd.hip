@@ -97,6 +97,8 @@ z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
 
 void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p, z* r2p, int precision, z* fdiag) {
   StageTimer st(ctx, "residual");
+  // mixed precision: every product outside the ladder's split kernels in FP32 arithmetic
+  Fp32Gemms fp32(ctx, precision != FC_FP64);
   const long o = I->o, v = I->v, N = I->ncd;
   const z one = make_double2(1, 0), zero = make_double2(0, 0), half = make_double2(0.5, 0),
           mone = make_double2(-1, 0), mhalf = make_double2(-0.5, 0), quarter = make_double2(0.25, 0);

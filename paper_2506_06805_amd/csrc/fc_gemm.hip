@@ -24,6 +24,26 @@ namespace fc {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Matrix-core arithmetic of a tile: FP64 (v_mfma_f64_16x16x4f64) or FP32 (v_mfma_f32_16x16x4f32),
+// both 16 x 16 x 4 with one element of each operand per lane.  row(lk, r): output row of
+// accumulator register r in lane group lk = lane / 16 (column = lane % 16).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  using acc = d4;
+  static __device__ __forceinline__ acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+  using acc = f4;
+  static __device__ __forceinline__ acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
 
 constexpr int KQ = 16;     // K chunks of split products are multiples of this (and of every K slice)
 constexpr int PAD = 16;    // LDS row padding (doubles): consecutive K rows land 32 banks apart
@@ -50,11 +70,11 @@ __device__ inline long xcd_tile(long bid, long tiles) {
   return (bid & 7) * per + (bid >> 3);
 }
 
-// K slice BK (complex elements) staged per step, double-buffered
-template <int BM, int BN, int BK>
+// K slice BK (complex elements) staged per step in the arithmetic type T, double-buffered
+template <int BM, int BN, int BK, typename T = double>
 struct TileSmem {
-  double Ar[2][BK][BM + PAD], Ai[2][BK][BM + PAD];
-  double Br[2][BK][BN + PAD], Bi[2][BK][BN + PAD];
+  T Ar[2][BK][BM + PAD], Ai[2][BK][BM + PAD];
+  T Br[2][BK][BN + PAD], Bi[2][BK][BN + PAD];
 };
 
 // One output tile [m0, m0 + BM) x [n0, n0 + BN) of one product over the K range [klo, khi).
@@ -70,9 +90,10 @@ struct TileJob {
   long lv, lnB;   // ladder epilogue (EPI == 1)
 };
 
-// Computes one tile with the whole workgroup.  The LDS buffers are free again on return.
-template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI>
-__device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>& sm) {
+// Computes one tile with the whole workgroup, operands rounded to T at staging, products and
+// sums in T, the result written in FP64.  The LDS buffers are free again on return.
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T = double>
+__device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK, T>& sm) {
   constexpr int NT = WGM * WGN * 64;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
   constexpr int FI = WTM / 16, FJ = WTN / 16;             // MFMA tiles per wave
@@ -115,22 +136,23 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>
     _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
       int e = tid + NT * r, mm, kk;                                                      \
       if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }           \
-      sAr[buf][kk][mm] = ra[r].x;                                                        \
-      sAi[buf][kk][mm] = sa * ra[r].y;                                                   \
+      sAr[buf][kk][mm] = (T)ra[r].x;                                                     \
+      sAi[buf][kk][mm] = (T)(sa * ra[r].y);                                              \
     }                                                                                    \
     _Pragma("unroll") for (int r = 0; r < LB; ++r) {                                     \
       int e = tid + NT * r, nn, kk;                                                      \
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }           \
-      sBr[buf][kk][nn] = rb[r].x;                                                        \
-      sBi[buf][kk][nn] = sb * rb[r].y;                                                   \
+      sBr[buf][kk][nn] = (T)rb[r].x;                                                     \
+      sBi[buf][kk][nn] = (T)(sb * rb[r].y);                                              \
     }                                                                                    \
   } while (0)
 
-  d4 cr[FI][FJ], ci[FI][FJ];
+  using Acc = typename Mfma<T>::acc;
+  Acc cr[FI][FJ], ci[FI][FJ];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < FJ; ++j) { cr[i][j] = d4{0, 0, 0, 0}; ci[i][j] = d4{0, 0, 0, 0}; }
+    for (int j = 0; j < FJ; ++j) { cr[i][j] = Acc{0, 0, 0, 0}; ci[i][j] = Acc{0, 0, 0, 0}; }
 
   const long nk = (khi - klo + BK - 1) / BK;
   FC_LOAD_TILE(klo);
@@ -142,7 +164,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>
     if (kt + 1 < nk) FC_LOAD_TILE(klo + (kt + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
-      double ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];
+      T ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];
 #pragma unroll
       for (int i = 0; i < FI; ++i) {
         ar[i] = sAr[buf][ks + lk][wm + 16 * i + lr];
@@ -158,15 +180,15 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>
       for (int i = 0; i < FI; ++i)
 #pragma unroll
         for (int j = 0; j < FJ; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
+          ci[i][j] = Mfma<T>::mac(ar[i], bi[j], ci[i][j]);
         }
 #pragma unroll
       for (int i = 0; i < FI; ++i)
 #pragma unroll
         for (int j = 0; j < FJ; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = Mfma<T>::mac(nai[i], bi[j], cr[i][j]);
+          ci[i][j] = Mfma<T>::mac(ai[i], br[j], ci[i][j]);
         }
     }
     if (kt + 1 < nk) FC_STORE_TILE(buf ^ 1);
@@ -182,10 +204,10 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>
     for (int j = 0; j < FJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const long m = m0 + wm + 16 * i + lk + 4 * r;
+        const long m = m0 + wm + 16 * i + Mfma<T>::row(lk, r);
         const long n = n0 + wn + 16 * j + lr;
         if (m >= g.M || n >= g.N) continue;
-        const double re = cr[i][j][r], im = ci[i][j][r];
+        const double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
         if (g.part) {  // split-K: raw partial sums, reduced in a fixed order afterwards
           g.part[m * g.N + n] = make_double2(re, im);
           continue;
@@ -207,9 +229,9 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK>
       }
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T>
 __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
-  __shared__ TileSmem<BM, BN, BK> sm;
+  __shared__ TileSmem<BM, BN, BK, T> sm;
   const long tile = xcd_tile(blockIdx.x, g.tiles);   // the grid is padded to a multiple of 8
   if (tile >= g.tiles) return;
   const long ntn = (g.N + BN - 1) / BN;
@@ -238,7 +260,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
   j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
   j.lv = g.lv; j.lnB = g.lnB;
-  gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI>(j, sm);
+  gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
 }
 
 // C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic)
@@ -260,13 +282,13 @@ __global__ void k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N,
   }
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK, int EPI>
+template <int BM, int BN, int WGM, int WGN, int BK, int EPI, typename T>
 void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
   constexpr int NT = WGM * WGN * 64;
-  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, false, EPI><<<grid, NT, 0, s>>>(g);
-  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, true, EPI><<<grid, NT, 0, s>>>(g);
-  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, false, EPI><<<grid, NT, 0, s>>>(g);
-  else zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, true, EPI><<<grid, NT, 0, s>>>(g);
+  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, false, EPI, T><<<grid, NT, 0, s>>>(g);
+  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, true, EPI, T><<<grid, NT, 0, s>>>(g);
+  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, false, EPI, T><<<grid, NT, 0, s>>>(g);
+  else zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, true, EPI, T><<<grid, NT, 0, s>>>(g);
 }
 
 // Tile configurations: 64 x 64 (4 waves), 128 x 64 (4 waves) and 128 x 128 (8 waves), each with
@@ -274,15 +296,15 @@ void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
 constexpr int NCFG = 6;
 constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128}, CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128};
 
-template <int EPI>
+template <int EPI, typename T>
 void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
   switch (cfg) {
-    case 0: launch<64, 64, 2, 2, 8, EPI>(g, ta, tb, grid, s); break;
-    case 1: launch<128, 64, 2, 2, 8, EPI>(g, ta, tb, grid, s); break;
-    case 2: launch<128, 128, 2, 4, 8, EPI>(g, ta, tb, grid, s); break;
-    case 3: launch<64, 64, 2, 2, 16, EPI>(g, ta, tb, grid, s); break;
-    case 4: launch<128, 64, 2, 2, 16, EPI>(g, ta, tb, grid, s); break;
-    default: launch<128, 128, 2, 4, 16, EPI>(g, ta, tb, grid, s); break;
+    case 0: launch<64, 64, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
+    case 1: launch<128, 64, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
+    case 2: launch<128, 128, 2, 4, 8, EPI, T>(g, ta, tb, grid, s); break;
+    case 3: launch<64, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s); break;
+    case 4: launch<128, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s); break;
+    default: launch<128, 128, 2, 4, 16, EPI, T>(g, ta, tb, grid, s); break;
   }
 }
 
@@ -292,11 +314,11 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
                const LadderEpilogue* lep);
 
 // Shape bucket: operand layouts, sizes rounded to powers of two, batching and epilogue kind.
-std::string bucket(char opA, char opB, long M, long N, long K, int batch, const LadderEpilogue* lep) {
+std::string bucket(char opA, char opB, long M, long N, long K, int batch, const LadderEpilogue* lep, int fp32) {
   auto lg = [](long x) { int b = 0; while ((1L << b) < x) ++b; return b; };
   char buf[96];
-  snprintf(buf, sizeof(buf), "%c%c_m%d_n%d_k%d_b%d_e%d", opA, opB, lg(M), lg(N), lg(K), batch > 1,
-           lep ? 1 + lep->triangular : 0);
+  snprintf(buf, sizeof(buf), "%c%c_m%d_n%d_k%d_b%d_e%d%s", opA, opB, lg(M), lg(N), lg(K), batch > 1,
+           lep ? 1 + lep->triangular : 0, fp32 ? "_s" : "");
   return buf;
 }
 
@@ -317,7 +339,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
   if (forced >= 0 && forced < NCFG && (CFG_BM[forced] == 64 || M >= 128) && (CFG_BN[forced] == 64 || N >= 128)) {
     cfg = forced;
   } else if (ctx->autotune && K > 0) {
-    const std::string key = bucket(opA, opB, M, N, K, batch, lep);
+    const std::string key = bucket(opA, opB, M, N, K, batch, lep, lep ? 0 : ctx->gemm_fp32);
     auto it = ctx->tune.find(key);
     if (it != ctx->tune.end()) {
       cfg = it->second.first;
@@ -402,8 +424,9 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
     g.part = work.as<z>();
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit, (unsigned)batch);
-  if (lep) launch_cfg<1>(cfg, g, ta, tb, grid, ctx->stream);
-  else launch_cfg<0>(cfg, g, ta, tb, grid, ctx->stream);
+  if (lep) launch_cfg<1, double>(cfg, g, ta, tb, grid, ctx->stream);
+  else if (ctx->gemm_fp32) launch_cfg<0, float>(cfg, g, ta, tb, grid, ctx->stream);
+  else launch_cfg<0, double>(cfg, g, ta, tb, grid, ctx->stream);
   FC_HIP(hipGetLastError());
   if (ksplit > 1) {
     const long MN = M * N;

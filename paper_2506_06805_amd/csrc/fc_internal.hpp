@@ -55,6 +55,9 @@ struct fc_ctx_s {
   std::map<std::string, long> stage_calls;
   // hipEvents bracketing ladder launches (measured on this context's stream)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ladder_events;
+  // while set, zgemm products run on the FP32 matrix cores (operands rounded to FP32 at staging,
+  // FP32 sums, FP64 result); the particle-particle ladder's own products are not affected
+  int gemm_fp32 = 0;
   // GEMM autotuning: shape bucket -> chosen configuration (and its measured time in ms)
   int autotune = 0;
   std::map<std::string, std::pair<int, float>> tune;
@@ -140,6 +143,16 @@ void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha
 // Dot products with FP64 accumulation in a fixed order (deterministic).
 z dotu(fc_ctx ctx, long n, const z* x, const z* y);    // sum x*y
 z dotc(fc_ctx ctx, long n, const z* x, const z* y);    // sum conj(x)*y
+
+// Scope in which zgemm runs in FP32 arithmetic (the mixed-precision residual).
+struct Fp32Gemms {
+  fc_ctx ctx;
+  int saved;
+  Fp32Gemms(fc_ctx c, bool on) : ctx(c), saved(c->gemm_fp32) { c->gemm_fp32 = on ? 1 : 0; }
+  ~Fp32Gemms() { ctx->gemm_fp32 = saved; }
+  Fp32Gemms(const Fp32Gemms&) = delete;
+  Fp32Gemms& operator=(const Fp32Gemms&) = delete;
+};
 
 // Timing helper: adds elapsed stream time of a scope to ctx->stage_ms[name] when enabled.
 struct StageTimer {

@@ -114,7 +114,13 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   const long per = (g.tiles + 7) / 8;
   const long tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= g.tiles) return;
-  const long m0 = (tile / ntn) * TM, n0 = (tile % ntn) * TN;
+  long mi = tile / ntn;
+  if (EPI == 1 && g.ltri) {
+    // triangular launches: fold the tile rows so every XCD's band mixes live and skipped tiles
+    const long tm = g.tiles / ntn;
+    mi = (mi & 1) ? tm - 1 - (mi >> 1) : (mi >> 1);
+  }
+  const long m0 = mi * TM, n0 = (tile % ntn) * TN;
   if (EPI == 1 && g.ltri) {
     const long amin = m0 / g.lv, bmax = (n0 + TN - 1 < g.N ? n0 + TN - 1 : g.N - 1) / g.lv;
     if (amin > bmax) return;

@@ -19,7 +19,7 @@ lib = C.CDLL(str(_LIB_PATH))
 
 FC_OK, FC_EARG, FC_EHIP, FC_ENOMEM, FC_ENOCONV, FC_ENUMERIC, FC_EUNSUPPORTED = range(7)
 FC_C128, FC_C64 = 0, 1
-FC_FP64, FC_SPLIT_BF16, FC_SPLIT_FP16 = 0, 1, 2
+FC_FP64, FC_SPLIT_BF16, FC_SPLIT_FP16, FC_FP32 = 0, 1, 2, 3
 PRECISION = {"fp64": FC_FP64, "split-bf16": FC_SPLIT_BF16, "split-fp16": FC_SPLIT_FP16}
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -58,7 +58,7 @@ _sig = {
     "ccsd_residual": (C.c_int, [P, P, P, P, P, P, C.c_int]),
     "fc_ladder": (C.c_int, [P, P, P, P, P, C.c_int]),
     "fc_zgemm": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P, C.c_long,
-                           P, P, C.c_long]),
+                           P, P, C.c_long, C.c_int]),
     "fc_amps_create": (C.c_int, [P, P, P, P, C.POINTER(P)]),
     "fc_amps_read": (C.c_int, [P, P, P]),
     "fc_free_amps": (None, [P]),
@@ -334,8 +334,9 @@ def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
     return R
 
 
-def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None):
-    """C = alpha op(A) op(B) + beta C on the library's FP64 complex GEMM (2-D contiguous tensors)."""
+def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False):
+    """C = alpha op(A) op(B) + beta C on the library's complex GEMM (2-D contiguous tensors);
+    FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True."""
     torch = ctx.torch
     tA, tB = opA in "TC", opB in "TC"
     M, K = (A.shape[1], A.shape[0]) if tA else (A.shape[0], A.shape[1])
@@ -345,7 +346,8 @@ def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None):
     al = np.array([complex(alpha).real, complex(alpha).imag])
     be = np.array([complex(beta).real, complex(beta).imag])
     ctx.check(lib.fc_zgemm(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
-                           _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1]), "fc_zgemm")
+                           _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1], FC_FP32 if fp32 else FC_FP64),
+              "fc_zgemm")
     return C
 
 

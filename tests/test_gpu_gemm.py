@@ -43,3 +43,21 @@ def test_zgemm_deterministic(gpu_ctx):
     c1 = fnscc.zgemm(gpu_ctx, "N", "N", A, B).cpu().numpy()
     c2 = fnscc.zgemm(gpu_ctx, "N", "N", A, B).cpu().numpy()
     assert np.array_equal(c1, c2)
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 133, 37), (3, 200, 5000), (256, 256, 513)])
+def test_zgemm_fp32_arithmetic(gpu_ctx, M, N, K):
+    # FP32 products and sums on FP64 data: error of order 2^-24 sqrt(K) of sum |a||b|
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(K)
+    for opA, opB in (("N", "N"), ("T", "C"), ("R", "T"), ("C", "N")):
+        A = _rand((K, M) if opA in "TC" else (M, K), rng)
+        B = _rand((N, K) if opB in "TC" else (K, N), rng)
+        ref = _op(A, opA) @ _op(B, opB)
+        scale = np.abs(_op(A, opA)) @ np.abs(_op(B, opB))
+        C = fnscc.zgemm(gpu_ctx, opA, opB, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), fp32=True)
+        err = (np.abs(C.cpu().numpy() - ref) / scale).max()
+        assert err < 4 * 2.0 ** -24 * np.sqrt(K), (opA, opB, err)
+        # and it is not FP64 arithmetic in disguise
+        assert err > 2.0 ** -40

@@ -64,6 +64,23 @@ def test_split_assembly_integrals(gpu_ctx, prec):
 
 
 @pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
+def test_mixed_residual_error(gpu_ctx, prec):
+    # split ladder + FP32 arithmetic for every other product of the residual
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 6, 40, 50
+    inst = synth.make_instance(o, v, N, seed=61, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    rng = np.random.default_rng(4)
+    t1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * 0.02
+    t2 = _tau(o, v, 5) * 0.5
+    w1, w2 = ccsd.residuals(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    r1, r2 = fnscc.ccsd_residual(gpu_ctx, ints, _dev(t1), _dev(t2), precision=prec)
+    for a, b in ((r1, w1), (r2, w2)):
+        rel = np.abs(a.cpu().numpy() - b).max() / np.abs(b).max()
+        assert rel < LADDER_TOL[prec], rel
+
+
+@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
 def test_mixed_solve_ip_error(gpu_ctx, prec):
     from paper_2506_06805_amd import fnscc
     o, v, N, k = 8, 32, 120, 4
