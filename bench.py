@@ -31,19 +31,20 @@ def ladder_flops(o, v, N):
     return 4.0 * N * v ** 3 * (v - 1) + o * (o - 1) * v ** 2 * (v - 1) ** 2
 
 
-def run_gpu(args, inst, wl):
+def run_gpu(args, inst, wl, precision, mlp=None, ctx=None):
     import torch
 
     from paper_2506_06805_amd import fnscc
 
     torch.cuda.set_device(0)
-    ctx = fnscc.Context(0)
+    ctx = ctx or fnscc.Context(0)
     L_dev = torch.from_numpy(inst.L).to("cuda")
     o, v, N, k = inst.o, inst.v, inst.ncd, wl["roots"]
+    extra = {"mlp": mlp} if mlp is not None else {}
 
     def step():
-        ints = fnscc.cd_integrals(ctx, inst.eps, L_dev, o, precision=args.precision)
-        e, it, amps = fnscc.ccsd_solve(ctx, ints, precision=args.precision)
+        ints = fnscc.cd_integrals(ctx, inst.eps, L_dev, o, precision=precision)
+        e, it, amps = fnscc.ccsd_solve(ctx, ints, precision=precision, **extra)
         w, its = fnscc.ipeom_davidson(ctx, ints, amps, k)
         return e, it, w, its
 
@@ -68,6 +69,22 @@ def run_gpu(args, inst, wl):
     e, it, w, its = out[-1]
     return dict(ms_per_step=ms_per_step, ladder_ms=lad_ms, ladder_calls=n_lad, e=e, iters=it, w=w,
                 eom_iters=its)
+
+
+def train_update_network(ctx, count=16, seed=7):
+    """The learned T2 update, trained on the GPU from plain-solver trajectories of small synthetic
+    instances (uneven-batch generator, o in 6..16, v in 30..80); returns (network, seconds, info)."""
+    import torch
+
+    from paper_2506_06805_amd import learn
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    data = learn.collect(ctx, learn.training_instances(count, seed), per_iter=1024, seed=seed)
+    net, hist = learn.train(ctx, data, epochs=12, batch=2048, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    return net, time.perf_counter() - t0, {"instances": count, "samples": int(data[0].shape[0]),
+                                           "epochs": 12, "loss_first": hist[0], "loss_last": hist[-1]}
 
 
 def run_ladder_only(args, inst):
@@ -220,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ladder-only", action="store_true",
                     help="time ladder evaluations alone (profiling aid; not the time-to-IPs metric)")
+    ap.add_argument("--no-compare", dest="compare", action="store_false",
+                    help="skip the split-BF16 and split-BF16 + learned runs on the same instance")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune GEMM tiles during the warmup steps (cached for the timed steps)")
     args = ap.parse_args()
@@ -278,7 +297,10 @@ def main():
                           "frac": achieved / PEAK[args.precision],
                           "config": {"workload": f"ladder o={o} v={v} N_CD={N}"}}), flush=True)
         return
-    r = run_gpu(args, inst, wl)
+    from paper_2506_06805_amd import fnscc
+
+    ctx = fnscc.Context(0)
+    r = run_gpu(args, inst, wl, args.precision, ctx=ctx)
     achieved = F / (r["ladder_ms"] * 1e-3) / 1e12 if r["ladder_ms"] > 0 else 0.0
     peak = PEAK[args.precision]
     dim = o + o * (o - 1) // 2 * v
@@ -304,6 +326,25 @@ def main():
         "result": {"e_corr": [r["e"].real, r["e"].imag], "ccsd_iters": r["iters"], "eom_iters": r["eom_iters"],
                    "ips": [float(x) for x in np.real(r["w"])]},
     }
+    if args.compare and args.precision == "fp64":
+        # the same instance through the split-BF16 path, then with the learned update on top
+        w64 = np.sort_complex(np.asarray(r["w"]))
+        cmp = {}
+        net, t_train, info = train_update_network(ctx)
+        for name, mlp in (("split-bf16", None), ("split-bf16+learned", net)):
+            rm = run_gpu(args, inst, wl, "split-bf16", mlp=mlp, ctx=ctx)
+            wm = np.sort_complex(np.asarray(rm["w"]))
+            lad = F / (rm["ladder_ms"] * 1e-3) / 1e12 if rm["ladder_ms"] > 0 else 0.0
+            cmp[name] = {"time_to_ips_s": rm["ms_per_step"] / 1000.0,
+                         "speedup_vs_fp64": r["ms_per_step"] / rm["ms_per_step"],
+                         "max_abs_dIP_vs_fp64": float(np.abs(wm - w64).max()),
+                         "abs_dE_vs_fp64": float(abs(rm["e"] - r["e"])),
+                         "ccsd_iters": rm["iters"],
+                         "ladder_tflops": lad, "ladder_frac_of_bf16_peak": lad / PEAK["split-bf16"],
+                         "ladder_ms": rm["ladder_ms"]}
+        cmp["split-bf16+learned"]["training_s"] = t_train
+        cmp["split-bf16+learned"]["training"] = info
+        line["compare"] = cmp
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, wl, r["iters"])
     print(json.dumps(line), flush=True)

@@ -75,8 +75,12 @@ def ladder(g: Blocks, t1, t2, rows=None):
     return out
 
 
-def residuals(g: Blocks, eps, t1, t2):
-    """Omega1 = RHS1 - D1 t1 and Omega2 = RHS2 - D2 t2 (Stanton-Gauss form)."""
+def residuals(g: Blocks, eps, t1, t2, rows=None):
+    """Omega1 = RHS1 - D1 t1 and Omega2 = RHS2 - D2 t2 (Stanton-Gauss form).
+
+    With `rows` (values of the virtual index a) the ladder is evaluated for those rows only, so
+    Omega2[:, :, a, :] is exact for a in rows and incomplete elsewhere (a sampled check at sizes
+    where the full ladder loop is too slow)."""
     o = g.o
     d1, d2 = denominators(eps, o)
     Fae, Fmi, Fme, Wmnij, Wmbej = intermediates(g, t1, t2)
@@ -92,7 +96,7 @@ def residuals(g: Blocks, eps, t1, t2):
     x = ein("imab,mj->ijab", t2, Fmi + 0.5 * ein("je,me->mj", t1, Fme))
     r2 -= x - x.transpose(1, 0, 2, 3)
     r2 += 0.5 * ein("mnab,mnij->ijab", tau, Wmnij)
-    r2 += ladder(g, t1, t2)
+    r2 += ladder(g, t1, t2, rows=rows)
     x = ein("imae,mbej->ijab", t2, Wmbej) - ein("ie,ma,mbej->ijab", t1, t1, g.ovvo)
     r2 += x - x.transpose(1, 0, 2, 3) - x.transpose(0, 1, 3, 2) + x.transpose(1, 0, 3, 2)
     x = ein("ie,abej->ijab", t1, g.vvvo)

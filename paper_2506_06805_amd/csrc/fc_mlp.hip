@@ -195,26 +195,84 @@ __global__ void k_samples(const z* __restrict__ t2, const z* __restrict__ r2, co
   }
 }
 
-// t2_new = t2 + (r2 / D)(1 + g(x)) with BF16 weights in LDS (FP32 arithmetic)
+// tanh through one exponential: 1 - 2 / (exp(2x) + 1), exact limits +-1 for large |x|
+__device__ inline float tanh_exp(float x) { return 1.0f - 2.0f / (__expf(2.0f * x) + 1.0f); }
+
+// (i, j) of pair index p among the n(n-1)/2 pairs i < j in lexicographic order
+__device__ inline void pair_of_index(long p, long n, long& i, long& j) {
+  const double t = (double)(n * (n - 1) / 2 - 1 - p);
+  long k = (long)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);   // t = k(k+1)/2 + r, 0 <= r <= k
+  while ((k + 1) * (k + 2) / 2 <= (long)t) ++k;
+  while (k * (k + 1) / 2 > (long)t) --k;
+  i = n - 2 - k;
+  j = i + 1 + (p - (i * n - i * (i + 1) / 2));
+}
+
+// t2_new = t2 + (r2 / D)(1 + g(x)) with BF16-rounded weights in LDS and FP32 arithmetic; one
+// thread per unique amplitude (i < j, a < b), written to its four antisymmetric images.  The
+// first hidden layer stays in registers; the second is folded into the output sums as it goes.
 __global__ __launch_bounds__(TPB) void k_learned_t2(const float* __restrict__ pbf, const z* __restrict__ t2,
                                                     const z* __restrict__ r2, const z* __restrict__ r2prev,
                                                     const double* __restrict__ eps,
                                                     const z* __restrict__ fd, long o, long v, z* __restrict__ out) {
-  __shared__ float P[NP];
+  __shared__ __attribute__((aligned(16))) float P[NP];
   for (long k = threadIdx.x; k < NP; k += blockDim.x) P[k] = pbf[k];
   __syncthreads();
-  GRID_STRIDE(x, o * o * v * v) {
-    const long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
-    if (i == j || a == b) { out[x] = make_double2(0, 0); continue; }
+  const long no = o * (o - 1) / 2, nv = v * (v - 1) / 2;
+  GRID_STRIDE(u, no * nv) {
+    long i, j, a, b;
+    pair_of_index(u / nv, o, i, j);
+    pair_of_index(u % nv, v, a, b);
+    const long x = ((i * o + j) * v + a) * v + b;
     const double D = eps[i] + eps[j] - eps[o + a] - eps[o + b];
     const double fr = fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x;
     const double fi = fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y;
-    float xin[NIN], h1[NH], h2[NH], y[NOUT];
+    float xin[NIN];
     features(D, fr, fi, r2, r2prev, x, xin);
-    mlp_forward(P, xin, h1, h2, y);
+    float h1[NH];
+#pragma unroll
+    for (int p = 0; p < NH; ++p) {
+      float s = P[OB1 + p];
+#pragma unroll
+      for (int q = 0; q < NIN; ++q) s += P[OW1 + p * NIN + q] * xin[q];
+      h1[p] = tanh_exp(s);
+    }
+    float y0 = P[OB3], y1 = P[OB3 + 1];
+#pragma unroll 2
+    for (int p = 0; p < NH; ++p) {
+      const float4* w = reinterpret_cast<const float4*>(P + OW2 + p * NH);
+      float s = P[OB2 + p];
+#pragma unroll
+      for (int q = 0; q < NH / 4; ++q) {
+        const float4 c = w[q];
+        s += c.x * h1[4 * q] + c.y * h1[4 * q + 1] + c.z * h1[4 * q + 2] + c.w * h1[4 * q + 3];
+      }
+      const float h = tanh_exp(s);
+      y0 += P[OW3 + p] * h;
+      y1 += P[OW3 + NH + p] * h;
+    }
     const double qr = r2[x].x / D, qi = r2[x].y / D;
-    const double gr = 1.0 + (double)y[0], gi = (double)y[1];
-    out[x] = make_double2(t2[x].x + qr * gr - qi * gi, t2[x].y + qr * gi + qi * gr);
+    const double gr = 1.0 + (double)y0, gi = (double)y1;
+    const z n = make_double2(t2[x].x + qr * gr - qi * gi, t2[x].y + qr * gi + qi * gr);
+    const z m = make_double2(-n.x, -n.y);
+    out[x] = n;
+    out[((j * o + i) * v + a) * v + b] = m;
+    out[((i * o + j) * v + b) * v + a] = m;
+    out[((j * o + i) * v + b) * v + a] = n;
+  }
+}
+// zeros where i == j or a == b (never visited by k_learned_t2)
+__global__ void k_zero_diagonals(z* out, long o, long v) {
+  GRID_STRIDE(t, o * v * v + o * o * v) {
+    long x;
+    if (t < o * v * v) {
+      const long b = t % v, a = (t / v) % v, i = t / (v * v);
+      x = ((i * o + i) * v + a) * v + b;
+    } else {
+      const long s = t - o * v * v, a = s % v, j = (s / v) % o, i = s / (v * o);
+      x = ((i * o + j) * v + a) * v + a;
+    }
+    out[x] = make_double2(0.0, 0.0);
   }
 }
 __global__ void k_jacobi_t1(const z* t, const z* r, z* out, const double* eps, long o, long v) {
@@ -237,8 +295,11 @@ int learned_step(fc_ctx ctx, fc_ints I, const void* mlpv, const z* t1, const z* 
   check_mlp(m);
   const long o = I->o, v = I->v;
   k_jacobi_t1<<<nblk(o * v), TPB, 0, ctx->stream>>>(t1, r1, o1, I->eps_d.as<double>(), o, v);
-  k_learned_t2<<<nblk(o * o * v * v), TPB, 0, ctx->stream>>>(m->pbf.as<float>(), t2, r2, r2prev,
-                                                              I->eps_d.as<double>(), fd, o, v, o2);
+  k_zero_diagonals<<<nblk(o * v * v + o * o * v), TPB, 0, ctx->stream>>>(o2, o, v);
+  const long nu = (o * (o - 1) / 2) * (v * (v - 1) / 2);
+  if (nu > 0)
+    k_learned_t2<<<nblk(nu), TPB, 0, ctx->stream>>>(m->pbf.as<float>(), t2, r2, r2prev, I->eps_d.as<double>(), fd,
+                                                     o, v, o2);
   FC_HIP(hipGetLastError());
   return FC_OK;
 }

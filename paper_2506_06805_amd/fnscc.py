@@ -11,6 +11,9 @@ import pathlib
 import weakref
 
 import numpy as np
+# torch loads the HIP runtime first so that the library binds to the same one (loaded the other
+# way round, the library's first hipSetDevice fails)
+import torch  # noqa: F401
 
 _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libfnscc.so"
 if not _LIB_PATH.exists():
@@ -132,6 +135,7 @@ class Context:
 
         self.torch = torch
         self.device = device
+        torch.cuda.set_device(device)   # initialise the device in torch before the library uses it
         self.stream = stream or torch.cuda.current_stream(device)
         self._children = weakref.WeakSet()   # handles that must be freed before the context
         if use_torch_allocator:

@@ -225,3 +225,22 @@ def test_mlp_oracle_closed_forms():
     # finite differences of the bias are the analytic derivative of the quadratic
     fd = omlp.fd_grad(p, X, q, r, idx=[p.size - 2, p.size - 1])
     assert abs(fd[p.size - 2]) < 1e-8 and abs(fd[p.size - 1]) < 1e-8
+
+
+def test_sampled_residual_rows_match_full():
+    # the row-sampled residual used for full-size checks is the full one restricted to those rows
+    o, v, N = 3, 7, 11
+    inst = synth.make_instance(o, v, N, seed=91, kappa=0.6)
+    g = integrals.Blocks(inst.L, o)
+    rng = np.random.default_rng(2)
+    t1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * 0.05
+    t2 = (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v))) * 0.05
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    r1, r2 = ccsd.residuals(g, inst.eps, t1, t2)
+    rows = [1, 4, 6]
+    s1, s2 = ccsd.residuals(g, inst.eps, t1, t2, rows=rows)
+    assert np.array_equal(s1, r1)
+    assert np.allclose(s2[:, :, rows, :], r2[:, :, rows, :], rtol=0, atol=1e-14)
+    others = [a for a in range(v) if a not in rows]
+    assert not np.allclose(s2[:, :, others, :], r2[:, :, others, :])
