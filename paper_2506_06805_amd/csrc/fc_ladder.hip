@@ -119,13 +119,15 @@ __global__ void k_maxabs_slots(const float2* __restrict__ W, const int* __restri
 }
 
 // R[i,j,a,b] (and its three antisymmetric images) from Rp[pij][c], c indexing the valid pairs a < b
+// Rp is [pair][i<j]: the contraction runs with the long (a,b)-pair dimension as rows, so the
+// tiles that share a panel of Wp are neighbours on one XCD and Wp is read from HBM about once
 __global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, const int2* pairs,
                                  long npairs, const int2* po, long no) {
   GRID_STRIDE(t, no * npairs) {
     const long s = t % npairs, pi = t / npairs;
     const int2 ab = pairs[s];
     const int2 ij = po[pi];
-    const z r = Rp[t], m = make_double2(-r.x, -r.y);
+    const z r = Rp[s * no + pi], m = make_double2(-r.x, -r.y);
     const long i = ij.x, j = ij.y, a = ab.x, b = ab.y;
     R[((i * o + j) * v + a) * v + b] = r;
     R[((j * o + i) * v + a) * v + b] = m;
@@ -253,12 +255,13 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
         k_ladder_anti<double2, AntiOut<double2>><<<agrid, 256, 0, ctx->stream>>>(Wbuf.as<double2>(),
                                                                                  compact_d.as<int>(), v, nbv, out);
         FC_HIP(hipGetLastError());
-        zgemm(ctx, 'N', 'T', no, nvalid, nv, one, taup.as<z>(), nv, Wp64.as<z>(), nv, zero, Rp.as<z>(), nvalid);
+        zgemm(ctx, 'N', 'T', nvalid, no, nv, one, Wp64.as<z>(), nv, taup.as<z>(), nv, zero, Rp.as<z>(), no);
       } else {
         Wps.scale = 1.0;
         if (precision == FC_SPLIT_FP16) {
           FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned), ctx->stream));
-          k_maxabs_slots<<<nblk(ns * v * v), TPB, 0, ctx->stream>>>(Wbuf.as<float2>(), compact_d.as<int>(), ns, v * v,
+          // at most 2048 workgroups: one atomic per workgroup on a single word
+          k_maxabs_slots<<<std::min(2048u, nblk(ns * v * v)), TPB, 0, ctx->stream>>>(Wbuf.as<float2>(), compact_d.as<int>(), ns, v * v,
                                                                     mx.as<unsigned>());
           FC_HIP(hipGetLastError());
           unsigned hb = 0;
@@ -281,7 +284,7 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
               Wbuf.as<float2>(), compact_d.as<int>(), v, nbv, out);
         }
         FC_HIP(hipGetLastError());
-        gemm_split_nt(ctx, Ts, 0, no, Wps, 0, nvalid, one, zero, Rp.as<z>(), nvalid);
+        gemm_split_nt(ctx, Wps, 0, nvalid, Ts, 0, no, one, zero, Rp.as<z>(), no);
       }
       hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nvalid)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), R, o, v,
                          slots_d.as<int2>(), nvalid, po.as<int2>(), no);
