@@ -95,7 +95,9 @@ int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v
 typedef struct fc_mlp_s* fc_mlp;
 
 /* Options of ccsd_solve. Jacobi update t += Omega/D with complex DIIS (FP64). Converged when
- * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol. learned = 1 with mlp != NULL uses
+ * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol; e_tol, r_tol <= 0 (the defaults)
+ * select 1e-10 and 1e-9 for FC_FP64 and 1e-8 and 1e-7 for the split precisions, whose product
+ * errors move the IPs by ~1e-7 Eh anyway. learned = 1 with mlp != NULL uses
  * the learned T2 step (DIIS on top) until the residual fails to decrease for stall_window
  * iterations, then plain Jacobi + DIIS. t1_init/t2_init: device, full layout, or NULL for t = 0.
  * on_iter (may be NULL): called with the current iterate (device pointers, valid during the call)

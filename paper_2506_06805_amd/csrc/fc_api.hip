@@ -94,6 +94,10 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
   StageTimer st(ctx, "ccsd");
   const long o = I->o, v = I->v, n1 = o * v, n2 = o * o * v * v, nt = n1 + n2;
   const int prec = op.precision >= 0 ? op.precision : I->precision;
+  // tolerances <= 0 pick the precision's own: converging the residual far below the error of the
+  // split products only chases rounding noise
+  const double e_tol = op.e_tol > 0 ? op.e_tol : (prec == FC_FP64 ? 1e-10 : 1e-8);
+  const double r_tol = op.r_tol > 0 ? op.r_tol : (prec == FC_FP64 ? 1e-9 : 1e-7);
   ZTensor t(ctx, {nt}), tn(ctx, {nt}), r(ctx, {nt}), tx(ctx, {nt});
   if (op.t1_init && op.t2_init) {
     FC_HIP(hipMemcpyAsync(t.p(), op.t1_init, sizeof(z) * n1, hipMemcpyDeviceToDevice, ctx->stream));
@@ -166,7 +170,7 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
     const double de = std::hypot(e.x - e_old.x, e.y - e_old.y);
     if (ctx->verbose)
       fprintf(stderr, "[ccsd] it %3d E %.12f %+.2e dE %.2e rms %.2e %s\n", it, e.x, e.y, de, rms, learned ? "learned" : "jacobi");
-    if (de < op.e_tol && rms < op.r_tol) { status = FC_OK; break; }
+    if (de < e_tol && rms < r_tol) { status = FC_OK; break; }
     e_old = e;
   }
   *ecorr = e;
@@ -424,8 +428,8 @@ int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v
 void fc_ccsd_default_opts(fc_ccsd_opts* op) {
   if (!op) return;
   std::memset(op, 0, sizeof(*op));
-  op->e_tol = 1e-10;
-  op->r_tol = 1e-9;
+  op->e_tol = 0;   // 0: by precision (FP64 1e-10 / 1e-9, split 1e-8 / 1e-7)
+  op->r_tol = 0;
   op->max_iter = 200;
   op->diis_dim = 8;
   op->learned = 0;

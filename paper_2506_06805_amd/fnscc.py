@@ -294,6 +294,8 @@ def ccsd_opts(**kw):
                 op.learned = 1
         elif k == "on_iter":
             val = ON_ITER_FN(val)
+        elif k in ("t1_init", "t2_init"):   # contiguous device tensors (full layout) or None; the
+            val = _ptr(val)                    # caller keeps them alive during the solve
         setattr(op, k, val)
     return op
 

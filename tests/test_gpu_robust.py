@@ -1,0 +1,59 @@
+"""Solver behaviour beyond parity: bitwise repeatability, restart from a saved iterate, and the
+precision-dependent default tolerances."""
+import numpy as np
+import pytest
+
+from paper_2506_06805_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def inst():
+    o, v, N = 6, 20, 60
+    return synth.make_instance(o, v, N, seed=77, kappa=synth.kappa_for(v, N))
+
+
+def test_solve_is_bitwise_repeatable(gpu_ctx, inst):
+    from paper_2506_06805_amd import fnscc
+    out = []
+    for _ in range(2):
+        ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, inst.o)
+        e, it, amps = fnscc.ccsd_solve(gpu_ctx, ints)
+        w, its = fnscc.ipeom_davidson(gpu_ctx, ints, amps, 4)
+        t1, t2 = amps.read()
+        out.append((e, it, t2.cpu().numpy(), w, its))
+    (e1, i1, a1, w1, j1), (e2, i2, a2, w2, j2) = out
+    assert e1 == e2 and i1 == i2 and j1 == j2
+    assert np.array_equal(a1, a2) and np.array_equal(w1, w2)
+
+
+def test_restart_from_saved_iterate(gpu_ctx, inst):
+    # a solve stopped early and resumed from its iterate reaches the same solution
+    from paper_2506_06805_amd import fnscc
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, inst.o)
+    e_ref, it_ref, _ = fnscc.ccsd_solve(gpu_ctx, ints)
+    _, it8, part = fnscc.ccsd_solve(gpu_ctx, ints, allow_noconv=True, max_iter=8)
+    assert it8 == 8
+    t1, t2 = part.read()
+    e, it, _ = fnscc.ccsd_solve(gpu_ctx, ints, t1_init=t1, t2_init=t2)
+    assert abs(e - e_ref) < 1e-9
+    assert it < it_ref
+
+
+def test_default_tolerance_follows_precision(gpu_ctx, inst):
+    # split products: the looser default stops earlier; the IPs stay within 1e-5 Eh of FP64
+    from paper_2506_06805_amd import fnscc
+    res = {}
+    for prec in ("fp64", "split-bf16"):
+        ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, inst.o, precision=prec)
+        e, it, amps = fnscc.ccsd_solve(gpu_ctx, ints, precision=prec)
+        w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, 4)
+        res[prec] = (e, it, np.sort_complex(w))
+    # with the FP64 tolerance the split path may sit on its rounding floor without ever converging
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, inst.o, precision="split-bf16")
+    _, it_tight, _ = fnscc.ccsd_solve(gpu_ctx, ints, precision="split-bf16", e_tol=1e-10, r_tol=1e-9,
+                                      max_iter=60, allow_noconv=True)
+    assert res["split-bf16"][1] <= it_tight
+    assert np.abs(res["split-bf16"][2] - res["fp64"][2]).max() < 1e-5
+    assert abs(res["split-bf16"][0] - res["fp64"][0]) < 1e-5
