@@ -46,7 +46,7 @@ template <> struct Mfma<float> {
 };
 
 constexpr int KQ = 16;     // K chunks of split products are multiples of this (and of every K slice)
-constexpr int PAD = 16;    // LDS row padding of the FP32 planes (elements)
+constexpr int PADF = 2;    // LDS row padding of the FP32 complex rows (elements of 8 bytes)
 constexpr int PADZ = 1;    // LDS row padding of the FP64 complex rows (elements of 16 bytes)
 
 struct GemmArgs {
@@ -72,15 +72,22 @@ __device__ inline long xcd_tile(long bid, long tiles) {
 }
 
 // K slice BK (complex elements) staged per step in the arithmetic type T, double-buffered.
-// FP32: separate real and imaginary planes.
+// FP32: interleaved complex rows of 8-byte elements padded by two, so that the staging stores of a
+// K-contiguous operand (8 K rows x 2 columns per 16 lanes) fall on distinct bank pairs.
 template <int BM, int BN, int BK, typename T = double>
 struct TileSmem {
-  T Ar[2][BK][BM + PAD], Ai[2][BK][BM + PAD];
-  T Br[2][BK][BN + PAD], Bi[2][BK][BN + PAD];
-  __device__ __forceinline__ void putA(int b, int k, int m, z v) { Ar[b][k][m] = (T)v.x; Ai[b][k][m] = (T)v.y; }
-  __device__ __forceinline__ void putB(int b, int k, int n, z v) { Br[b][k][n] = (T)v.x; Bi[b][k][n] = (T)v.y; }
-  __device__ __forceinline__ void getA(int b, int k, int m, T& re, T& im) const { re = Ar[b][k][m]; im = Ai[b][k][m]; }
-  __device__ __forceinline__ void getB(int b, int k, int n, T& re, T& im) const { re = Br[b][k][n]; im = Bi[b][k][n]; }
+  __attribute__((aligned(8))) float2 A[2][BK][BM + PADF];
+  __attribute__((aligned(8))) float2 B[2][BK][BN + PADF];
+  __device__ __forceinline__ void putA(int b, int k, int m, z v) { A[b][k][m] = make_float2((float)v.x, (float)v.y); }
+  __device__ __forceinline__ void putB(int b, int k, int n, z v) { B[b][k][n] = make_float2((float)v.x, (float)v.y); }
+  __device__ __forceinline__ void getA(int b, int k, int m, T& re, T& im) const {
+    const float2 v = A[b][k][m];
+    re = v.x; im = v.y;
+  }
+  __device__ __forceinline__ void getB(int b, int k, int n, T& re, T& im) const {
+    const float2 v = B[b][k][n];
+    re = v.x; im = v.y;
+  }
 };
 // FP64: interleaved complex rows of 16-byte elements, one read yields the real and the imaginary
 // part.  Rows of BM + 1 elements put the 8 K rows of a K-contiguous operand's staging store on
