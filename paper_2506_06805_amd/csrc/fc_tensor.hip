@@ -297,38 +297,65 @@ void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z bet
   auto prod = [&](const std::string& x) { long p = 1; for (char ch : x) p *= dim[ch]; return p; };
   const long M = prod(FA), N = prod(FB), KK = prod(K);
 
-  // A operand: as [FA, K] (N) or [K, FA] (T) in A's own order, else permuted to [FA(C order), K].
-  std::string faOrd, kOrd;
-  const z* Ap = A.p; char opA; DBuf Atmp;
-  {
-    std::string pre = s.a.substr(0, FA.size()), post = s.a.substr(FA.size());
-    std::string pre2 = s.a.substr(0, K.size()), post2 = s.a.substr(K.size());
-    if (is_perm_of(pre, FA) && is_perm_of(post, K)) { faOrd = pre; kOrd = post; opA = conjA ? 'R' : 'N'; }
-    else if (is_perm_of(pre2, K) && is_perm_of(post2, FA)) { kOrd = pre2; faOrd = post2; opA = conjA ? 'C' : 'T'; }
-    else {
-      faOrd.clear();
-      for (char ch : s.c) if (FA.find(ch) != std::string::npos) faOrd += ch;
-      kOrd = K;
-      Atmp = DBuf(ctx, sizeof(z) * std::max(1L, A.size()));
-      permute(ctx, A, perm_to(s.a, faOrd + kOrd), make_double2(1, 0), make_double2(0, 0), Atmp.as<z>(), conjA);
-      Ap = Atmp.as<z>(); opA = 'N';
-    }
+  // Plan: the order of the summed indices (kOrd) decides which operands can be used in place.
+  // Candidates are the orders in which either operand already holds its summed indices
+  // contiguously; the plan that moves the fewest bytes through permutations wins.
+  struct Plan {
+    std::string kOrd, faOrd, fbOrd;
+    bool permA = false, permB = false, permC = false;
+    char opA = 'N', opB = 'N';
+    double cost = 0;
+  };
+  std::string cFA, cFB;   // free indices in the output's order
+  for (char ch : s.c) (FA.find(ch) != std::string::npos ? cFA : cFB) += ch;
+  auto plan_for = [&](const std::string& kOrd) {
+    Plan p;
+    p.kOrd = kOrd;
+    const std::string pre = s.a.substr(0, FA.size()), post = s.a.substr(FA.size());
+    const std::string pre2 = s.a.substr(0, K.size()), post2 = s.a.substr(K.size());
+    if (is_perm_of(pre, FA) && post == kOrd) { p.faOrd = pre; p.opA = conjA ? 'R' : 'N'; }
+    else if (pre2 == kOrd && is_perm_of(post2, FA)) { p.faOrd = post2; p.opA = conjA ? 'C' : 'T'; }
+    else { p.faOrd = cFA; p.permA = true; p.opA = 'N'; }
+    const std::string bpre = s.b.substr(0, K.size()), bpost = s.b.substr(K.size());
+    const std::string bpre2 = s.b.substr(0, FB.size()), bpost2 = s.b.substr(FB.size());
+    if (bpre == kOrd && is_perm_of(bpost, FB)) { p.fbOrd = bpost; p.opB = conjB ? 'R' : 'N'; }
+    else if (bpost2 == kOrd && is_perm_of(bpre2, FB)) { p.fbOrd = bpre2; p.opB = conjB ? 'C' : 'T'; }
+    else { p.fbOrd = cFB; p.permB = true; p.opB = 'N'; }
+    p.permC = !(s.c == p.faOrd + p.fbOrd || s.c == p.fbOrd + p.faOrd);
+    p.cost = (p.permA ? 2.0 * A.size() : 0.0) + (p.permB ? 2.0 * B.size() : 0.0) + (p.permC ? 3.0 * M * N : 0.0);
+    return p;
+  };
+  std::vector<std::string> cands;
+  auto add = [&](const std::string& k) {
+    if (is_perm_of(k, K) && std::find(cands.begin(), cands.end(), k) == cands.end()) cands.push_back(k);
+  };
+  add(s.a.substr(FA.size()));
+  add(s.a.substr(0, K.size()));
+  add(s.b.substr(0, K.size()));
+  add(s.b.substr(FB.size()));
+  add(K);
+  Plan best;
+  best.cost = -1;
+  for (const auto& k : cands) {
+    Plan p = plan_for(k);
+    if (best.cost < 0 || p.cost < best.cost) best = p;
   }
-  // B operand: [K(kOrd), FB] (N) or [FB, K(kOrd)] (T), else permuted to [K(kOrd), FB(C order)].
-  std::string fbOrd;
-  const z* Bp = B.p; char opB; DBuf Btmp;
-  {
-    std::string pre = s.b.substr(0, K.size()), post = s.b.substr(K.size());
-    std::string pre2 = s.b.substr(0, FB.size()), post2 = s.b.substr(FB.size());
-    if (pre == kOrd && is_perm_of(post, FB)) { fbOrd = post; opB = conjB ? 'R' : 'N'; }
-    else if (post2 == kOrd && is_perm_of(pre2, FB)) { fbOrd = pre2; opB = conjB ? 'C' : 'T'; }
-    else {
-      fbOrd.clear();
-      for (char ch : s.c) if (FB.find(ch) != std::string::npos) fbOrd += ch;
-      Btmp = DBuf(ctx, sizeof(z) * std::max(1L, B.size()));
-      permute(ctx, B, perm_to(s.b, kOrd + fbOrd), make_double2(1, 0), make_double2(0, 0), Btmp.as<z>(), conjB);
-      Bp = Btmp.as<z>(); opB = 'N';
-    }
+  if (ctx->verbose >= 2 && best.cost > 0)
+    fprintf(stderr, "[zein] %s permutes A:%d B:%d C:%d (%.1f MB moved)\n", spec, best.permA, best.permB, best.permC,
+            best.cost * sizeof(z) / 1e6);
+  const std::string& kOrd = best.kOrd;
+  const std::string faOrd = best.faOrd, fbOrd = best.fbOrd;
+  const z* Ap = A.p; char opA = best.opA; DBuf Atmp;
+  if (best.permA) {
+    Atmp = DBuf(ctx, sizeof(z) * std::max(1L, A.size()));
+    permute(ctx, A, perm_to(s.a, faOrd + kOrd), make_double2(1, 0), make_double2(0, 0), Atmp.as<z>(), conjA);
+    Ap = Atmp.as<z>();
+  }
+  const z* Bp = B.p; char opB = best.opB; DBuf Btmp;
+  if (best.permB) {
+    Btmp = DBuf(ctx, sizeof(z) * std::max(1L, B.size()));
+    permute(ctx, B, perm_to(s.b, kOrd + fbOrd), make_double2(1, 0), make_double2(0, 0), Btmp.as<z>(), conjB);
+    Bp = Btmp.as<z>();
   }
   const long lda = (opA == 'N' || opA == 'R') ? KK : M;
   const long ldb = (opB == 'N' || opB == 'R') ? N : KK;
