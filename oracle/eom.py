@@ -128,6 +128,30 @@ def dense_roots(h: Hbar, k):
     return wk, V[:, idx]
 
 
+def sigma_left(h: Hbar, vec):
+    """Left sigma: the row vector(s) l times the IP-EOM matrix, (L H-bar) restricted to the 1h + 2h1p
+    space (Eq. 19-20: <Phi0| L_k H-bar = omega_k <Phi0| L_k).  Plain definition through the dense
+    matrix, whose columns are pinned by the Fock-space brute force."""
+    vec = np.asarray(vec, dtype=np.complex128)
+    return vec @ dense_matrix(h)
+
+
+def left_right_roots(h: Hbar, k):
+    """Lowest-k roots with right vectors (columns of R) and left vectors (rows of L) normalised to
+    the biorthogonality of Eq. 19, sum_x L[k, x] R[x, l] = delta_kl (a bilinear product: <Phi0|L_k
+    R_l|Phi0> pairs l^i with r_i and l_b^ij with r_ij^b, no complex conjugation)."""
+    M = dense_matrix(h)
+    w, V = np.linalg.eig(M)
+    Vinv = np.linalg.inv(V)              # rows: left eigenvectors, Vinv V = 1
+    wk, idx = lowest_roots(w, k)
+    return wk, V[:, idx], Vinv[idx, :]
+
+
+def one_hole_weight(L, R, o):
+    """Share of the biorthonormal product carried by the 1h part, sum_i l^i r_i, per root."""
+    return np.einsum("ki,ik->k", L[:, :o], R[:o, :])
+
+
 def davidson(h: Hbar, k, r_tol=1e-9, w_tol=1e-10, max_iter=200, max_sub=None, nguess=None, verbose=False):
     """Non-Hermitian Davidson for the k eigenvalues of lowest real part.
 

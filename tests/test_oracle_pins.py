@@ -244,3 +244,35 @@ def test_sampled_residual_rows_match_full():
     assert np.allclose(s2[:, :, rows, :], r2[:, :, rows, :], rtol=0, atol=1e-14)
     others = [a for a in range(v) if a not in rows]
     assert not np.allclose(s2[:, :, others, :], r2[:, :, others, :])
+
+
+def test_left_vectors_biorthonormal_and_left_sigma():
+    # Eq. 19: <Phi0|L_k R_l|Phi0> = delta_kl; left vectors satisfy L H-bar = omega L
+    o, v, N, k = 3, 6, 9, 5
+    inst = synth.make_instance(o, v, N, seed=73, kappa=0.5)
+    e, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, o)
+    assert conv
+    h = eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    w, R, L = eom.left_right_roots(h, k)
+    assert np.allclose(L @ R, np.eye(k), atol=1e-10)
+    S = eom.sigma_left(h, L)
+    assert np.allclose(S, w[:, None] * L, atol=1e-10)
+    # left and right sigma are transposes: y . (H x) = (y H) . x for random x, y
+    rng = np.random.default_rng(1)
+    d = eom.dim(o, v)
+    x = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    y = rng.standard_normal(d) + 1j * rng.standard_normal(d)
+    assert abs(y @ eom.sigma(h, x) - eom.sigma_left(h, y) @ x) < 1e-10 * np.abs(y).sum() * np.abs(x).sum()
+
+
+def test_left_vectors_pure_one_hole_without_interaction():
+    # no two-electron term: H-bar is diagonal, the o lowest roots are -eps_i with 1h weight 1
+    o, v, N = 3, 5, 4
+    inst = synth.make_instance(o, v, N, seed=3, kappa=1.0)
+    L0 = np.zeros_like(inst.L)
+    t1 = np.zeros((o, v), dtype=np.complex128)
+    t2 = np.zeros((o, o, v, v), dtype=np.complex128)
+    h = eom.Hbar(integrals.Blocks(L0, o), inst.eps, t1, t2)
+    w, R, L = eom.left_right_roots(h, o)
+    assert np.allclose(np.sort(w.real), np.sort(-inst.eps[:o]), atol=1e-12)
+    assert np.allclose(eom.one_hole_weight(L, R, o), 1.0, atol=1e-12)
