@@ -13,26 +13,31 @@ from __future__ import annotations
 import numpy as np
 
 
-def pivoted_cholesky(M, tau):
-    """Return (Lvec (nvec, m), residual diagonal) with M ~= Lvec^T Lvec."""
+def pivoted_cholesky(M, tau, max_vec=None, with_pivots=False):
+    """Return (Lvec (nvec, m), residual diagonal) with M ~= Lvec^T Lvec; with_pivots adds the
+    pivot index of each vector.  max_vec caps the number of vectors (the loop then ends early
+    with the diagonal still above tau)."""
     M = np.asarray(M, dtype=np.float64)
     m = M.shape[0]
+    cap = m if max_vec is None else min(m, max_vec)
     d = np.diag(M).copy()
-    vecs = []
-    while True:
-        p = int(np.argmax(d)) if m else 0
-        if m == 0 or d[p] < tau:
+    vecs, pivots = [], []
+    while len(vecs) < cap:
+        p = int(np.argmax(d))          # first index among equal maxima
+        if d[p] < tau:
             break
         col = M[:, p].copy()
         for l in vecs:
             col -= l * l[p]
         l = col / np.sqrt(d[p])
         vecs.append(l)
+        pivots.append(p)
         d = d - l * l
         d[p] = 0.0
-        if len(vecs) == m:
-            break
-    return (np.array(vecs) if vecs else np.zeros((0, m))), d
+    Lvec = np.array(vecs) if vecs else np.zeros((0, m))
+    if with_pivots:
+        return Lvec, d, np.array(pivots, dtype=np.int64)
+    return Lvec, d
 
 
 def ao_to_spinor(Lao, C, nao):

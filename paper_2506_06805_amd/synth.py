@@ -163,13 +163,20 @@ def make_ao_eri(nao: int, rank: int, seed: int) -> np.ndarray:
     decaying weights w_k = exp(-3 k / rank): positive semi-definite, rank <= rank, and with the
     permutational symmetry (mu nu | ka la) = (nu mu | ka la) = (ka la | mu nu).
     """
+    w, X = make_ao_eri_factors(nao, rank, seed)
+    return (X.T * w) @ X
+
+
+def make_ao_eri_factors(nao: int, rank: int, seed: int):
+    """The factors of make_ao_eri: weights w (rank) and rows X[k] = x_k flattened (rank x nao^2),
+    M = X^T diag(w) X.  Same draws, so large supermatrices can be formed on the device."""
     rng = np.random.default_rng(seed)
-    M = np.zeros((nao * nao, nao * nao))
+    X = np.empty((rank, nao * nao))
     for k in range(rank):
         x = rng.standard_normal((nao, nao))
-        x = 0.5 * (x + x.T)
-        M += math.exp(-3.0 * k / rank) * np.outer(x.ravel(), x.ravel())
-    return M
+        X[k] = (0.5 * (x + x.T)).ravel()
+    w = np.exp(-3.0 * np.arange(rank) / rank)
+    return w, X
 
 
 def make_spinor_coefficients(nao: int, n: int, seed: int) -> np.ndarray:

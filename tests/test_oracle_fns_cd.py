@@ -44,6 +44,33 @@ def test_p5_cd_exact_limit_matches_four_index_transform():
     assert np.abs(integrals.full_antisym(L) - anti).max() < 1e-10
 
 
+def test_p5_cd_pivot_order_diagonal_matrix():
+    # a diagonal M is its own Cholesky factor: vectors sqrt(m_pp) e_p, pivots in descending order
+    # of the diagonal, the lowest index first among equal entries; max_vec stops early
+    vals = np.array([3.0, 1.0, 4.0, 1.5, 9.0, 2.6, 4.0])
+    Lv, d, piv = cd.pivoted_cholesky(np.diag(vals), 1e-12, with_pivots=True)
+    assert list(piv) == [4, 2, 6, 0, 5, 3, 1]
+    assert np.allclose(Lv, np.sqrt(vals)[piv, None] * np.eye(7)[piv], atol=0, rtol=1e-15)
+    assert np.abs(d).max() == 0.0
+    Lv2, d2, piv2 = cd.pivoted_cholesky(np.diag(vals), 1e-12, max_vec=2, with_pivots=True)
+    assert list(piv2) == [4, 2] and np.array_equal(Lv2, Lv[:2])
+    assert d2.max() == 4.0
+    _, _, piv3 = cd.pivoted_cholesky(np.diag(vals), 2.0, with_pivots=True)
+    assert list(piv3) == [4, 2, 6, 0, 5]
+
+
+def test_p5_cd_full_rank_is_permuted_cholesky():
+    # positive definite M, tau -> 0: M[piv][:, piv] = G G^T with G lower triangular, G = L[:, piv]^T
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((9, 9))
+    M = A @ A.T + 0.1 * np.eye(9)
+    Lv, _, piv = cd.pivoted_cholesky(M, 1e-14, with_pivots=True)
+    assert sorted(piv) == list(range(9))
+    G = Lv[:, piv].T
+    assert np.abs(np.triu(G, 1)).max() < 1e-12    # earlier pivots vanish in later vectors
+    assert np.abs(G - np.linalg.cholesky(M[np.ix_(piv, piv)])).max() < 1e-12
+
+
 def test_p6_density_properties():
     inst = synth.make_instance(4, 9, 15, seed=5, kappa=0.6)
     D = fns.vv_density(inst.L, inst.eps, inst.o)
