@@ -49,10 +49,13 @@ def run_gpu(args, inst, wl, precision, mlp=None, ctx=None):
     o, v, N, k = inst.o, inst.v, inst.ncd, wl["roots"]
     extra = {"mlp": mlp} if mlp is not None else {}
 
+    last = {}
+
     def step():
         ints = fnscc.cd_integrals(ctx, inst.eps, L_dev, o, precision=precision)
         e, it, amps = fnscc.ccsd_solve(ctx, ints, precision=precision, **extra)
         w, its = fnscc.ipeom_davidson(ctx, ints, amps, k)
+        last.update(ints=ints, amps=amps)
         return e, it, w, its
 
     for _ in range(args.warmup):
@@ -75,7 +78,25 @@ def run_gpu(args, inst, wl, precision, mlp=None, ctx=None):
     lad_ms = tm.get("ladder_event_ms", 0.0) / max(n_lad, 1.0)
     e, it, w, its = out[-1]
     return dict(ms_per_step=ms_per_step, ladder_ms=lad_ms, ladder_calls=n_lad, e=e, iters=it, w=w,
-                eom_iters=its)
+                eom_iters=its, **last)
+
+
+def left_vectors(ctx, r, k):
+    """Left eigenvectors and one-hole weights (Eq. 19-20) of the timed solve's last step, timed on
+    their own: they are not part of time-to-IPs."""
+    import torch
+
+    from paper_2506_06805_amd import fnscc
+
+    w, _, R = fnscc.ipeom_davidson(ctx, r["ints"], r["amps"], k, want_vectors=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wl, its, L, wt = fnscc.ipeom_left(ctx, r["ints"], r["amps"], k, R)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bi = float(np.abs(L.cpu().numpy() @ R.cpu().numpy().T - np.eye(k)).max())
+    return {"seconds": t1 - t0, "davidson_iters": its, "max_abs_dw_vs_right": float(np.abs(wl - w).max()),
+            "max_abs_biorthonormality_error": bi, "one_hole_weights": [float(x) for x in np.real(wt)]}
 
 
 def train_update_network(ctx, count=16, seed=7):
@@ -250,6 +271,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ladder-only", action="store_true",
                     help="time ladder evaluations alone (profiling aid; not the time-to-IPs metric)")
+    ap.add_argument("--no-left", dest="left", action="store_false",
+                    help="skip the left eigenvectors and one-hole weights of the benchmarked instance")
     ap.add_argument("--no-compare", dest="compare", action="store_false",
                     help="skip the split-BF16 and split-BF16 + learned runs on the same instance")
     ap.add_argument("--host-inputs", action="store_true",
@@ -343,6 +366,10 @@ def main():
         "result": {"e_corr": [r["e"].real, r["e"].imag], "ccsd_iters": r["iters"], "eom_iters": r["eom_iters"],
                    "ips": [float(x) for x in np.real(r["w"])]},
     }
+    if args.left:
+        line["left_vectors"] = left_vectors(ctx, r, wl["roots"])
+    r.pop("ints", None)
+    r.pop("amps", None)
     if args.compare and args.precision == "fp64":
         # the same instance through the split-BF16 path, then with the learned update on top
         w64 = np.sort_complex(np.asarray(r["w"]))

@@ -67,6 +67,24 @@ int fc_autotune_save(fc_ctx ctx, const char* path);
 int fc_autotune_load(fc_ctx ctx, const char* path);
 int fc_autotune_size(fc_ctx ctx);
 
+/* cd_ao_pivoted - single-step pivoted Cholesky of the AO two-electron supermatrix (Eq. 21):
+ * M ~= sum_P l_P l_P^T.  Each step takes as pivot the largest remaining diagonal entry (the lowest
+ * index among equal ones), forms l = (M[p, :] - sum_{earlier P} l_P[p] l_P) / sqrt(d_p) and
+ * lowers the diagonal by l^2; the loop stops before the step whose pivot is < tau.
+ * M: device, m x m doubles, row-major, symmetric positive semi-definite (the supermatrix
+ * (mu nu|ka la) over any composite index of AO pairs; read only).  tau > 0.  L: device,
+ * max_vec x m doubles, row P = vector P.  nvec: host, vectors formed.  piv: host, max_vec ints
+ * (the pivot of each vector) or NULL.  FC_ENOCONV when max_vec < m vectors were formed while the
+ * largest diagonal is still >= tau (L then holds those vectors); FC_EARG for bad sizes. */
+int cd_ao_pivoted(fc_ctx ctx, long m, const double* M, double tau, int max_vec, double* L, int* nvec, int* piv);
+/* ao_to_spinor - the two-component transform of Eq. 22:
+ * L^P_pq = sum_{s = alpha, beta} sum_{mu nu} conj(C[s nao + mu][p]) L^P_{mu nu} C[s nao + nu][q].
+ * Lao: device, nvec x nao x nao doubles (the real AO vectors, full square, as cd_ao_pivoted
+ * returns them for the composite index mu nao + nu).  C: device, 2 nao x n complex128 spinor
+ * coefficients (rows: alpha AOs, then beta AOs).  Lmo: device, nvec x n x n complex128, the
+ * layout cd_integrals takes (select columns of C to transform a subset of spinors). */
+int ao_to_spinor(fc_ctx ctx, int nvec, int nao, int n, const double* Lao, const void* C, void* Lmo);
+
 /* cd_integrals - stage the Cholesky vectors (Eq. 22) and assemble the stored antisymmetrised
  * integrals with at most two virtual indices (Eq. 23 and the storage rule of Sec. 3:
  * <mn||ij>, <mn||ie>, <mn||ef>, <mb||ej> and the blocks derived from them by index symmetry).
@@ -147,6 +165,13 @@ void fc_free_amps(fc_amps t);
  * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3). */
 int ipeom_sigma(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* R, void* S);
 
+/* ipeom_sigma_left - the left product S = Y H-bar (Eq. 19-20): each row of Y holds the
+ * amplitudes l^i and l_b^ij (i < j) of one left vector in the layout of R above, and the matching
+ * row of S is that row vector times the IP-EOM-CCSD matrix, so that for any R
+ * sum_x S[x] R[x] = sum_x Y[x] (H-bar R)[x] (a bilinear product, no conjugation).
+ * Y, S: device, nvec x dim complex128.  Errors as ipeom_sigma. */
+int ipeom_sigma_left(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* Y, void* S);
+
 /* graph: 1 (default) captures the sigma launches of all instances once into a HIP graph and
  * replays it for every Davidson iteration; 0 launches them directly (same results bit for bit). */
 typedef struct {
@@ -163,6 +188,21 @@ void fc_eom_default_opts(fc_eom_opts* opts);
  * R_out: device, sum(nroots) x dim_b right eigenvectors (or NULL). iters: host, nb ints. */
 int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
                    const fc_eom_opts* opts, double* omega, void* R_out, int* iters);
+
+/* ipeom_left - left eigenvectors L_k (Eq. 20) dual to the right eigenvectors R of ipeom_davidson,
+ * normalised by the biorthogonality condition of Eq. 19: sum_x L_k[x] R_l[x] = delta_kl over the
+ * packed layout (a bilinear product, no conjugation).  The lowest nroots left roots are solved by
+ * the same batched Davidson on the transposed problem; L is then replaced by O^-1 L with
+ * O = L R^T, which also handles degenerate roots.
+ * R: device, sum(nroots) x dim_b right eigenvectors as returned by ipeom_davidson (same nb,
+ * ints, t and nroots; read only).  omega: host, sum(nroots) x 2 doubles, the left eigenvalues
+ * (equal to the right ones within the solver tolerance).  L_out: device, sum(nroots) x dim_b.
+ * weight: host, sum(nroots) x 2 doubles, the one-hole part sum_i l^i_k r_{k,i} of the
+ * normalisation (the ionisation strength of root k when ground-state relaxation is neglected).
+ * iters: host, nb ints, or NULL.  FC_ENUMERIC when the left and right roots do not pair up
+ * (O near singular); FC_ENOCONV as ipeom_davidson. */
+int ipeom_left(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
+               const fc_eom_opts* opts, const void* R, double* omega, void* L_out, double* weight, int* iters);
 
 /* Learned update network. Parameters: one FP32 vector W1 (64x4), b1, W2 (64x64), b2, W3 (2x64),
  * b3 (fc_mlp_num_params() entries). fc_mlp_create: params_host (host) or NULL for a seeded

@@ -28,6 +28,7 @@ SOURCES = [
     "fc_sigma.hip",
     "fc_eom.hip",
     "fc_mlp.hip",
+    "fc_aocd.hip",
     "fc_api.hip",
     "fc_linalg.cpp",
 ]

@@ -14,7 +14,9 @@ namespace fc {
 void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype);
 void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2);
 int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
-                   const fc_eom_opts& op, z* omega, z* Rout, int* iters);
+                   const fc_eom_opts& op, z* omega, z* Rout, int* iters, bool left = false);
+int left_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
+               const fc_eom_opts& op, const z* R, z* omega, z* L, z* weight, int* iters);
 
 namespace {
 constexpr int TPB = 256;
@@ -372,6 +374,28 @@ int fc_autotune_load(fc_ctx ctx, const char* path) {
 
 int fc_autotune_size(fc_ctx ctx) { return ctx ? (int)ctx->tune.size() : 0; }
 
+int cd_ao_pivoted(fc_ctx ctx, long m, const double* M, double tau, int max_vec, double* L, int* nvec, int* piv) {
+  if (!ctx || m < 1 || !M || !L || !nvec || max_vec < 1 || !(tau > 0)) return FC_EARG;
+  FC_TRY(ctx, {
+    *nvec = 0;
+    // m vectors exhaust any m x m matrix: reaching them is convergence, not a cap
+    const int cap = (int)std::min<long>(max_vec, m);
+    int s = cd_pivoted_dev(ctx, m, M, tau, cap, L, nvec, piv);
+    if (s == FC_ENOCONV && cap == m) s = FC_OK;
+    if (s == FC_ENOCONV) ctx->last_error = "cd_ao_pivoted: max_vec vectors formed before the diagonal fell below tau";
+    return s;
+  })
+}
+
+int ao_to_spinor(fc_ctx ctx, int nvec, int nao, int n, const double* Lao, const void* C, void* Lmo) {
+  if (!ctx || nvec < 1 || nao < 1 || n < 1 || !Lao || !C || !Lmo) return FC_EARG;
+  FC_TRY(ctx, {
+    ao_to_spinor_dev(ctx, nvec, nao, n, Lao, (const z*)C, (z*)Lmo);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
 int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const void* L, int l_dtype, int l_on_device,
                  int precision, fc_ints* out) {
   if (!ctx || !out) return FC_EARG;
@@ -546,6 +570,16 @@ int ipeom_sigma(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* R, void*
   })
 }
 
+int ipeom_sigma_left(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* Y, void* S) {
+  if (!ctx || !I || !T || nvec < 0 || (nvec > 0 && (!Y || !S))) return FC_EARG;
+  FC_TRY(ctx, {
+    FC_REQUIRE(T->ints == I, FC_EARG, "ipeom_sigma_left: amplitudes belong to another integral handle");
+    sigma_dev(ctx, I, T, nvec, (const z*)Y, (z*)S, true);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
 void fc_eom_default_opts(fc_eom_opts* op) {
   if (!op) return;
   op->r_tol = 1e-9;
@@ -572,6 +606,29 @@ int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, co
     const int s = davidson_batch(ctx, nb, ints, t, nroots, op, w.data(), (z*)R_out, iters);
     for (long r = 0; r < total; ++r) { omega[2 * r] = w[r].x; omega[2 * r + 1] = w[r].y; }
     if (s == FC_ENOCONV) ctx->last_error = "ipeom_davidson: not converged within max_iter";
+    return s;
+  })
+}
+
+int ipeom_left(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const int* nroots,
+               const fc_eom_opts* opts, const void* R, double* omega, void* L_out, double* weight, int* iters) {
+  if (!ctx || nb < 1 || !ints || !t || !nroots || !R || !omega || !L_out || !weight) return FC_EARG;
+  FC_TRY(ctx, {
+    fc_eom_opts op;
+    if (opts) op = *opts; else fc_eom_default_opts(&op);
+    FC_REQUIRE(op.max_iter >= 1, FC_EARG, "ipeom_left: max_iter must be >= 1");
+    long total = 0;
+    for (int b = 0; b < nb; ++b) {
+      FC_REQUIRE(nroots[b] >= 1, FC_EARG, "ipeom_left: nroots must be >= 1");
+      total += nroots[b];
+    }
+    std::vector<z> w(total), wt(total);
+    const int s = left_batch(ctx, nb, ints, t, nroots, op, (const z*)R, w.data(), (z*)L_out, wt.data(), iters);
+    for (long r = 0; r < total; ++r) {
+      omega[2 * r] = w[r].x; omega[2 * r + 1] = w[r].y;
+      weight[2 * r] = wt[r].x; weight[2 * r + 1] = wt[r].y;
+    }
+    if (s == FC_ENOCONV) ctx->last_error = "ipeom_left: not converged within max_iter";
     return s;
   })
 }

@@ -146,10 +146,10 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   H.ready = true;
 }
 
-void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S) {
+void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S, bool left) {
   if (nvec <= 0) return;
   const long k = nvec;
-  SigmaBatch sb(ctx, 1, &I, &T, &k, false);
+  SigmaBatch sb(ctx, 1, &I, &T, &k, false, left);
   sb.run(&R, &S, &k);
 }
 
@@ -259,8 +259,11 @@ size_t split_elems(long M, long N, long K, const GroupTiling& tl) {
 }
 }  // namespace
 
+// With `left` the trial vectors are multiplied from the left (sigma = V H-bar), so the solve
+// finds the eigenvectors of the transposed matrix: the left eigenvectors of Eq. 19-20, with the
+// same eigenvalues and the same diagonal preconditioner.
 int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
-                   const fc_eom_opts& op, z* omega, z* Rout, int* iters) {
+                   const fc_eom_opts& op, z* omega, z* Rout, int* iters, bool left) {
   StageTimer st(ctx, "davidson");
   const z one = make_double2(1, 0), zero = make_double2(0, 0), mone = make_double2(-1, 0);
   const GroupTiling tl{0, 1024};
@@ -346,7 +349,7 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
   std::vector<const z*> Rp(nb);
   std::vector<z*> Sp(nb);
   for (int b = 0; b < nb; ++b) kmax[b] = std::max(in[b].nguess, in[b].k);
-  SigmaBatch sb(ctx, nb, ints, amps, kmax.data(), op.graph != 0);
+  SigmaBatch sb(ctx, nb, ints, amps, kmax.data(), op.graph != 0, left);
   for (int b = 0; b < nb; ++b) {
     nv[b] = in[b].nguess;
     Rp[b] = in[b].V.as<z>();
@@ -648,6 +651,63 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
     if (s.status != FC_OK) status = s.status;
   }
   FC_HIP(hipStreamSynchronize(ctx->stream));
+  return status;
+}
+
+// Left eigenvectors dual to given right ones (Eq. 19): the lowest roots of the transposed problem
+// by the same Davidson, then L <- O^-1 L with the bilinear overlap O = L R^T, so that
+// sum_x L_k[x] R_l[x] = delta_kl (no complex conjugation anywhere).  O^-1 rather than a
+// per-root scale keeps the result right when roots are degenerate or come out of the two solves
+// in a different order.  weight_k = sum_i l^i_k r_{k,i}, the one-hole part of that product.
+int left_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
+               const fc_eom_opts& op, const z* R, z* omega, z* L, z* weight, int* iters) {
+  StageTimer st(ctx, "left");
+  const int status = davidson_batch(ctx, nb, ints, amps, nroots, op, omega, L, iters, true);
+  const z one = make_double2(1, 0), zero = make_double2(0, 0);
+  long roff = 0, off = 0;
+  for (int b = 0; b < nb; ++b) {
+    const long o = ints[b]->o, v = ints[b]->v, dim = o + o * (o - 1) / 2 * v;
+    const int k = nroots[b];
+    const z* Rb = R + roff;
+    z* Lb = L + roff;
+    DBuf O(ctx, sizeof(z) * k * k), Oi(ctx, sizeof(z) * k * k), Ln(ctx, sizeof(z) * (size_t)k * dim);
+    zgemm(ctx, 'N', 'T', k, k, dim, one, Lb, dim, Rb, dim, zero, O.as<z>(), k);
+    std::vector<z> Oh((size_t)k * k), inv((size_t)k * k);
+    FC_HIP(hipMemcpyAsync(Oh.data(), O.p, sizeof(z) * k * k, hipMemcpyDeviceToHost, ctx->stream));
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    // rows of L and R have unit norm, so a large inverse means the two solves found different roots
+    double big = 0;
+    for (int c = 0; c < k; ++c) {
+      std::vector<z> e(k, zero);
+      e[c] = one;
+      FC_REQUIRE(lin_solve(k, Oh, e), FC_ENUMERIC, "ipeom_left: singular left-right overlap");
+      for (int r = 0; r < k; ++r) {
+        inv[(size_t)r * k + c] = e[r];
+        big = std::max(big, std::hypot(e[r].x, e[r].y));
+      }
+    }
+    FC_REQUIRE(big < 1e6, FC_ENUMERIC, "ipeom_left: left and right vectors belong to different roots");
+    FC_HIP(hipMemcpyAsync(Oi.p, inv.data(), sizeof(z) * k * k, hipMemcpyHostToDevice, ctx->stream));
+    zgemm(ctx, 'N', 'N', k, dim, k, one, Oi.as<z>(), k, Lb, dim, zero, Ln.as<z>(), dim);
+    FC_HIP(hipMemcpyAsync(Lb, Ln.p, sizeof(z) * (size_t)k * dim, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<z> lh((size_t)k * o), rh((size_t)k * o);
+    FC_HIP(hipMemcpy2DAsync(lh.data(), sizeof(z) * o, Lb, sizeof(z) * dim, sizeof(z) * o, k, hipMemcpyDeviceToHost,
+                            ctx->stream));
+    FC_HIP(hipMemcpy2DAsync(rh.data(), sizeof(z) * o, Rb, sizeof(z) * dim, sizeof(z) * o, k, hipMemcpyDeviceToHost,
+                            ctx->stream));
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < k; ++r) {
+      z w = zero;
+      for (long i = 0; i < o; ++i) {
+        const z a = lh[(size_t)r * o + i], c = rh[(size_t)r * o + i];
+        w.x += a.x * c.x - a.y * c.y;
+        w.y += a.x * c.y + a.y * c.x;
+      }
+      weight[off + r] = w;
+    }
+    roff += (long)k * dim;
+    off += k;
+  }
   return status;
 }
 

@@ -10,6 +10,15 @@
 //              + x[i][j][a] - x[j][i][a],   x[i][(j, a)] = sum_{(m, e)} r_im^e W_maej
 // Only the ring product x needs the unpacked, antisymmetric r_im^e.  Every product here is an
 // FP64 MFMA GEMM; for all instances together they form two grouped persistent launches.
+//
+// The left product s = Y H-bar (row vectors l_i, l_b^ij of Eq. 20) applies the transpose of the
+// same linear map.  Unpacking and packing are each other's transposes, so the left sequence keeps
+// both kernels and transposes the products in between:
+//   s_m        = sum_x Y[x] BL1[x][m]                   BL1 = [B1[:o]^T ; B2[:o]^T]
+//   Z_e        = sum_{(p, a)} Y[(p, a)] t_ij^ae         (rows o + e of B2, transposed)
+//   s_p^e      = sum_a Y[(p, a)] F_ae + sum_q Mp[q][p] Y[(q, e)]
+//   s_(q, f)  += sum_i l_i B1[(q, f)][i] + sum_e Z_e <mn||ef>   = [l_i | Z_e] BL2
+//              + x[m][n][f] - x[n][m][f],   x[m][(n, f)] = sum_{(j, a)} l_mj^a W_nafj
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -84,6 +93,19 @@ __global__ void k_prep_B2(z* B2, const z* Wmbij, const z* t2, const int2* pairs,
     }
   }
 }
+// transposed operators of the left product, gathered from the right ones
+__global__ void k_prep_BL1(z* BL1, const z* B1, const z* B2, long o, long nv) {
+  GRID_STRIDE(t, (o + nv) * o) {
+    const long m = t % o, x = t / o;
+    BL1[t] = x < o ? B1[m * o + x] : B2[m * nv + (x - o)];
+  }
+}
+__global__ void k_prep_BL2(z* BL2, const z* B1, const z* Xop, long o, long v, long nv) {
+  GRID_STRIDE(t, (o + v) * nv) {
+    const long c = t % nv, x = t / nv;
+    BL2[t] = x < o ? B1[(o + c) * o + x] : Xop[c * v + (x - o)];
+  }
+}
 
 // ------------------------------------------------------------------ per-call elementwise kernels
 struct SigInst {
@@ -155,9 +177,26 @@ __global__ void k_sig_pack(const char* __restrict__ tab) {
 }
 }  // namespace
 
-void prep_sigma_ops(fc_ctx ctx, fc_ints I, fc_amps T) {
+static void prep_left_ops(fc_ctx ctx, fc_ints I, SigmaOps& so) {
+  StageTimer st(ctx, "sigma_prep");
+  const long o = I->o, v = I->v, no = o * (o - 1) / 2, nv = no * v;
+  so.BL1 = ZTensor(ctx, {o + nv, o});
+  so.BL2 = ZTensor(ctx, {o + v, nv});
+  hipLaunchKernelGGL(k_prep_BL1, dim3(nblk((o + nv) * o)), dim3(TPB), 0, ctx->stream, so.BL1.p(), so.B1.p(),
+                     so.B2.p(), o, nv);
+  if (no)
+    hipLaunchKernelGGL(k_prep_BL2, dim3(nblk((o + v) * nv)), dim3(TPB), 0, ctx->stream, so.BL2.p(), so.B1.p(),
+                       so.Xop.p(), o, v, nv);
+  FC_HIP(hipGetLastError());
+  so.left_ready = true;
+}
+
+void prep_sigma_ops(fc_ctx ctx, fc_ints I, fc_amps T, bool left) {
   SigmaOps& so = T->so;
-  if (so.ready) return;
+  if (so.ready) {
+    if (left && !so.left_ready) prep_left_ops(ctx, I, so);
+    return;
+  }
   if (!T->hb.ready) build_hbar(ctx, I, T);
   StageTimer st(ctx, "sigma_prep");
   const HbarBlocks& H = T->hb;
@@ -186,16 +225,18 @@ void prep_sigma_ops(fc_ctx ctx, fc_ints I, fc_amps T) {
   hipLaunchKernelGGL(k_prep_Wt, dim3(nblk(o * v * o * v)), dim3(TPB), 0, ctx->stream, so.Wt.p(), H.Wmbej.p(), o, v);
   FC_HIP(hipGetLastError());
   so.ready = true;
+  if (left) prep_left_ops(ctx, I, so);
 }
 
 // ------------------------------------------------------------------------------- SigmaBatch
-SigmaBatch::SigmaBatch(fc_ctx ctx, int nb, const fc_ints* I, const fc_amps* T, const long* kmax, bool graph)
-    : ctx_(ctx), nb_(nb), I_(I, I + nb), T_(T, T + nb), kmax_(kmax, kmax + nb), graph_(graph) {
+SigmaBatch::SigmaBatch(fc_ctx ctx, int nb, const fc_ints* I, const fc_amps* T, const long* kmax, bool graph,
+                       bool left)
+    : ctx_(ctx), nb_(nb), I_(I, I + nb), T_(T, T + nb), kmax_(kmax, kmax + nb), graph_(graph), left_(left) {
   FC_REQUIRE(nb >= 1, FC_EARG, "sigma: no instances");
   for (int b = 0; b < nb; ++b) {
     FC_REQUIRE(I[b] && T[b] && T[b]->ints == I[b], FC_EARG, "sigma: bad handles");
     FC_REQUIRE(kmax[b] >= 0, FC_EARG, "sigma: negative vector count");
-    prep_sigma_ops(ctx, I[b], T[b]);
+    prep_sigma_ops(ctx, I[b], T[b], left);
     const long o = I[b]->o, v = I[b]->v, no = o * (o - 1) / 2, k = std::max(1L, kmax[b]);
     r2_.emplace_back(ctx, std::vector<long>{k, o, o, v});
     x_.emplace_back(ctx, std::vector<long>{k, o, o, v});
@@ -252,6 +293,41 @@ void SigmaBatch::lists(const z* const* R, z* const* S, const long* nvec, std::ve
     eu += k * o * o * v + k * o;
     ep += k * nv;
     GroupGemm p;
+    if (left_) {
+      const z* R2 = R[b] ? R[b] + o : nullptr;
+      // s_m = Y BL1
+      p = GroupGemm{}; p.M = k; p.N = o; p.K = dim;
+      p.A = R[b]; p.lda = dim; p.B = so.BL1.p(); p.ldb = o; p.C = S[b]; p.ldc = dim;
+      g1.push_back(p);
+      // ring: x[(k, m)][(n, f)] = y2[(k, m)][(j, a)] Wt[(n, f)][(j, a)]
+      p = GroupGemm{}; p.opB = 'T'; p.M = k * o; p.N = ov; p.K = ov;
+      p.A = s.r2; p.lda = ov; p.B = so.Wt.p(); p.ldb = ov; p.C = s.x; p.ldc = ov;
+      g1.push_back(p);
+      if (no) {
+        // Z_e into Y[:, o:]
+        p = GroupGemm{}; p.opB = 'T'; p.M = k; p.N = v; p.K = nv;
+        p.A = R2; p.lda = dim; p.B = so.B2.p() + o * nv; p.ldb = nv;
+        p.C = s.Y + o; p.ldc = o + v;
+        g1.push_back(p);
+        // l_ij^a F_ae straight into the packed output, one batch entry per vector
+        p = GroupGemm{}; p.M = no; p.N = v; p.K = v; p.batch = k;
+        p.A = R2; p.lda = v; p.sA = dim; p.B = T_[b]->hb.Fae.p(); p.ldb = v;
+        p.C = S[b] ? S[b] + o : nullptr; p.ldc = v; p.sC = dim;
+        g1.push_back(p);
+        // pair mixing, transposed, into s2b
+        p = GroupGemm{}; p.opA = 'T'; p.M = no; p.N = v; p.K = no; p.batch = k;
+        p.A = so.Mp.p(); p.lda = no; p.sA = 0;
+        p.B = R2; p.ldb = v; p.sB = dim;
+        p.C = s.s2b; p.ldc = v; p.sC = nv;
+        g1.push_back(p);
+        // [l_i | Z_e] BL2 added to the packed output
+        p = GroupGemm{}; p.M = k; p.N = nv; p.K = o + v;
+        p.A = s.Y; p.lda = o + v; p.B = so.BL2.p(); p.ldb = nv;
+        p.beta = one; p.C = S[b] ? S[b] + o : nullptr; p.ldc = dim;
+        g2.push_back(p);
+      }
+      continue;
+    }
     // sigma_i = R B1
     p = GroupGemm{}; p.M = k; p.N = o; p.K = dim;
     p.A = R[b]; p.lda = dim; p.B = so.B1.p(); p.ldb = o; p.C = S[b]; p.ldc = dim;
@@ -343,7 +419,8 @@ void SigmaBatch::tune(const z* const* R, z* const* S, const long* nvec) {
     flops += 8.0 * nvec[b] * o * o * o * v * v;
   }
   char key[64];
-  snprintf(key, sizeof(key), "sigma_nb%d_f%d", nb_, (int)std::ceil(std::log2(std::max(1.0, flops))));
+  snprintf(key, sizeof(key), "sigma_%snb%d_f%d", left_ ? "left_" : "", nb_,
+           (int)std::ceil(std::log2(std::max(1.0, flops))));
   auto it = ctx_->tune.find(key);
   if (it != ctx_->tune.end()) {
     const int c = it->second.first;

@@ -5,19 +5,23 @@
 
 namespace fc {
 
-// Forms T->so from the H-bar blocks (building those first if needed).
-void prep_sigma_ops(fc_ctx ctx, fc_ints I, fc_amps T);
+// Forms T->so from the H-bar blocks (building those first if needed); with `left`, also the two
+// matrices of the left products.
+void prep_sigma_ops(fc_ctx ctx, fc_ints I, fc_amps T, bool left = false);
 
-// sigma = H-bar R for a set of instances, each with its own block of trial vectors, as one
-// sequence of four launches shared by every instance: unpack r_ij^a, one grouped launch of the
-// products that read R only, one of the products that need X_e, and a pack that applies P(ij).
+// sigma = H-bar R (or the left product R H-bar) for a set of instances, each with its own block of
+// trial vectors, as one sequence of four launches shared by every instance: unpack r_ij^a, one
+// grouped launch of the products that read R only, one of the products that need X_e (or its left
+// counterpart Z_e), and a pack that applies P(ij).
 // The launch plans live at fixed device addresses and are rewritten before every call, so with
 // `graph` the sequence is captured once into a HIP graph and replayed for any vector counts up to
 // the kmax given at construction.  Buffers for kmax vectors per instance are held for the
 // object's lifetime; calls are ordered on the context stream.
 class SigmaBatch {
  public:
-  SigmaBatch(fc_ctx ctx, int nb, const fc_ints* I, const fc_amps* T, const long* kmax, bool graph);
+  // left: row vectors times H-bar (Eq. 19-20) instead of H-bar times column vectors (Eq. 18)
+  SigmaBatch(fc_ctx ctx, int nb, const fc_ints* I, const fc_amps* T, const long* kmax, bool graph,
+             bool left = false);
   ~SigmaBatch();
   SigmaBatch(const SigmaBatch&) = delete;
   SigmaBatch& operator=(const SigmaBatch&) = delete;
@@ -39,7 +43,7 @@ class SigmaBatch {
   std::vector<fc_amps> T_;
   std::vector<long> kmax_;
   std::vector<ZTensor> r2_, Y_, x_, s2b_;
-  bool graph_;
+  bool graph_, left_;
   bool configured_ = false;
   GroupTiling tl1_, tl2_;
   char* host_ = nullptr;

@@ -34,6 +34,10 @@ struct SigmaOps {
   fc::ZTensor B2;    // [o + v][(p, a)]: rows m: -W_maij; rows o + e: t_ij^ae
   fc::DBuf pairs;    // int2 (i, j) of each pair index
   bool ready = false;
+  // left sigma (row vector times H-bar), formed on first use:
+  fc::ZTensor BL1;   // [dim][o]: rows i < o: B1[m][i]; rows o + c: B2[m][c]   (t_m = sum_x Y[x] BL1[x][m])
+  fc::ZTensor BL2;   // [o + v][(q, f)]: rows i: B1[o + (q, f)][i]; rows o + e: Xop[(q, f)][e]
+  bool left_ready = false;
 };
 
 struct fc_amps_s {
@@ -60,7 +64,12 @@ void learn_samples(fc_ctx ctx, fc_ints I, const z* t2, const z* r2, const z* r2p
                    long nsamp, unsigned long long seed, float* X, float* q, float* r);
 // fc_eom.hip
 void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T);
-void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S);
+// left: S = R H-bar (rows of R are left vectors) instead of S = H-bar R
+void sigma_dev(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const z* R, z* S, bool left = false);
+// fc_aocd.hip
+int cd_pivoted_dev(fc_ctx ctx, long m, const double* M, double tau, int max_vec, double* L, int* nvec,
+                   int* piv_host);
+void ao_to_spinor_dev(fc_ctx ctx, long nvec, long nao, long n, const double* Lao, const z* C, z* Lmo);
 // fc_linalg.cpp (host FP64)
 void herm_eig(int n, std::vector<z>& A, std::vector<double>& w);           // A -> eigenvectors (columns)
 void gen_eig(int n, const std::vector<z>& A, std::vector<z>& w, std::vector<z>& VR);

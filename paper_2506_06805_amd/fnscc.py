@@ -52,6 +52,8 @@ _sig = {
     "fc_autotune_save": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_load": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_size": (C.c_int, [P]),
+    "cd_ao_pivoted": (C.c_int, [P, C.c_long, P, C.c_double, C.c_int, P, C.POINTER(C.c_int), P]),
+    "ao_to_spinor": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, P, P]),
     "cd_integrals": (C.c_int, [P, C.c_int, C.c_int, C.c_int, P, P, C.c_int, C.c_int, C.c_int, C.POINTER(P)]),
     "fc_ints_info": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "fc_free_ints": (None, [P]),
@@ -68,6 +70,8 @@ _sig = {
     "ipeom_sigma": (C.c_int, [P, P, P, C.c_int, P, P]),
     "fc_eom_default_opts": (None, [C.POINTER(EomOpts)]),
     "ipeom_davidson": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P), P, C.POINTER(EomOpts), P, P, P]),
+    "ipeom_sigma_left": (C.c_int, [P, P, P, C.c_int, P, P]),
+    "ipeom_left": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(P), P, C.POINTER(EomOpts), P, P, P, P, P]),
     "fc_mlp_create": (C.c_int, [P, P, C.c_ulonglong, C.POINTER(P)]),
     "fc_mlp_free": (None, [P]),
     "fc_mlp_num_params": (C.c_long, []),
@@ -252,6 +256,43 @@ class Amps(_Handle):
         return t1, t2
 
 
+def cd_ao_pivoted(ctx: Context, M, tau, max_vec, allow_cap=False):
+    """Pivoted Cholesky of the symmetric PSD supermatrix M (m x m float64 device tensor), Eq. 21.
+
+    Returns (L (nvec x m device tensor), pivots (numpy int32))."""
+    torch = ctx.torch
+    if M.dtype != torch.float64 or M.dim() != 2 or M.shape[0] != M.shape[1] or M.device.type != "cuda":
+        raise ValueError("cd_ao_pivoted: M must be a square float64 GPU tensor")
+    M = M.contiguous()
+    m = M.shape[0]
+    max_vec = int(min(max_vec, m))
+    L = torch.empty((max_vec, m), dtype=torch.float64, device=M.device)
+    nv = C.c_int()
+    piv = np.zeros(max_vec, dtype=np.int32)
+    rc = lib.cd_ao_pivoted(ctx.h, m, _ptr(M), float(tau), max_vec, _ptr(L), C.byref(nv), piv.ctypes.data)
+    if rc == FC_ENOCONV and allow_cap:
+        rc = FC_OK
+    ctx.check(rc, "cd_ao_pivoted")
+    return L[:nv.value], piv[:nv.value]
+
+
+def ao_to_spinor(ctx: Context, Lao, Cspin, nao):
+    """Spinor-basis vectors L^P_pq (nvec x n x n complex128) from real AO vectors (nvec x nao^2) and
+    two-component coefficients Cspin (2 nao x n complex128), Eq. 22."""
+    torch = ctx.torch
+    Lao = Lao.contiguous()
+    Cspin = Cspin.contiguous()
+    nvec = Lao.shape[0]
+    n = Cspin.shape[1]
+    if Lao.dtype != torch.float64 or Lao.numel() != nvec * nao * nao:
+        raise ValueError("ao_to_spinor: Lao must be nvec x nao^2 float64")
+    if Cspin.dtype != torch.complex128 or Cspin.shape[0] != 2 * nao:
+        raise ValueError("ao_to_spinor: C must be 2 nao x n complex128")
+    out = torch.empty((nvec, n, n), dtype=torch.complex128, device=Lao.device)
+    ctx.check(lib.ao_to_spinor(ctx.h, nvec, nao, n, _ptr(Lao), _ptr(Cspin), _ptr(out)), "ao_to_spinor")
+    return out
+
+
 def cd_integrals(ctx: Context, eps, L, o, precision="fp64"):
     """Stage Cholesky vectors L[P, p, q] (numpy host array or torch device tensor) and build integrals."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
@@ -373,6 +414,17 @@ def ipeom_sigma(ctx: Context, ints: Ints, amps: Amps, R):
     return S
 
 
+def ipeom_sigma_left(ctx: Context, ints: Ints, amps: Amps, Y):
+    """Rows of Y times the IP-EOM-CCSD matrix (the left product of Eq. 19-20)."""
+    torch = ctx.torch
+    Y = Y.contiguous()
+    if Y.dim() == 1:
+        Y = Y[None]
+    S = torch.empty_like(Y)
+    ctx.check(lib.ipeom_sigma_left(ctx.h, ints.h, amps.h, Y.shape[0], _ptr(Y), _ptr(S)), "ipeom_sigma_left")
+    return S
+
+
 def eom_opts(**kw):
     op = EomOpts()
     lib.fc_eom_default_opts(C.byref(op))
@@ -409,6 +461,41 @@ def ipeom_davidson(ctx: Context, ints, amps, nroots, want_vectors=False, allow_n
         vecs = Rout.view(nr[0], il[0].dim) if want_vectors else None
         return (w, int(its[0]), vecs) if want_vectors else (w, int(its[0]))
     return (w, its, Rout) if want_vectors else (w, its)
+
+
+def ipeom_left(ctx: Context, ints, amps, nroots, R, allow_noconv=False, **kw):
+    """Left eigenvectors dual to the right eigenvectors R of ipeom_davidson (Eq. 19-20).
+
+    Returns (omega_left, iters, L, weight): L has the layout of R with sum_x L_k[x] R_l[x] = delta_kl,
+    weight[k] = sum_i l^i_k r_{k,i} (complex)."""
+    torch = ctx.torch
+    single = isinstance(ints, Ints)
+    il = [ints] if single else list(ints)
+    al = [amps] if single else list(amps)
+    nr = [nroots] * len(il) if isinstance(nroots, int) else list(nroots)
+    nb = len(il)
+    total = sum(k * x.dim for k, x in zip(nr, il))
+    R = R.contiguous().reshape(-1)
+    if R.dtype != torch.complex128 or R.numel() != total or R.device.type != "cuda":
+        raise ValueError(f"ipeom_left: R must be {total} complex128 entries on the GPU")
+    ai = (P * nb)(*[x.h for x in il])
+    aa = (P * nb)(*[x.h for x in al])
+    nra = np.array(nr, dtype=np.int32)
+    om = np.zeros(2 * sum(nr))
+    wt = np.zeros(2 * sum(nr))
+    its = np.zeros(nb, dtype=np.int32)
+    L = torch.empty(total, dtype=torch.complex128, device=f"cuda:{ctx.device}")
+    op = eom_opts(**kw)
+    rc = lib.ipeom_left(ctx.h, nb, ai, aa, nra.ctypes.data, C.byref(op), _ptr(R), om.ctypes.data, _ptr(L),
+                        wt.ctypes.data, its.ctypes.data)
+    if rc == FC_ENOCONV and allow_noconv:
+        rc = FC_OK
+    ctx.check(rc, "ipeom_left")
+    w = om[0::2] + 1j * om[1::2]
+    weight = wt[0::2] + 1j * wt[1::2]
+    if single:
+        return w, int(its[0]), L.view(nr[0], il[0].dim), weight
+    return w, its, L, weight
 
 
 # ------------------------------------------------------------------------------ learned update

@@ -9,6 +9,9 @@ hot path uses, next to torch's complex128 matmul.
 
 `python -m paper_2506_06805_amd.profiling fns-presets` runs the paper's frozen-natural-spinor presets
 against the untruncated solve on the FNS-structured generator.
+
+`python -m paper_2506_06805_amd.profiling ao-cd` times the pivoted Cholesky of a synthetic AO
+supermatrix and the two-component transform of its vectors on the device.
 """
 from __future__ import annotations
 
@@ -115,6 +118,59 @@ def fns_presets(o: int, v: int, ncd: int, gamma: float, roots: int, seed: int) -
                           "max_abs_dIP_eV": float(np.abs(w - w_ref).max() * 27.211386)}), flush=True)
 
 
+def ao_cd(nao: int, rank: int, n: int, tau: float, reps: int, seed: int) -> None:
+    """Pivoted Cholesky (Eq. 21) of an nao^2 x nao^2 synthetic supermatrix and the transform
+    (Eq. 22) of its vectors to n spinors.  Algorithmic bytes of the Cholesky: step j reads the j
+    earlier vectors and the pivot row of M, reads and writes the diagonal and writes the new
+    vector, (j + 4) m doubles.  Algorithmic flops of the transform: 2 nvec nao^2 (2n) real
+    multiply-adds of the real AO vectors with the complex coefficients (4 flop each as complex
+    products with one real factor) and 8 nvec n^2 (2 nao) for the complex products."""
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import fnscc, synth
+
+    ctx = fnscc.Context(0)
+    m = nao * nao
+    w, X = synth.make_ao_eri_factors(nao, rank, seed)
+    Xd = torch.from_numpy(X).cuda()
+    M = synth.symmetrize_eri((Xd.T * torch.from_numpy(w).cuda()) @ Xd, nao)
+    del Xd
+    Cs = torch.from_numpy(synth.make_spinor_coefficients(nao, n, seed + 1)).cuda()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    fnscc.cd_ao_pivoted(ctx, M, tau, 4 * rank)       # warm-up
+    tcd = []
+    for _ in range(reps):
+        t, (L, piv) = timed(lambda: fnscc.cd_ao_pivoted(ctx, M, tau, 4 * rank))
+        tcd.append(t)
+    nvec = L.shape[0]
+    cd_bytes = 8.0 * m * sum(j + 4 for j in range(nvec))
+    fnscc.ao_to_spinor(ctx, L, Cs, nao)              # warm-up
+    ttr = []
+    for _ in range(reps):
+        t, Lmo = timed(lambda: fnscc.ao_to_spinor(ctx, L, Cs, nao))
+        ttr.append(t)
+    tr_flop = 4.0 * nvec * nao * nao * 2 * n + 8.0 * nvec * n * n * 2 * nao
+    t_cd, t_tr = min(tcd), min(ttr)
+    print(json.dumps({"nao": nao, "m": m, "rank": rank, "tau": tau, "nvec": nvec, "n_spinors": n,
+                      "cd_s": round(t_cd, 5), "cd_algorithmic_bytes": cd_bytes,
+                      "cd_GBps": round(cd_bytes / t_cd / 1e9, 1), "cd_frac_of_hbm": round(cd_bytes / t_cd / 8e12, 3),
+                      "transform_s": round(t_tr, 5), "transform_flop": tr_flop,
+                      "transform_TFLOPs": round(tr_flop / t_tr / 1e12, 2),
+                      "transform_frac_of_fp64_peak": round(tr_flop / t_tr / 78.6e12, 3),
+                      "max_abs_imag_diag": float(torch.diagonal(Lmo, dim1=1, dim2=2).imag.abs().max())}),
+          flush=True)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -129,6 +185,13 @@ def main() -> None:
     f.add_argument("--gamma", type=float, default=6.0)
     f.add_argument("--roots", type=int, default=8)
     f.add_argument("--seed", type=int, default=5000)
+    a = sub.add_parser("ao-cd")
+    a.add_argument("--nao", type=int, default=200)
+    a.add_argument("--rank", type=int, default=1000)
+    a.add_argument("--n", type=int, default=300)
+    a.add_argument("--tau", type=float, default=1e-6)
+    a.add_argument("--reps", type=int, default=3)
+    a.add_argument("--seed", type=int, default=6000)
     args = ap.parse_args()
     if args.cmd == "copy":
         copy_probe(args.mib)
@@ -136,6 +199,8 @@ def main() -> None:
         gemm_probe(args.reps)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
+    elif args.cmd == "ao-cd":
+        ao_cd(args.nao, args.rank, args.n, args.tau, args.reps, args.seed)
 
 
 if __name__ == "__main__":

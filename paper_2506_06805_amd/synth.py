@@ -161,10 +161,20 @@ def make_ao_eri(nao: int, rank: int, seed: int) -> np.ndarray:
 
     M = sum_k w_k x_k x_k^T with x_k a random real symmetric nao x nao matrix (flattened) and
     decaying weights w_k = exp(-3 k / rank): positive semi-definite, rank <= rank, and with the
-    permutational symmetry (mu nu | ka la) = (nu mu | ka la) = (ka la | mu nu).
+    permutational symmetry (mu nu | ka la) = (nu mu | ka la) = (ka la | mu nu) exact to the bit.
     """
     w, X = make_ao_eri_factors(nao, rank, seed)
-    return (X.T * w) @ X
+    return symmetrize_eri((X.T * w) @ X, nao)
+
+
+def symmetrize_eri(M, nao: int):
+    """Average M over (mu nu) <-> (nu mu), (ka la) <-> (la ka) and bra <-> ket so that the
+    permutational symmetry holds bit for bit (numpy arrays or torch tensors)."""
+    M4 = M.reshape(nao, nao, nao, nao)
+    M4 = 0.5 * (M4 + M4.swapaxes(0, 1))
+    M4 = 0.5 * (M4 + M4.swapaxes(2, 3))
+    M2 = M4.reshape(nao * nao, nao * nao)
+    return 0.5 * (M2 + M2.swapaxes(0, 1))
 
 
 def make_ao_eri_factors(nao: int, rank: int, seed: int):

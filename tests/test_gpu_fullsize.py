@@ -5,7 +5,9 @@ configuration), checked against the oracle where the oracle can afford it:
   one row at a time), with and without T1 dressing;
 * the correlation energy expression at the GPU's converged amplitudes;
 * every GPU eigenpair against the oracle's H-bar built from those amplitudes;
-* the mixed-precision path against the FP64 path (|dIP| <= 1e-5 Eh).
+* the mixed-precision path against the FP64 path (|dIP| <= 1e-5 Eh);
+* the left eigenvectors (Eq. 19-20): biorthonormality and the left residual projected on random
+  probes through the oracle's matrix-free right product.
 """
 import numpy as np
 import pytest
@@ -30,8 +32,13 @@ def c2(gpu_ctx):
     e, it, amps = fnscc.ccsd_solve(gpu_ctx, ints)
     w, its, X = fnscc.ipeom_davidson(gpu_ctx, ints, amps, k, want_vectors=True)
     t1, t2 = amps.read()
-    return dict(inst=inst, L=L, ints=ints, e=e, w=w, k=k, X=X.cpu().numpy().reshape(k, -1),
+    return dict(inst=inst, L=L, ints=ints, amps=amps, e=e, w=w, k=k, Xd=X, X=X.cpu().numpy().reshape(k, -1),
                 t1=t1.cpu().numpy(), t2=t2.cpu().numpy(), g=integrals.Blocks(inst.L, o))
+
+
+@pytest.fixture(scope="module")
+def hbar(c2):
+    return eom.Hbar(c2["g"], c2["inst"].eps, c2["t1"], c2["t2"])
 
 
 @pytest.mark.parametrize("dressed", [False, True])
@@ -64,9 +71,8 @@ def test_energy_expression_full_size(c2):
     assert abs(e - c2["e"]) < 1e-10
 
 
-def test_eigenpairs_against_oracle_hbar_full_size(c2):
-    h = eom.Hbar(c2["g"], c2["inst"].eps, c2["t1"], c2["t2"])
-    S = eom.sigma(h, c2["X"])
+def test_eigenpairs_against_oracle_hbar_full_size(c2, hbar):
+    S = eom.sigma(hbar, c2["X"])
     for r in range(c2["k"]):
         x = c2["X"][r]
         res = np.linalg.norm(S[r] - c2["w"][r] * x) / np.linalg.norm(x)
@@ -81,3 +87,20 @@ def test_mixed_path_within_1e5_full_size(gpu_ctx, c2):
     w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, c2["k"])
     assert np.abs(np.sort_complex(w) - np.sort_complex(c2["w"])).max() < 1e-5
     assert abs(e - c2["e"]) < 1e-5
+
+
+def test_left_vectors_full_size(gpu_ctx, c2, hbar):
+    # (L_k H - w_k L_k) . p for random probes p, with H p from the oracle's matrix-free product, is a
+    # random projection of the left residual: E|res . p|^2 = 2 |res|^2 for unit complex normals
+    from paper_2506_06805_amd import fnscc
+    k = c2["k"]
+    w_l, _, L, wt = fnscc.ipeom_left(gpu_ctx, c2["ints"], c2["amps"], k, c2["Xd"])
+    assert np.abs(w_l - c2["w"]).max() < 1e-8
+    Lh, Rh = L.cpu().numpy(), c2["X"]
+    assert np.abs(Lh @ Rh.T - np.eye(k)).max() < 1e-9
+    o = c2["inst"].o
+    assert np.abs(wt - np.einsum("ki,ki->k", Lh[:, :o], Rh[:, :o])).max() < 1e-12
+    rng = np.random.default_rng(37)
+    P = rng.standard_normal((3, Rh.shape[1])) + 1j * rng.standard_normal((3, Rh.shape[1]))
+    proj = Lh @ eom.sigma(hbar, P).T - w_l[:, None] * (Lh @ P.T)
+    assert (np.abs(proj) / np.linalg.norm(Lh, axis=1)[:, None]).max() < 1e-6
