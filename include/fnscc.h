@@ -195,8 +195,9 @@ int ipeom_davidson(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, co
  * the same batched Davidson on the transposed problem; L is then replaced by O^-1 L with
  * O = L R^T, which also handles degenerate roots.
  * R: device, sum(nroots) x dim_b right eigenvectors as returned by ipeom_davidson (same nb,
- * ints, t and nroots; read only).  omega: host, sum(nroots) x 2 doubles, the left eigenvalues
- * (equal to the right ones within the solver tolerance).  L_out: device, sum(nroots) x dim_b.
+ * ints, t and nroots; read only).  omega: host, sum(nroots) x 2 doubles: for right root k, the
+ * eigenvalue of the left root that overlaps it most (equal to the right eigenvalue within the
+ * solver tolerance).  L_out: device, sum(nroots) x dim_b, row k dual to right root k.
  * weight: host, sum(nroots) x 2 doubles, the one-hole part sum_i l^i_k r_{k,i} of the
  * normalisation (the ionisation strength of root k when ground-state relaxation is neglected).
  * iters: host, nb ints, or NULL.  FC_ENUMERIC when the left and right roots do not pair up

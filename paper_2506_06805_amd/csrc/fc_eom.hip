@@ -687,6 +687,17 @@ int left_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, con
       }
     }
     FC_REQUIRE(big < 1e6, FC_ENUMERIC, "ipeom_left: left and right vectors belong to different roots");
+    // report for right root k the eigenvalue of the left root that overlaps it most (the two
+    // solves may order nearly equal real parts differently)
+    std::vector<z> wl(omega + off, omega + off + k);
+    for (int c = 0; c < k; ++c) {
+      int best = c;
+      for (int r = 0; r < k; ++r)
+        if (std::hypot(Oh[(size_t)r * k + c].x, Oh[(size_t)r * k + c].y) >
+            std::hypot(Oh[(size_t)best * k + c].x, Oh[(size_t)best * k + c].y))
+          best = r;
+      omega[off + c] = wl[best];
+    }
     FC_HIP(hipMemcpyAsync(Oi.p, inv.data(), sizeof(z) * k * k, hipMemcpyHostToDevice, ctx->stream));
     zgemm(ctx, 'N', 'N', k, dim, k, one, Oi.as<z>(), k, Lb, dim, zero, Ln.as<z>(), dim);
     FC_HIP(hipMemcpyAsync(Lb, Ln.p, sizeof(z) * (size_t)k * dim, hipMemcpyDeviceToDevice, ctx->stream));

@@ -449,6 +449,13 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
     g.part = work.as<z>();
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit, (unsigned)batch);
+  // FNSCC_VERBOSE >= 3: every product is timed on its own (synchronising) and logged
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->verbose >= 3) {
+    FC_HIP(hipEventCreate(&e0));
+    FC_HIP(hipEventCreate(&e1));
+    FC_HIP(hipEventRecord(e0, ctx->stream));
+  }
   if (lep) launch_cfg<1, double>(cfg, g, ta, tb, grid, ctx->stream);
   else if (ctx->gemm_fp32) launch_cfg<0, float>(cfg, g, ta, tb, grid, ctx->stream);
   else launch_cfg<0, double>(cfg, g, ta, tb, grid, ctx->stream);
@@ -458,6 +465,18 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
     unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 255) / 256));
     k_splitk_reduce<<<nb, 256, 0, ctx->stream>>>(g.part, (int)ksplit, M, N, C, ldc, alpha, beta);
     FC_HIP(hipGetLastError());
+  }
+  if (e0) {
+    FC_HIP(hipEventRecord(e1, ctx->stream));
+    FC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double fl = 8.0 * M * N * K * batch;
+    fprintf(stderr, "[gemm] %c%c M %ld N %ld K %ld batch %d cfg %d ksplit %ld %s %.3f ms %.1f TF/s\n", opA, opB,
+            M, N, K, batch, cfg, ksplit, lep ? "ladder" : ctx->gemm_fp32 ? "fp32" : "fp64", ms,
+            fl / (ms * 1e-3) / 1e12);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   }
 }
 

@@ -12,6 +12,9 @@ against the untruncated solve on the FNS-structured generator.
 
 `python -m paper_2506_06805_amd.profiling ao-cd` times the pivoted Cholesky of a synthetic AO
 supermatrix and the two-component transform of its vectors on the device.
+
+`python -m paper_2506_06805_amd.profiling sigma` times the right and left IP-EOM sigma products for
+blocks of k trial vectors against the FP64 matrix-core peak.
 """
 from __future__ import annotations
 
@@ -171,6 +174,47 @@ def ao_cd(nao: int, rank: int, n: int, tau: float, reps: int, seed: int) -> None
           flush=True)
 
 
+def sigma_flops(o: int, v: int, k: int) -> float:
+    """Algorithmic flops of one sigma product for k vectors (8 per complex multiply-add): the 1h
+    block R B1, the ring product over the unpacked r_im^e, X_e, F_ae, the pair mixing and
+    [r_m | X_e] B2 (the left product has the same shapes transposed)."""
+    no = o * (o - 1) // 2
+    dim = o + no * v
+    return 8.0 * k * (dim * o + o ** 3 * v ** 2 + 2 * no * v * v + no * no * v + (o + v) * no * v)
+
+
+def sigma_probe(o: int, v: int, ncd: int, ks, reps: int, seed: int) -> None:
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import fnscc, synth
+
+    ctx = fnscc.Context(0)
+    inst = synth.make_instance(o, v, ncd, seed=seed, kappa=synth.kappa_for(v, ncd))
+    ints = fnscc.cd_integrals(ctx, inst.eps, torch.from_numpy(inst.L).cuda(), o)
+    _, _, amps = fnscc.ccsd_solve(ctx, ints)
+    dim = o + o * (o - 1) // 2 * v
+    rng = np.random.default_rng(seed)
+    for k in ks:
+        R = torch.from_numpy(rng.standard_normal((k, dim)) + 1j * rng.standard_normal((k, dim))).cuda()
+        for name, fn in (("right", fnscc.ipeom_sigma), ("left", fnscc.ipeom_sigma_left)):
+            fn(ctx, ints, amps, R)                     # operators built, warm-up
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn(ctx, ints, amps, R)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = min(ts)
+            f = sigma_flops(o, v, k)
+            print(json.dumps({"sigma": name, "o": o, "v": v, "k": k, "ms": round(t * 1e3, 3), "flop": f,
+                              "TFLOPs": round(f / t / 1e12, 2), "frac_of_fp64_peak": round(f / t / 78.6e12, 3)}),
+                  flush=True)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -192,6 +236,13 @@ def main() -> None:
     a.add_argument("--tau", type=float, default=1e-6)
     a.add_argument("--reps", type=int, default=3)
     a.add_argument("--seed", type=int, default=6000)
+    q = sub.add_parser("sigma")
+    q.add_argument("--o", type=int, default=24)
+    q.add_argument("--v", type=int, default=160)
+    q.add_argument("--ncd", type=int, default=500)
+    q.add_argument("--ks", type=str, default="1,8,16,32")
+    q.add_argument("--reps", type=int, default=5)
+    q.add_argument("--seed", type=int, default=1001)
     args = ap.parse_args()
     if args.cmd == "copy":
         copy_probe(args.mib)
@@ -199,6 +250,8 @@ def main() -> None:
         gemm_probe(args.reps)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
+    elif args.cmd == "sigma":
+        sigma_probe(args.o, args.v, args.ncd, [int(x) for x in args.ks.split(",")], args.reps, args.seed)
     elif args.cmd == "ao-cd":
         ao_cd(args.nao, args.rank, args.n, args.tau, args.reps, args.seed)
 
