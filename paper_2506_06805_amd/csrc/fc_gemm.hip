@@ -257,7 +257,11 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T>
 __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   __shared__ TileSmem<BM, BN, BK, T> sm;
-  const long tile = xcd_tile(blockIdx.x, g.tiles);   // the grid is padded to a multiple of 8
+  // The x extent is a multiple of 8, so a workgroup runs on XCD blockIdx.x % 8 whatever its split
+  // (y) and batch (z) index.  Rotating x by those indices spreads the splits and batch entries
+  // of a product with few tiles over all XCDs instead of stacking them on the XCD of tile 0.
+  const long bx = ((long)blockIdx.x + blockIdx.y + (long)gridDim.y * blockIdx.z) % gridDim.x;
+  const long tile = xcd_tile(bx, g.tiles);
   if (tile >= g.tiles) return;
   const long ntn = (g.N + BN - 1) / BN;
   long mi = tile / ntn;
@@ -288,23 +292,53 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
 }
 
-// C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic)
-__global__ void k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N, z* __restrict__ C, long ldc,
-                                z alpha, z beta) {
+// C = alpha * sum_s P[s] + beta * C.  Lane x of a workgroup owns output t = 64 b + x; its W waves
+// take the splits s = w, w + W, ... in ascending order (two running sums each) and wave 0 adds
+// the W results in wave order.  The order depends only on (ns, W), so results repeat bit for bit,
+// and many splits of a small output are summed by W waves at once instead of one serial loop.
+template <int W>
+__global__ void __launch_bounds__(64 * W) k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N,
+                                                          z* __restrict__ C, long ldc, z alpha, z beta) {
+  __shared__ z acc[W][64];
   const long MN = M * N;
   const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < MN; t += (long)gridDim.x * blockDim.x) {
-    double re = 0, im = 0;
-    for (int s = 0; s < ns; ++s) { z p = P[s * MN + t]; re += p.x; im += p.y; }
-    long m = t / N, n = t % N;
-    z out = make_double2(alpha.x * re - alpha.y * im, alpha.x * im + alpha.y * re);
-    if (use_beta) {
-      z c0 = C[m * ldc + n];
-      out.x += beta.x * c0.x - beta.y * c0.y;
-      out.y += beta.x * c0.y + beta.y * c0.x;
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  for (long base = blockIdx.x * 64L; base < MN; base += (long)gridDim.x * 64) {
+    const long t = base + lane;
+    double re0 = 0, im0 = 0, re1 = 0, im1 = 0;
+    if (t < MN) {
+      int s = w;
+      for (; s + W < ns; s += 2 * W) {
+        const z p = P[s * MN + t], q = P[(s + W) * MN + t];
+        re0 += p.x; im0 += p.y;
+        re1 += q.x; im1 += q.y;
+      }
+      if (s < ns) { const z p = P[s * MN + t]; re0 += p.x; im0 += p.y; }
     }
-    C[m * ldc + n] = out;
+    acc[w][lane] = make_double2(re0 + re1, im0 + im1);
+    __syncthreads();
+    if (w == 0 && t < MN) {
+      double re = 0, im = 0;
+      for (int q = 0; q < W; ++q) { re += acc[q][lane].x; im += acc[q][lane].y; }
+      const long m = t / N, n = t % N;
+      z out = make_double2(alpha.x * re - alpha.y * im, alpha.x * im + alpha.y * re);
+      if (use_beta) {
+        const z c0 = C[m * ldc + n];
+        out.x += beta.x * c0.x - beta.y * c0.y;
+        out.y += beta.x * c0.y + beta.y * c0.x;
+      }
+      C[m * ldc + n] = out;
+    }
+    __syncthreads();
   }
+}
+
+void splitk_reduce(hipStream_t st, const z* part, long ns, long M, long N, z* C, long ldc, z alpha, z beta) {
+  const long MN = M * N;
+  const unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 63) / 64));
+  if (ns >= 64) k_splitk_reduce<16><<<nb, 64 * 16, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
+  else if (ns >= 8) k_splitk_reduce<4><<<nb, 64 * 4, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
+  else k_splitk_reduce<1><<<nb, 64, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
 }
 
 template <int BM, int BN, int WGM, int WGN, int BK, int EPI, typename T>
@@ -317,9 +351,13 @@ void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
 }
 
 // Tile configurations: 64 x 64 (4 waves), 128 x 64 (4 waves) and 128 x 128 (8 waves), each with
-// K slices of 8 (configurations 0-2) or 16 (3-5) complex elements per pipeline step.
-constexpr int NCFG = 6;
-constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128}, CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128};
+// K slices of 8 (configurations 0-2) or 16 (3-5) complex elements per pipeline step; 128 x 96
+// (4 waves of 64 x 48, configuration 6) for outputs about 300 columns wide, whose 64- and 128-wide
+// tiles leave up to a third of the last column of tiles idle; 32 x 32 (one wave, configuration 7)
+// for outputs of a few hundred elements with long K, which a 64 x 64 tile would mostly pad.
+constexpr int NCFG = 8;
+constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32},
+              CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32};
 
 template <int EPI, typename T>
 void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
@@ -329,7 +367,9 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
     case 2: launch<128, 128, 2, 4, 8, EPI, T>(g, ta, tb, grid, s); break;
     case 3: launch<64, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s); break;
     case 4: launch<128, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s); break;
-    default: launch<128, 128, 2, 4, 16, EPI, T>(g, ta, tb, grid, s); break;
+    case 5: launch<128, 128, 2, 4, 16, EPI, T>(g, ta, tb, grid, s); break;
+    case 6: launch<128, 96, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
+    default: launch<32, 32, 1, 1, 8, EPI, T>(g, ta, tb, grid, s); break;
   }
 }
 
@@ -348,8 +388,14 @@ std::string bucket(char opA, char opB, long M, long N, long K, int batch, const 
 }
 
 int heuristic_cfg(long M, long N, int batch) {
+  if (M <= 32 && N <= 32) return 7;
+  if (M >= 1024 && N > 192 && N <= 288) return 6;
   const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * (long)batch >= 512;
   return big ? 2 : 0;
+}
+// A configuration fits a product when its tile is not larger than the padded output needs.
+bool cfg_fits(int c, long M, long N) {
+  return (CFG_BM[c] <= 64 || M >= 128) && (CFG_BN[c] <= 64 || N >= 96);
 }
 
 void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B,
@@ -361,7 +407,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
     const char* e = getenv("FNSCC_GEMM_CFG");   // tuning override: one configuration for every product
     return e ? atoi(e) : -1;
   }();
-  if (forced >= 0 && forced < NCFG && (CFG_BM[forced] == 64 || M >= 128) && (CFG_BN[forced] == 64 || N >= 128)) {
+  if (forced >= 0 && forced < NCFG && cfg_fits(forced, M, N)) {
     cfg = forced;
   } else if (ctx->autotune && K > 0) {
     const std::string key = bucket(opA, opB, M, N, K, batch, lep, lep ? 0 : ctx->gemm_fp32);
@@ -379,8 +425,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
       float best = 1e30f;
       int bestc = cfg;
       for (int c = 0; c < NCFG; ++c) {
-        if (CFG_BM[c] > 64 && M < 128) continue;
-        if (CFG_BN[c] > 64 && N < 128) continue;
+        if (!cfg_fits(c, M, N)) continue;
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
           if (!lep && (beta.x != 0.0 || beta.y != 0.0))
@@ -461,9 +506,7 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   else launch_cfg<0, double>(cfg, g, ta, tb, grid, ctx->stream);
   FC_HIP(hipGetLastError());
   if (ksplit > 1) {
-    const long MN = M * N;
-    unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 255) / 256));
-    k_splitk_reduce<<<nb, 256, 0, ctx->stream>>>(g.part, (int)ksplit, M, N, C, ldc, alpha, beta);
+    splitk_reduce(ctx->stream, g.part, ksplit, M, N, C, ldc, alpha, beta);
     FC_HIP(hipGetLastError());
   }
   if (e0) {

@@ -110,9 +110,11 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
   const long ntn = (g.N + TN - 1) / TN;
-  // XCD x (= blockIdx.x % 8) walks the contiguous tiles [x * per, (x + 1) * per)
+  // XCD x (= blockIdx.x % 8) walks the contiguous tiles [x * per, (x + 1) * per); the split index
+  // rotates the slot so that the splits of one tile spread over all XCDs
   const long per = (g.tiles + 7) / 8;
-  const long tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const long bx = ((long)blockIdx.x + blockIdx.y) % gridDim.x;
+  const long tile = (bx & 7) * per + (bx >> 3);
   if (tile >= g.tiles) return;
   long mi = tile / ntn;
   if (EPI == 1 && g.ltri) {

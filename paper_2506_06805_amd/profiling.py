@@ -38,17 +38,22 @@ def copy_probe(mib: int) -> None:
 # the sigma ring product of a 6-vector block at o=24 v=200, and ladder contractions at o=24 and o=40
 GEMM_SHAPES = [("square4096", 4096, 4096, 4096, "N", "N"), ("assembly_T64", 10240, 10240, 500, "N", "T"),
                ("assembly_T32", 5120, 5120, 500, "N", "T"), ("ring_sigma", 144, 4800, 4800, "N", "N"),
-               ("contraction_o24", 12720, 276, 12720, "N", "T"), ("contraction_o40", 8000, 780, 20000, "N", "T")]
+               ("contraction_o24", 12720, 276, 12720, "N", "T"), ("contraction_o40", 8000, 780, 20000, "N", "T"),
+               ("ring_o24v160", 3840, 3840, 3840, "N", "N"), ("fmi_o24v160", 24, 24, 614400, "N", "T"),
+               ("fae_o24v160", 160, 160, 92160, "N", "N")]
 
 
-def gemm_probe(reps: int) -> None:
+def gemm_probe(reps: int, tune: bool = False) -> None:
     """TFLOP/s of the library's complex GEMM (FP64 and FP32 arithmetic) on the listed shapes, next
-    to torch's complex128 matmul on the same operands (a vendor-library reference point)."""
+    to torch's complex128 matmul on the same operands (a vendor-library reference point).  With
+    `tune` the library's autotuner times every tile configuration first and keeps the fastest."""
     import torch
 
     from . import fnscc
 
     ctx = fnscc.Context(0)
+    if tune:
+        ctx.set_autotune(True)
 
     def timed(fn):
         fn()
@@ -222,6 +227,7 @@ def main() -> None:
     c.add_argument("--mib", type=int, default=1024)
     g = sub.add_parser("gemm")
     g.add_argument("--reps", type=int, default=5)
+    g.add_argument("--tune", action="store_true")
     f = sub.add_parser("fns-presets")
     f.add_argument("--o", type=int, default=24)
     f.add_argument("--v", type=int, default=300)
@@ -247,7 +253,7 @@ def main() -> None:
     if args.cmd == "copy":
         copy_probe(args.mib)
     elif args.cmd == "gemm":
-        gemm_probe(args.reps)
+        gemm_probe(args.reps, args.tune)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
     elif args.cmd == "sigma":

@@ -17,7 +17,10 @@ def _rand(shape, rng):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 133, 37), (1, 300, 2000), (129, 65, 8), (256, 256, 513)])
+# shapes reach every tile configuration: 64 x 64 and 128 x 128 with and without split K, 128 x 96
+# (M >= 1024, N about 300) and 32 x 32 (tiny output, long K, many splits)
+@pytest.mark.parametrize("M,N,K", [(70, 133, 37), (1, 300, 2000), (129, 65, 8), (256, 256, 513),
+                                   (1100, 260, 200), (24, 20, 3000)])
 def test_zgemm_layouts(gpu_ctx, M, N, K):
     import torch
     from paper_2506_06805_amd import fnscc
@@ -45,7 +48,8 @@ def test_zgemm_deterministic(gpu_ctx):
     assert np.array_equal(c1, c2)
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 133, 37), (3, 200, 5000), (256, 256, 513)])
+@pytest.mark.parametrize("M,N,K", [(70, 133, 37), (3, 200, 5000), (256, 256, 513), (1100, 260, 200),
+                                   (24, 20, 3000)])
 def test_zgemm_fp32_arithmetic(gpu_ctx, M, N, K):
     # FP32 products and sums on FP64 data: error of order 2^-24 sqrt(K) of sum |a||b|
     import torch
