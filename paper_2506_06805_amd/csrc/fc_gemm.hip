@@ -387,11 +387,16 @@ std::string bucket(char opA, char opB, long M, long N, long K, int batch, const 
   return buf;
 }
 
-int heuristic_cfg(long M, long N, int batch) {
+// Default tile choice, from timing every configuration on the hot path's shapes: 32 x 32 for
+// tiny outputs; 128 x 128 when there are enough such tiles to fill the chip; otherwise 64 x 64,
+// with 16-element K slices in FP64 when K is long (skinny and split-K products), and 128 x 96 in
+// FP32 for outputs about 300 columns wide.
+int heuristic_cfg(long M, long N, long K, int batch, bool fp32) {
   if (M <= 32 && N <= 32) return 7;
-  if (M >= 1024 && N > 192 && N <= 288) return 6;
   const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * (long)batch >= 512;
-  return big ? 2 : 0;
+  if (big) return 2;
+  if (fp32) return (M >= 1024 && N > 192 && N <= 288) ? 6 : 0;
+  return K >= 2048 ? 3 : 0;
 }
 // A configuration fits a product when its tile is not larger than the padded output needs.
 bool cfg_fits(int c, long M, long N) {
@@ -402,7 +407,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
                 long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC, const LadderEpilogue* lep) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
-  int cfg = heuristic_cfg(M, N, batch);
+  int cfg = heuristic_cfg(M, N, K, batch, !lep && ctx->gemm_fp32);
   static const int forced = [] {
     const char* e = getenv("FNSCC_GEMM_CFG");   // tuning override: one configuration for every product
     return e ? atoi(e) : -1;

@@ -43,7 +43,7 @@ GEMM_SHAPES = [("square4096", 4096, 4096, 4096, "N", "N"), ("assembly_T64", 1024
                ("fae_o24v160", 160, 160, 92160, "N", "N")]
 
 
-def gemm_probe(reps: int, tune: bool = False) -> None:
+def gemm_probe(reps: int, tune: bool = False, save: str = "") -> None:
     """TFLOP/s of the library's complex GEMM (FP64 and FP32 arithmetic) on the listed shapes, next
     to torch's complex128 matmul on the same operands (a vendor-library reference point).  With
     `tune` the library's autotuner times every tile configuration first and keeps the fastest."""
@@ -79,6 +79,8 @@ def gemm_probe(reps: int, tune: bool = False) -> None:
         res["torch_complex128_tflops"] = fl / timed(lambda: torch.matmul(A, Bn, out=C)) / 1e9
         print(json.dumps({k: (round(x, 1) if isinstance(x, float) else x) for k, x in res.items()}), flush=True)
         del A, B, C, Bn
+    if tune and save:
+        ctx.autotune_save(save)
 
 
 # The paper's thresholds (Sec. 4.1): natural-spinor occupation and Cholesky threshold per preset.
@@ -228,6 +230,7 @@ def main() -> None:
     g = sub.add_parser("gemm")
     g.add_argument("--reps", type=int, default=5)
     g.add_argument("--tune", action="store_true")
+    g.add_argument("--save", type=str, default="", help="with --tune: write the tuned table to this file")
     f = sub.add_parser("fns-presets")
     f.add_argument("--o", type=int, default=24)
     f.add_argument("--v", type=int, default=300)
@@ -253,7 +256,7 @@ def main() -> None:
     if args.cmd == "copy":
         copy_probe(args.mib)
     elif args.cmd == "gemm":
-        gemm_probe(args.reps, args.tune)
+        gemm_probe(args.reps, args.tune, args.save)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
     elif args.cmd == "sigma":

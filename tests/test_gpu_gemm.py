@@ -17,10 +17,11 @@ def _rand(shape, rng):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
-# shapes reach every tile configuration: 64 x 64 and 128 x 128 with and without split K, 128 x 96
-# (M >= 1024, N about 300) and 32 x 32 (tiny output, long K, many splits)
+# shapes reach the default tile configurations: 64 x 64 with 8- and 16-element K slices, with and
+# without split K, and 32 x 32 (tiny output, long K, many splits); 128 x 128 and 128 x 96 (FP32)
+# in the tests below and in the solver tests
 @pytest.mark.parametrize("M,N,K", [(70, 133, 37), (1, 300, 2000), (129, 65, 8), (256, 256, 513),
-                                   (1100, 260, 200), (24, 20, 3000)])
+                                   (1100, 260, 200), (24, 20, 3000), (70, 90, 2100)])
 def test_zgemm_layouts(gpu_ctx, M, N, K):
     import torch
     from paper_2506_06805_amd import fnscc
