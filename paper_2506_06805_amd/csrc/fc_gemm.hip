@@ -393,7 +393,9 @@ std::string bucket(char opA, char opB, long M, long N, long K, int batch, const 
 // FP32 for outputs about 300 columns wide.
 int heuristic_cfg(long M, long N, long K, int batch, bool fp32) {
   if (M <= 32 && N <= 32) return 7;
-  const bool big = M >= 256 && N >= 256 && ((M + 127) / 128) * ((N + 127) / 128) * (long)batch >= 512;
+  const long t128 = ((M + 127) / 128) * ((N + 127) / 128), t64 = ((M + 63) / 64) * ((N + 63) / 64);
+  // 128 x 128 unless its padding costs a quarter more work than 64 x 64 tiles (e.g. 300 x 300)
+  const bool big = M >= 256 && N >= 256 && t128 * (long)batch >= 512 && 4 * t128 * 4 <= 5 * t64;
   if (big) return 2;
   if (fp32) return (M >= 1024 && N > 192 && N <= 288) ? 6 : 0;
   return K >= 2048 ? 3 : 0;
