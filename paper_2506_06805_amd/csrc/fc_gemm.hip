@@ -223,13 +223,30 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 #undef FC_STORE_TILE
 
   const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
+  // Ladder layout: off = ((a nB + b) v + e) v + f = (a nB v + e) v + (b v^2 + f) splits into a row
+  // part and a column part, each formed once per row or column of the lane with 32-bit division
+  // (a per-element 64-bit division cost more than a tenth of the assembly's time).
+  long coff[FJ];
+  if (EPI == 1) {
+    const unsigned lv = (unsigned)g.lv;
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+      const unsigned n = (unsigned)(n0 + wn + 16 * j + lr), b = n / lv;
+      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int j = 0; j < FJ; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const long m = m0 + wm + 16 * i + Mfma<T>::row(lk, r);
+      long roff = 0;
+      if (EPI == 1) {
+        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
+        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
+      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const long m = m0 + wm + 16 * i + Mfma<T>::row(lk, r);
+      for (int j = 0; j < FJ; ++j) {
         const long n = n0 + wn + 16 * j + lr;
         if (m >= g.M || n >= g.N) continue;
         const double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
@@ -237,13 +254,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
           g.part[m * g.N + n] = make_double2(re, im);
           continue;
         }
-        long off;
-        if (EPI == 1) {
-          const long a = m / g.lv, e = m % g.lv, b = n / g.lv, f = n % g.lv;
-          off = ((a * g.lnB + b) * g.lv + e) * g.lv + f;
-        } else {
-          off = m * g.ldc + n;
-        }
+        const long off = EPI == 1 ? roff + coff[j] : m * g.ldc + n;
         z out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
         if (use_beta) {
           z c0 = C[off];
@@ -252,6 +263,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
         }
         C[off] = out;
       }
+    }
 }
 
 template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T>
@@ -479,6 +491,7 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   const bool tb = (opB == 'T' || opB == 'C');
   FC_REQUIRE(batch <= 65535, FC_EARG, "zgemm: batch too large");
   FC_REQUIRE(cfg >= 0 && cfg < NCFG, FC_EARG, "zgemm: bad tile configuration");
+  FC_REQUIRE(!lep || (M < (1L << 31) && N < (1L << 31) && lep->v >= 1), FC_EARG, "zgemm: ladder product too large");
   const long bm = CFG_BM[cfg], bn = CFG_BN[cfg];
   const long tiles = ((N + bn - 1) / bn) * ((M + bm - 1) / bm);
   FC_REQUIRE(tiles < (1L << 30), FC_EARG, "zgemm: problem too large for one launch");

@@ -199,18 +199,34 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
 
   const int orow = 4 * (lane >> 4), ocol = lane & 15;
   const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
+  // ladder layout ((a nB + b) v + e) v + f as a row part plus a column part, one 32-bit division
+  // per row or column of the lane
+  long coff[2] = {0, 0};
+  if (EPI == 1) {
+    const unsigned lv = (unsigned)g.lv;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const unsigned n = (unsigned)(n0 + wn + 16 * j + ocol), b = n / lv;
+      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int r = 0; r < 4; ++r) {
+      const long m = m0 + wm + 16 * i + orow + r;
+      long roff = 0;
+      if (EPI == 1) {
+        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
+        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
+      }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        long m = m0 + wm + 16 * i + orow + r, n = n0 + wn + 16 * j + ocol;
+      for (int j = 0; j < 2; ++j) {
+        const long n = n0 + wn + 16 * j + ocol;
         if (m >= g.M || n >= g.N) continue;
         double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * g.inv_scale, imv = (double)im[i][j][r] * g.inv_scale;
         if (EPI == 1) {
-          const long a = m / g.lv, e = m % g.lv, b = n / g.lv, f = n % g.lv;
-          g.W[((a * g.lnB + b) * g.lv + e) * g.lv + f] = make_float2((float)re, (float)imv);
+          g.W[roff + coff[j]] = make_float2((float)re, (float)imv);
           continue;
         }
         if (g.part) {
@@ -225,6 +241,7 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
         }
         g.C[m * g.ldc + n] = out;
       }
+    }
 }
 
 __global__ void k_split_reduce(const z* __restrict__ P, int ns, long M, long N, z* __restrict__ C, long ldc, z alpha,
@@ -330,6 +347,7 @@ void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const 
   FC_REQUIRE(A.prec == B.prec && A.kp == B.kp, FC_EARG, "gemm_split_ladder: operand mismatch");
   FC_REQUIRE(a_row0 >= 0 && b_row0 >= 0 && a_row0 + M <= A.rows && b_row0 + N <= B.rows, FC_EARG,
              "gemm_split_ladder: row range outside operand");
+  FC_REQUIRE(M < (1L << 31) && N < (1L << 31) && lep.v >= 1, FC_EARG, "gemm_split_ladder: product too large");
   SArgs g;
   g.A = A.buf.as<u16>(); g.a_plane = A.rows_pad * A.kp; g.a_row0 = a_row0;
   g.B = B.buf.as<u16>(); g.b_plane = B.rows_pad * B.kp; g.b_row0 = b_row0;
