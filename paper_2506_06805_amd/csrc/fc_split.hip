@@ -105,8 +105,9 @@ __device__ inline f4 mma(const u16* a, const u16* b, f4 c) {
 
 template <int PREC, int EPI>
 __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
-  __shared__ __attribute__((aligned(16))) u16 sA[4][TM][LDK];
-  __shared__ __attribute__((aligned(16))) u16 sB[4][TN][LDK];
+  // double-buffered: 2 x 80 KB, the whole LDS of a CU
+  __shared__ __attribute__((aligned(16))) u16 sA[2][4][TM][LDK];
+  __shared__ __attribute__((aligned(16))) u16 sB[2][4][TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
   const long ntn = (g.N + TN - 1) / TN;
@@ -148,16 +149,16 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
     rb2 = *reinterpret_cast<const uint4*>(B + 2 * g.b_plane + goffB + (k0));                         \
     rb3 = *reinterpret_cast<const uint4*>(B + 3 * g.b_plane + goffB + (k0));                         \
   } while (0)
-#define FC_SSTORE()                                                                                  \
+#define FC_SSTORE(buf)                                                                               \
   do {                                                                                               \
-    *reinterpret_cast<uint4*>(&sA[0][srow][skc]) = ra0;                                              \
-    *reinterpret_cast<uint4*>(&sA[1][srow][skc]) = ra1;                                              \
-    *reinterpret_cast<uint4*>(&sA[2][srow][skc]) = ra2;                                              \
-    *reinterpret_cast<uint4*>(&sA[3][srow][skc]) = ra3;                                              \
-    *reinterpret_cast<uint4*>(&sB[0][srow][skc]) = rb0;                                              \
-    *reinterpret_cast<uint4*>(&sB[1][srow][skc]) = rb1;                                              \
-    *reinterpret_cast<uint4*>(&sB[2][srow][skc]) = rb2;                                              \
-    *reinterpret_cast<uint4*>(&sB[3][srow][skc]) = rb3;                                              \
+    *reinterpret_cast<uint4*>(&sA[buf][0][srow][skc]) = ra0;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][1][srow][skc]) = ra1;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][2][srow][skc]) = ra2;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][3][srow][skc]) = ra3;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][0][srow][skc]) = rb0;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][1][srow][skc]) = rb1;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][2][srow][skc]) = rb2;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][3][srow][skc]) = rb3;                                         \
   } while (0)
 
   f4 rr[4][2], ii[4][2], im[4][2];
@@ -167,20 +168,27 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
     for (int j = 0; j < 2; ++j) { rr[i][j] = f4{0, 0, 0, 0}; ii[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0}; }
 
   const int lr = lane & 15, lk = 8 * (lane >> 4);
-  if (klo < khi) FC_GLOAD(klo);
-  for (long k0 = klo; k0 < khi; k0 += TK) {
-    __syncthreads();
-    FC_SSTORE();
-    __syncthreads();
-    if (k0 + TK < khi) FC_GLOAD(k0 + TK);
+  // one barrier per K step: the loads of the next slice are issued before the products of this
+  // one and stored to the other buffer after them
+  if (klo < khi) {
+    FC_GLOAD(klo);
+    FC_SSTORE(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (long k0 = klo; k0 < khi; k0 += TK, buf ^= 1) {
+    const bool more = k0 + TK < khi;
+    if (more) FC_GLOAD(k0 + TK);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int ra_ = wm + 16 * i + lr;
-      const u16 *aRh = &sA[0][ra_][lk], *aRl = &sA[1][ra_][lk], *aIh = &sA[2][ra_][lk], *aIl = &sA[3][ra_][lk];
+      const u16 *aRh = &sA[buf][0][ra_][lk], *aRl = &sA[buf][1][ra_][lk], *aIh = &sA[buf][2][ra_][lk],
+                *aIl = &sA[buf][3][ra_][lk];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int rb_ = wn + 16 * j + lr;
-        const u16 *bRh = &sB[0][rb_][lk], *bRl = &sB[1][rb_][lk], *bIh = &sB[2][rb_][lk], *bIl = &sB[3][rb_][lk];
+        const u16 *bRh = &sB[buf][0][rb_][lk], *bRl = &sB[buf][1][rb_][lk], *bIh = &sB[buf][2][rb_][lk],
+                  *bIl = &sB[buf][3][rb_][lk];
         rr[i][j] = mma<PREC>(aRh, bRh, rr[i][j]);
         rr[i][j] = mma<PREC>(aRh, bRl, rr[i][j]);
         rr[i][j] = mma<PREC>(aRl, bRh, rr[i][j]);
@@ -195,6 +203,8 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
         im[i][j] = mma<PREC>(aIl, bRh, im[i][j]);
       }
     }
+    if (more) FC_SSTORE(buf ^ 1);
+    __syncthreads();
   }
 
   const int orow = 4 * (lane >> 4), ocol = lane & 15;
