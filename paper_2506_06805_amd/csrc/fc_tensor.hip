@@ -134,6 +134,77 @@ __global__ void k_permute(const z* __restrict__ in, z* __restrict__ out, PermArg
   }
 }
 
+// The same with 32-bit index arithmetic (every tensor here has fewer than 2^31 elements): the
+// 64-bit divisions of the general kernel cost more than its memory traffic.
+struct PermArgs32 {
+  int nd;
+  unsigned odims[MAXD], istr[MAXD];
+  unsigned n;
+  z alpha, beta;
+  int conj, use_beta;
+};
+__global__ void k_permute32(const z* __restrict__ in, z* __restrict__ out, PermArgs32 a) {
+  for (unsigned o = blockIdx.x * blockDim.x + threadIdx.x; o < a.n; o += gridDim.x * blockDim.x) {
+    unsigned rem = o, ioff = 0;
+    for (int d = a.nd - 1; d >= 0; --d) {
+      const unsigned q = rem / a.odims[d];
+      ioff += (rem - q * a.odims[d]) * a.istr[d];
+      rem = q;
+    }
+    z v = in[ioff];
+    if (a.conj) v.y = -v.y;
+    z r = cmul(a.alpha, v);
+    if (a.use_beta) r = cadd(r, cmul(a.beta, out[o]));
+    out[o] = r;
+  }
+}
+
+// Permutes whose innermost output index is not the innermost input index, as 32 x 32 tiles
+// through LDS: reads run along the input's contiguous index p, writes along the output's last
+// index q, both coalesced.  blockIdx.x walks the (p, q) tiles, blockIdx.y the remaining indices.
+struct TransArgs {
+  int nouter;
+  unsigned odim[MAXD], istr[MAXD], ostr[MAXD];   // the remaining output indices, outermost first
+  unsigned Dp, Dq, istr_q, ostr_p, ntq, nouter_total;
+  z alpha, beta;
+  int conj, use_beta;
+};
+constexpr int TT = 32, TR = 8;
+__global__ void __launch_bounds__(TT * TR) k_permute_tiled(const z* __restrict__ in, z* __restrict__ out, TransArgs a) {
+  __shared__ z tile[TT][TT + 1];
+  const unsigned tq = blockIdx.x % a.ntq, tp = blockIdx.x / a.ntq;
+  const unsigned p0 = tp * TT, q0 = tq * TT;
+  const int tx = threadIdx.x % TT, ty = threadIdx.x / TT;
+  for (unsigned ob = blockIdx.y; ob < a.nouter_total; ob += gridDim.y) {
+    unsigned rem = ob, ib = 0, obase = 0;
+    for (int d = a.nouter - 1; d >= 0; --d) {
+      const unsigned q = rem / a.odim[d], c = rem - q * a.odim[d];
+      ib += c * a.istr[d];
+      obase += c * a.ostr[d];
+      rem = q;
+    }
+#pragma unroll
+    for (int r = 0; r < TT / TR; ++r) {
+      const unsigned pp = p0 + tx, qq = q0 + ty + TR * r;
+      if (pp < a.Dp && qq < a.Dq) tile[ty + TR * r][tx] = in[ib + pp + qq * a.istr_q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TT / TR; ++r) {
+      const unsigned qq = q0 + tx, pp = p0 + ty + TR * r;
+      if (pp < a.Dp && qq < a.Dq) {
+        z v = tile[tx][ty + TR * r];
+        if (a.conj) v.y = -v.y;
+        z res = cmul(a.alpha, v);
+        z* dst = out + obase + pp * a.ostr_p + qq;
+        if (a.use_beta) res = cadd(res, cmul(a.beta, *dst));
+        *dst = res;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // r[i,j,a,b] += alpha * P(..) x
 __global__ void k_antisym_add(z* __restrict__ r, const z* __restrict__ x, long o, long v, int mode, z alpha) {
   const long n = o * o * v * v;
@@ -215,7 +286,49 @@ void permute(fc_ctx ctx, const ZT& in, const std::vector<int>& perm, z alpha, z 
   a.alpha = alpha; a.beta = beta; a.conj = conj;
   a.use_beta = (beta.x != 0.0 || beta.y != 0.0);
   if (a.n <= 0) return;
-  hipLaunchKernelGGL(k_permute, dim3(nblocks(a.n, 4)), dim3(TPB), 0, ctx->stream, in.p, out, a);
+  if (a.n >= (1L << 31)) {
+    hipLaunchKernelGGL(k_permute, dim3(nblocks(a.n, 4)), dim3(TPB), 0, ctx->stream, in.p, out, a);
+    FC_HIP(hipGetLastError());
+    return;
+  }
+  // p: the output index that is contiguous in the input; q: the last output index
+  int p = -1;
+  for (int d = 0; d < nd; ++d)
+    if (a.istr[d] == 1 && a.odims[d] > 1) p = d;
+  const int q = nd - 1;
+  if (p >= 0 && p != q && a.odims[p] >= 8 && a.odims[q] >= 8) {
+    TransArgs t{};
+    std::vector<long> ostr(nd);
+    long os = 1;
+    for (int d = nd - 1; d >= 0; --d) { ostr[d] = os; os *= a.odims[d]; }
+    t.nouter = 0;
+    long nout = 1;
+    for (int d = 0; d < nd; ++d) {
+      if (d == p || d == q) continue;
+      t.odim[t.nouter] = (unsigned)a.odims[d];
+      t.istr[t.nouter] = (unsigned)a.istr[d];
+      t.ostr[t.nouter] = (unsigned)ostr[d];
+      ++t.nouter;
+      nout *= a.odims[d];
+    }
+    t.Dp = (unsigned)a.odims[p]; t.Dq = (unsigned)a.odims[q];
+    t.istr_q = (unsigned)a.istr[q]; t.ostr_p = (unsigned)ostr[p];
+    t.ntq = (unsigned)((t.Dq + TT - 1) / TT);
+    t.nouter_total = (unsigned)nout;
+    t.alpha = alpha; t.beta = beta; t.conj = conj; t.use_beta = a.use_beta;
+    const long ntiles = (long)t.ntq * ((t.Dp + TT - 1) / TT);
+    FC_REQUIRE(ntiles < (1L << 31), FC_EARG, "permute: too many tiles");
+    const unsigned gy = (unsigned)std::max(1L, std::min(nout, 65535L));
+    hipLaunchKernelGGL(k_permute_tiled, dim3((unsigned)ntiles, gy), dim3(TT * TR), 0, ctx->stream, in.p, out, t);
+    FC_HIP(hipGetLastError());
+    return;
+  }
+  PermArgs32 b{};
+  b.nd = nd;
+  for (int d = 0; d < nd; ++d) { b.odims[d] = (unsigned)a.odims[d]; b.istr[d] = (unsigned)a.istr[d]; }
+  b.n = (unsigned)a.n;
+  b.alpha = alpha; b.beta = beta; b.conj = conj; b.use_beta = a.use_beta;
+  hipLaunchKernelGGL(k_permute32, dim3(nblocks(a.n, 4)), dim3(TPB), 0, ctx->stream, in.p, out, b);
   FC_HIP(hipGetLastError());
 }
 
