@@ -40,10 +40,16 @@ DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-pa
           "-munsafe-fp-atomics"]
 
 
+# Host FP64 linear algebra on small complex matrices: plain complex products and quotients (no
+# Annex G inf/nan recovery, which turns every complex multiply into a library call); the
+# matrices are well scaled, far from overflow.
+EXTRA = {"fc_linalg.cpp": ["-fcx-limited-range"]}
+
+
 def _compile(src: str) -> pathlib.Path:
     s = CSRC / src
     obj = BUILD / (s.stem + ".o")
-    cmd = [HIPCC, *COMMON]
+    cmd = [HIPCC, *COMMON, *EXTRA.get(src, [])]
     cmd += ["-x", "hip", *DEVICE]
     cmd += ["-c", str(s), "-o", str(obj)]
     r = subprocess.run(cmd, capture_output=True, text=True)

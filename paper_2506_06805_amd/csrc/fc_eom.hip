@@ -8,8 +8,12 @@
 // the Cholesky vectors in occupied-index chunks, never stored whole.  The sigma products
 // themselves are evaluated as matrix products over the packed vector layout (fc_sigma.hip).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "fc_sigma.hpp"
 
@@ -252,6 +256,35 @@ struct Inst {
   std::vector<int> roots;        // roots that get a correction vector this iteration
 };
 
+// fn(0..n-1) on up to 16 host threads (the calling thread included); the first exception
+// thrown by any call is rethrown after all threads have joined.
+template <class F>
+void for_each_parallel(int n, F&& fn) {
+  const int nt = std::max(1, std::min({n, 16, (int)std::thread::hardware_concurrency()}));
+  if (nt <= 1) {
+    for (int t = 0; t < n; ++t) fn(t);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  auto worker = [&] {
+    for (int t; (t = next.fetch_add(1)) < n;) {
+      try {
+        fn(t);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!err) err = std::current_exception();
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < nt; ++i) th.emplace_back(worker);
+  worker();
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
+
 // split-K partial sums (complex elements) of one product under tiling `tl`
 size_t split_elems(long M, long N, long K, const GroupTiling& tl) {
   if (K <= tl.kchunk) return 0;
@@ -392,10 +425,18 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
     arena.run(g, tl);
     mir.down(rg_g, sizeof(z) * gused);
     FC_HIP(hipStreamSynchronize(ctx->stream));
-    // (2) subspace eigenproblems on the host; Ritz coefficients up
+    // (2) subspace eigenproblems on the host, the instances spread over host threads; Ritz
+    // coefficients up
     size_t yused = 0;
+    std::vector<Inst*> act;
     for (Inst& s : in) {
       if (!s.active) continue;
+      s.off_y = rg_y + sizeof(z) * yused;
+      yused += (size_t)s.m * s.k;
+      act.push_back(&s);
+    }
+    for_each_parallel((int)act.size(), [&](int t) {
+      Inst& s = *act[t];
       const int nn = s.m - s.gold;
       const z* gh = mir.host<z>(s.off_g);
       for (int p = 0; p < s.m; ++p)
@@ -409,14 +450,12 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
         for (int q = 0; q < s.m; ++q) Gm[(size_t)p * s.m + q] = s.G[(size_t)p * s.maxsub + q];
       gen_eig(s.m, Gm, s.w, s.Y);
       lowest_by_real(s.w, s.k, s.sel);
-      s.off_y = rg_y + sizeof(z) * yused;
-      yused += (size_t)s.m * s.k;
       z* yk = mir.host<z>(s.off_y);
       for (int p = 0; p < s.m; ++p)
         for (int r = 0; r < s.k; ++r) yk[(size_t)p * s.k + r] = s.Y[(size_t)p * s.m + s.sel[r]];
       s.theta.assign(s.k, zero);
       for (int r = 0; r < s.k; ++r) s.theta[r] = s.w[s.sel[r]];
-    }
+    });
     mir.up(rg_y, sizeof(z) * yused);
     // (3) Ritz vectors X = Yk^T V and residuals R = Yk^T S - theta X with their norms
     g.clear();
