@@ -220,6 +220,15 @@ int fc_mlp_get_params(fc_mlp mlp, float* host, int bf16_rounded);
 int fc_mlp_grad(fc_mlp mlp, const float* X, const float* q, const float* r, long B, float* grad_host, float* loss);
 int fc_mlp_train_step(fc_mlp mlp, const float* X, const float* q, const float* r, long B, float lr, float* loss);
 int fc_mlp_forward(fc_mlp mlp, const float* X, long B, float* Y, int bf16_weights);
+/* fc_learned_step - one learned amplitude update as the solver applies it (test and measurement
+ * helper): t1_out = t1 + r1 / D1 (Jacobi); for every i < j, a < b, with the features above built
+ * from fdiag and the residual ratio r2 / r2prev (r2prev NULL: ratio 0) and g the network output
+ * with BF16-rounded weights, t2_out_ij^ab = t2_ij^ab + (r2_ij^ab / D_ij^ab)(1 + g), written to all
+ * four antisymmetric images, and zero where i == j or a == b.  t1, r1, t1_out: device o x v;
+ * t2, r2, r2prev, t2_out: device o x o x v x v; fdiag: device o + v complex128 (F_mi then F_ae
+ * diagonals).  All complex128. */
+int fc_learned_step(fc_ctx ctx, fc_ints ints, fc_mlp mlp, const void* t1, const void* t2, const void* r1,
+                    const void* r2, const void* r2prev, const void* fdiag, void* t1_out, void* t2_out);
 /* Training samples at the iterate (t1, t2) (device, full layout) of a solve whose converged
  * doubles are t2_star, the previous iterate (t1prev, t2prev) giving the residual ratio (NULL: 0):
  * nsamp unique amplitudes (i<j, a<b) drawn by a counter-based hash of seed; writes X (B x 4),

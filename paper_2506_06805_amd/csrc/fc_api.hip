@@ -498,6 +498,17 @@ int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, i
   })
 }
 
+int fc_learned_step(fc_ctx ctx, fc_ints I, fc_mlp mlp, const void* t1, const void* t2, const void* r1, const void* r2,
+                    const void* r2prev, const void* fdiag, void* t1_out, void* t2_out) {
+  if (!ctx || !I || !mlp || !t1 || !t2 || !r1 || !r2 || !fdiag || !t1_out || !t2_out) return FC_EARG;
+  FC_TRY(ctx, {
+    learned_step(ctx, I, mlp, (const z*)t1, (const z*)t2, (const z*)r1, (const z*)r2, (const z*)r2prev,
+                 (const z*)fdiag, (z*)t1_out, (z*)t2_out);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
+    return FC_OK;
+  })
+}
+
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
              long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision) {
   if (!ctx || !alpha || !beta || M < 0 || N < 0 || K < 0) return FC_EARG;

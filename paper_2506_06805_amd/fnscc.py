@@ -79,6 +79,7 @@ _sig = {
     "fc_mlp_grad": (C.c_int, [P, P, P, P, C.c_long, P, P]),
     "fc_mlp_train_step": (C.c_int, [P, P, P, P, C.c_long, C.c_float, P]),
     "fc_mlp_forward": (C.c_int, [P, P, C.c_long, P, C.c_int]),
+    "fc_learned_step": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P]),
     "fc_learn_samples": (C.c_int, [P, P, P, P, P, P, P, C.c_long, C.c_ulonglong, P, P, P]),
     "fc_host_zheev": (C.c_int, [C.c_int, P, P]),
     "fc_host_zgeev": (C.c_int, [C.c_int, P, P, P]),
@@ -543,6 +544,17 @@ class Mlp(_Handle):
         Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=X.device)
         self.ctx.check(lib.fc_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(Y), int(bf16)), "fc_mlp_forward")
         return Y
+
+
+def learned_step(ctx: Context, ints: Ints, mlp: Mlp, t1, t2, r1, r2, r2prev, fdiag):
+    """One learned amplitude update (device tensors, complex128); returns (t1_new, t2_new)."""
+    torch = ctx.torch
+    t1, t2, r1, r2, fdiag = (x.contiguous() for x in (t1, t2, r1, r2, fdiag))
+    r2prev = r2prev.contiguous() if r2prev is not None else None
+    o1, o2 = torch.empty_like(t1), torch.empty_like(t2)
+    ctx.check(lib.fc_learned_step(ctx.h, ints.h, mlp.h, _ptr(t1), _ptr(t2), _ptr(r1), _ptr(r2), _ptr(r2prev),
+                                  _ptr(fdiag), _ptr(o1), _ptr(o2)), "fc_learned_step")
+    return o1, o2
 
 
 def learn_samples(ctx: Context, ints: Ints, t1_ptr, t2_ptr, t2_star, nsamp, seed, out=None, offset=0, prev=None):

@@ -69,6 +69,58 @@ def trained(gpu_ctx):
     return net, hist
 
 
+def _antisym(rng, o, v, scale):
+    x = (rng.standard_normal((o, o, v, v)) + 1j * rng.standard_normal((o, o, v, v))) * scale
+    x = x - x.transpose(1, 0, 2, 3)
+    return x - x.transpose(0, 1, 3, 2)
+
+
+@pytest.mark.parametrize("o,v,prev", [(5, 12, True), (3, 7, False), (7, 40, True)])
+def test_learned_step_matches_network(gpu_ctx, o, v, prev):
+    # the solver's inference kernel against the FP64 network on the same FP32 features: features of
+    # amplitude (i<j, a<b) are u = (F_aa + F_bb - F_ii - F_jj) / D and rho = r2 / r2prev (|rho| <= 1.5)
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(o * 100 + v)
+    inst = synth.make_instance(o, v, 3 * v, seed=o + v, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    params = (rng.standard_normal(fnscc.Mlp.num_params()) * 0.3).astype(np.float32)
+    net = fnscc.Mlp(gpu_ctx, params=params)
+    t1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * 0.05
+    r1 = (rng.standard_normal((o, v)) + 1j * rng.standard_normal((o, v))) * 0.01
+    t2, r2 = _antisym(rng, o, v, 0.05), _antisym(rng, o, v, 0.01)
+    r2p = _antisym(rng, o, v, 0.012) if prev else None
+    fd = (rng.standard_normal(o + v) + 1j * rng.standard_normal(o + v)) * 0.5 + np.r_[inst.eps[:o], inst.eps[o:]]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    o1, o2 = fnscc.learned_step(gpu_ctx, ints, net, dev(t1), dev(t2), dev(r1), dev(r2),
+                                dev(r2p) if prev else None, dev(fd))
+    o1, o2 = o1.cpu().numpy(), o2.cpu().numpy()
+    e = inst.eps
+    assert np.abs(o1 - (t1 + r1 / (e[:o, None] - e[None, o:]))).max() < 1e-12
+    ii, jj = np.triu_indices(o, 1)
+    aa, bb = np.triu_indices(v, 1)
+    I, A = np.meshgrid(np.arange(len(ii)), np.arange(len(aa)), indexing="ij")
+    i, j, a, b = ii[I].ravel(), jj[I].ravel(), aa[A].ravel(), bb[A].ravel()
+    D = e[i] + e[j] - e[o + a] - e[o + b]
+    u = (fd[o + a] + fd[o + b] - fd[i] - fd[j]) / D
+    if prev:
+        rho = r2[i, j, a, b] / r2p[i, j, a, b]
+        m = np.abs(rho)
+        rho = np.where(m > 1.5, rho * 1.5 / np.maximum(m, 1e-300), rho)
+    else:
+        rho = np.zeros_like(u)
+    X = np.stack([u.real, u.imag, rho.real, rho.imag], 1).astype(np.float32).astype(np.float64)
+    y = omlp.forward(net.params(bf16=True).astype(np.float64), X)
+    g = y[:, 0] + 1j * y[:, 1]
+    q = r2[i, j, a, b] / D
+    ref = t2[i, j, a, b] + q * (1 + g)
+    got = o2[i, j, a, b]
+    assert np.abs((got - ref) / q).max() < 2e-5
+    assert np.array_equal(o2[j, i, a, b], -got) and np.array_equal(o2[i, j, b, a], -got)
+    assert np.array_equal(o2[j, i, b, a], got)
+    assert not np.any(o2[np.arange(o), np.arange(o)]) and not np.any(o2[:, :, np.arange(v), np.arange(v)])
+
+
 def test_training_reduces_loss(trained):
     _, hist = trained
     assert hist[-1] < 0.8 * hist[0], hist
