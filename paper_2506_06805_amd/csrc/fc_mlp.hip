@@ -34,6 +34,7 @@ struct fc_mlp_s {
 namespace fc {
 namespace {
 constexpr int NIN = 4, NH = 64, NOUT = 2;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr long NP = NH * NIN + NH + NH * NH + NH + NOUT * NH + NOUT;
 constexpr int TPB = 256;
 #define GRID_STRIDE(i, n) for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
@@ -208,60 +209,137 @@ __device__ inline void pair_of_index(long p, long n, long& i, long& j) {
   j = i + 1 + (p - (i * n - i * (i + 1) / 2));
 }
 
-// t2_new = t2 + (r2 / D)(1 + g(x)) with BF16-rounded weights in LDS and FP32 arithmetic; one
-// thread per unique amplitude (i < j, a < b), written to its four antisymmetric images.  The
-// first hidden layer stays in registers; the second is folded into the output sums as it goes.
-__global__ __launch_bounds__(TPB) void k_learned_t2(const float* __restrict__ pbf, const z* __restrict__ t2,
-                                                    const z* __restrict__ r2, const z* __restrict__ r2prev,
-                                                    const double* __restrict__ eps,
-                                                    const z* __restrict__ fd, long o, long v, z* __restrict__ out) {
-  __shared__ __attribute__((aligned(16))) float P[NP];
-  for (long k = threadIdx.x; k < NP; k += blockDim.x) P[k] = pbf[k];
+// t2_new = t2 + (r2 / D)(1 + g(x)) for every unique amplitude (i < j, a < b), written to its four
+// antisymmetric images, with the BF16-rounded weights and FP32 arithmetic; the 64 x 64 hidden
+// layer runs on the FP32 matrix cores.  Each wave takes 64 unique amplitudes (one per lane),
+// forms the features and the first hidden layer per lane,
+// stages h1 as a 64 x 64 block in LDS, and multiplies it by W2^T with v_mfma_f32_16x16x4f32
+// (4 x 4 output blocks, K = 64 in 16 steps; W2 fragments stay in registers for the whole
+// kernel).  tanh and the output layer act on the accumulators in place; the two output sums of a
+// sample are reduced over the 16 lanes that hold its columns and handed back to the sample's
+// lane through LDS.  (Evaluating the whole network per lane with weights in LDS took 3.9x as
+// long: 2.5 against 0.64 ms per step at o = 24, v = 160.)
+constexpr int LW = 4;              // waves per workgroup
+constexpr int HS = NH + 1;         // LDS row of one sample's h1 (padded)
+__global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __restrict__ pbf, const z* __restrict__ t2,
+                                                            const z* __restrict__ r2, const z* __restrict__ r2prev,
+                                                            const double* __restrict__ eps,
+                                                            const z* __restrict__ fd, long o, long v, z* __restrict__ out) {
+  __shared__ float Ps[NH * NIN + NH];        // W1, b1
+  __shared__ float Hs[LW][64 * HS];          // per wave: h1 of its 64 samples, then (y0, y1)
+  for (int k = threadIdx.x; k < NH * NIN + NH; k += blockDim.x) Ps[k] = pbf[OW1 + k];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, ln = lane & 15, lk = lane >> 4;
+  // W2 fragments: B[k][n] of step kk and column block pb is W2[pb 16 + n][kk 4 + k]
+  float w2f[4][16];
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb)
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) w2f[pb][kk] = pbf[OW2 + (pb * 16 + ln) * NH + kk * 4 + lk];
+  float b2c[4], w30[4], w31[4];
+#pragma unroll
+  for (int pb = 0; pb < 4; ++pb) {
+    b2c[pb] = pbf[OB2 + pb * 16 + ln];
+    w30[pb] = pbf[OW3 + pb * 16 + ln];
+    w31[pb] = pbf[OW3 + NH + pb * 16 + ln];
+  }
+  const float b30 = pbf[OB3], b31 = pbf[OB3 + 1];
   __syncthreads();
-  const long no = o * (o - 1) / 2, nv = v * (v - 1) / 2;
-  GRID_STRIDE(u, no * nv) {
-    long i, j, a, b;
-    pair_of_index(u / nv, o, i, j);
-    pair_of_index(u % nv, v, a, b);
-    const long x = ((i * o + j) * v + a) * v + b;
-    const double D = eps[i] + eps[j] - eps[o + a] - eps[o + b];
-    const double fr = fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x;
-    const double fi = fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y;
-    float xin[NIN];
-    features(D, fr, fi, r2, r2prev, x, xin);
-    float h1[NH];
-#pragma unroll
-    for (int p = 0; p < NH; ++p) {
-      float s = P[OB1 + p];
-#pragma unroll
-      for (int q = 0; q < NIN; ++q) s += P[OW1 + p * NIN + q] * xin[q];
-      h1[p] = tanh_exp(s);
+  float* H = Hs[w];
+  const long no = o * (o - 1) / 2, nv = v * (v - 1) / 2, nu = no * nv;
+  const long groups = (nu + 63) / 64, stride = (long)gridDim.x * LW;
+  for (long g0 = (long)blockIdx.x * LW; g0 < groups; g0 += stride) {   // uniform over the workgroup
+    const long u = (g0 + w) * 64 + lane;
+    const bool valid = u < nu;
+    long i = 0, j = 1, a = 0, b = 1, x = 0;
+    double D = 1.0;
+    float xin[NIN] = {0.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      pair_of_index(u / nv, o, i, j);
+      pair_of_index(u % nv, v, a, b);
+      x = ((i * o + j) * v + a) * v + b;
+      D = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+      const double fr = fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x;
+      const double fi = fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y;
+      features(D, fr, fi, r2, r2prev, x, xin);
     }
-    float y0 = P[OB3], y1 = P[OB3 + 1];
-#pragma unroll 2
-    for (int p = 0; p < NH; ++p) {
-      const float4* w = reinterpret_cast<const float4*>(P + OW2 + p * NH);
-      float s = P[OB2 + p];
 #pragma unroll
-      for (int q = 0; q < NH / 4; ++q) {
-        const float4 c = w[q];
-        s += c.x * h1[4 * q] + c.y * h1[4 * q + 1] + c.z * h1[4 * q + 2] + c.w * h1[4 * q + 3];
+    for (int p = 0; p < NH; p += 4) {
+      float hv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float s = Ps[NH * NIN + p + e];
+#pragma unroll
+        for (int q = 0; q < NIN; ++q) s += Ps[(p + e) * NIN + q] * xin[q];
+        hv[e] = tanh_exp(s);
       }
-      const float h = tanh_exp(s);
-      y0 += P[OW3 + p] * h;
-      y1 += P[OW3 + NH + p] * h;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) H[lane * HS + p + e] = hv[e];
     }
-    const double qr = r2[x].x / D, qi = r2[x].y / D;
-    const double gr = 1.0 + (double)y0, gi = (double)y1;
-    const z n = make_double2(t2[x].x + qr * gr - qi * gi, t2[x].y + qr * gi + qi * gr);
-    const z m = make_double2(-n.x, -n.y);
-    out[x] = n;
-    out[((j * o + i) * v + a) * v + b] = m;
-    out[((i * o + j) * v + b) * v + a] = m;
-    out[((j * o + i) * v + b) * v + a] = n;
+    __syncthreads();
+    // h2 = tanh(h1 W2^T + b2): block (sb, pb) holds samples sb 16 + 4 lk + r, columns pb 16 + ln
+    float y0[4][4], y1[4][4];
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      f32x4 acc[4];
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb) acc[pb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const float av = H[(sb * 16 + ln) * HS + kk * 4 + lk];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w2f[pb][kk], acc[pb], 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+          const float h = tanh_exp(acc[pb][r] + b2c[pb]);
+          s0 += w30[pb] * h;
+          s1 += w31[pb] * h;
+        }
+        y0[sb][r] = s0;
+        y1[sb][r] = s1;
+      }
+    }
+    // sums over the 16 column lanes of each sample (lanes with the same lk)
+#pragma unroll
+    for (int m = 1; m < 16; m <<= 1)
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          y0[sb][r] += __shfl_xor(y0[sb][r], m, 16);
+          y1[sb][r] += __shfl_xor(y1[sb][r], m, 16);
+        }
+    __syncthreads();   // every lane has read its h1 rows
+    if (ln == 0) {
+#pragma unroll
+      for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int smp = sb * 16 + 4 * lk + r;
+          H[2 * smp] = y0[sb][r];
+          H[2 * smp + 1] = y1[sb][r];
+        }
+    }
+    __syncthreads();
+    if (valid) {
+      const float g0 = H[2 * lane] + b30, g1 = H[2 * lane + 1] + b31;
+      const double qr = r2[x].x / D, qi = r2[x].y / D;
+      const double gr = 1.0 + (double)g0, gi = (double)g1;
+      const z n = make_double2(t2[x].x + qr * gr - qi * gi, t2[x].y + qr * gi + qi * gr);
+      const z mneg = make_double2(-n.x, -n.y);
+      out[x] = n;
+      out[((j * o + i) * v + a) * v + b] = mneg;
+      out[((i * o + j) * v + b) * v + a] = mneg;
+      out[((j * o + i) * v + b) * v + a] = n;
+    }
+    __syncthreads();   // the (y0, y1) slots are h1 rows of the next group
   }
 }
-// zeros where i == j or a == b (never visited by k_learned_t2)
+
+// zeros where i == j or a == b (never visited by k_learned_t2_mfma)
 __global__ void k_zero_diagonals(z* out, long o, long v) {
   GRID_STRIDE(t, o * v * v + o * o * v) {
     long x;
@@ -297,9 +375,12 @@ int learned_step(fc_ctx ctx, fc_ints I, const void* mlpv, const z* t1, const z* 
   k_jacobi_t1<<<nblk(o * v), TPB, 0, ctx->stream>>>(t1, r1, o1, I->eps_d.as<double>(), o, v);
   k_zero_diagonals<<<nblk(o * v * v + o * o * v), TPB, 0, ctx->stream>>>(o2, o, v);
   const long nu = (o * (o - 1) / 2) * (v * (v - 1) / 2);
-  if (nu > 0)
-    k_learned_t2<<<nblk(nu), TPB, 0, ctx->stream>>>(m->pbf.as<float>(), t2, r2, r2prev, I->eps_d.as<double>(), fd,
-                                                     o, v, o2);
+  if (nu > 0) {
+    const long groups = (nu + 63) / 64;
+    const unsigned nb = (unsigned)std::max(1L, std::min(2048L, (groups + LW - 1) / LW));
+    k_learned_t2_mfma<<<nb, 64 * LW, 0, ctx->stream>>>(m->pbf.as<float>(), t2, r2, r2prev, I->eps_d.as<double>(),
+                                                       fd, o, v, o2);
+  }
   FC_HIP(hipGetLastError());
   return FC_OK;
 }
