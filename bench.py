@@ -274,7 +274,7 @@ def main():
     ap.add_argument("--no-left", dest="left", action="store_false",
                     help="skip the left eigenvectors and one-hole weights of the benchmarked instance")
     ap.add_argument("--no-compare", dest="compare", action="store_false",
-                    help="skip the split-BF16 and split-BF16 + learned runs on the same instance")
+                    help="skip the FP64 + learned, split-BF16 and split-BF16 + learned runs on the same instance")
     ap.add_argument("--host-inputs", action="store_true",
                     help="pass the Cholesky vectors from host memory (PCIe-inclusive time-to-IPs; not the metric)")
     ap.add_argument("--autotune", action="store_true",
@@ -371,12 +371,14 @@ def main():
     r.pop("ints", None)
     r.pop("amps", None)
     if args.compare and args.precision == "fp64":
-        # the same instance through the split-BF16 path, then with the learned update on top
+        # the same instance with the learned update on the FP64 path, through the split-BF16 path,
+        # and through the split-BF16 path with the learned update
         w64 = np.sort_complex(np.asarray(r["w"]))
         cmp = {}
         net, t_train, info = train_update_network(ctx)
-        for name, mlp in (("split-bf16", None), ("split-bf16+learned", net)):
-            rm = run_gpu(args, inst, wl, "split-bf16", mlp=mlp, ctx=ctx)
+        for name, prec, mlp in (("fp64+learned", "fp64", net), ("split-bf16", "split-bf16", None),
+                                ("split-bf16+learned", "split-bf16", net)):
+            rm = run_gpu(args, inst, wl, prec, mlp=mlp, ctx=ctx)
             wm = np.sort_complex(np.asarray(rm["w"]))
             lad = F / (rm["ladder_ms"] * 1e-3) / 1e12 if rm["ladder_ms"] > 0 else 0.0
             cmp[name] = {"time_to_ips_s": rm["ms_per_step"] / 1000.0,
@@ -384,9 +386,10 @@ def main():
                          "max_abs_dIP_vs_fp64": float(np.abs(wm - w64).max()),
                          "abs_dE_vs_fp64": float(abs(rm["e"] - r["e"])),
                          "ccsd_iters": rm["iters"],
-                         "ladder_tflops": lad, "ladder_frac_of_bf16_peak": lad / PEAK["split-bf16"],
-                         "ladder_ms": rm["ladder_ms"]}
-        cmp["split-bf16+learned"]["training_s"] = t_train
+                         "ladder_tflops": lad, f"ladder_frac_of_{'fp64' if prec == 'fp64' else 'bf16'}_peak":
+                         lad / PEAK[prec], "ladder_ms": rm["ladder_ms"]}
+        for name in ("fp64+learned", "split-bf16+learned"):
+            cmp[name]["training_s"] = t_train
         cmp["split-bf16+learned"]["training"] = info
         line["compare"] = cmp
     if not args.no_cpu_baseline:
