@@ -90,7 +90,8 @@ int ao_to_spinor(fc_ctx ctx, int nvec, int nao, int n, const double* Lao, const 
  * <mn||ij>, <mn||ie>, <mn||ef>, <mb||ej> and the blocks derived from them by index symmetry).
  * eps: host, n doubles. L: ncd*n*n complex of `l_dtype`, host (l_on_device = 0) or device (1).
  * precision: FC_FP64 / FC_SPLIT_BF16 / FC_SPLIT_FP16, used by the assembly GEMMs and kept as the
- * default of the ladder. Returns FC_EARG for o < 1, v < 1, ncd < 1 or NULL pointers. */
+ * default of the ladder. Returns FC_EARG for o < 1, v < 1, ncd < 1 or NULL pointers and
+ * FC_EUNSUPPORTED for o == 1 or v == 1 (no doubles amplitudes, no 2h1p space). */
 int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const void* L, int l_dtype,
                  int l_on_device, int precision, fc_ints* out);
 int fc_ints_info(fc_ints ints, int* o, int* v, int* ncd);
@@ -102,7 +103,8 @@ void fc_free_ints(fc_ints ints);
  * semicanonicalise F_vv in the kept space; U = V~ Z~ (v x v'); rotate the virtual Cholesky
  * vectors and rebuild the stored integrals. Occupied spinors are untouched.
  * occ: host, v doubles (all occupations, descending) or NULL. U: host, v*v' complex128 row-major
- * or NULL. *out is a new handle; `in` stays valid. */
+ * or NULL. *out is a new handle; `in` stays valid. FC_EUNSUPPORTED when fewer than two virtual
+ * spinors pass the threshold. */
 int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v_kept, double* occ,
                  void* U);
 

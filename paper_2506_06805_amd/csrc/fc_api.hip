@@ -206,7 +206,7 @@ static fc_ints fns_impl(fc_ctx ctx, fc_ints I, double thresh, int* v_kept, doubl
   for (long c = v - 1; c >= 0; --c)
     if (nocc[c] > thresh) keep.push_back((int)c);  // descending occupation
   const long vp = (long)keep.size();
-  FC_REQUIRE(vp >= 1, FC_EARG, "fns_truncate: threshold removes every virtual spinor");
+  FC_REQUIRE(vp >= 2, FC_EUNSUPPORTED, "fns_truncate: the threshold keeps fewer than two virtual spinors");
   if (occ_out) for (long c = 0; c < v; ++c) occ_out[c] = nocc[v - 1 - c];
   // F^NS = V~^H diag(eps_v) V~ (Eq. 26), semicanonical Z~ (Eq. 27), U = V~ Z~ (Eq. 28)
   std::vector<z> F(vp * vp);
@@ -402,6 +402,8 @@ int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const voi
   *out = nullptr;
   FC_TRY(ctx, {
     FC_REQUIRE(o >= 1 && v >= 1 && ncd >= 1, FC_EARG, "cd_integrals: o, v and ncd must be >= 1");
+    // one occupied or one virtual spinor leaves no doubles (and no 2h1p space): not supported
+    FC_REQUIRE(o >= 2 && v >= 2, FC_EUNSUPPORTED, "cd_integrals: needs at least two occupied and two virtual spinors");
     FC_REQUIRE(eps && L, FC_EARG, "cd_integrals: NULL eps or L");
     FC_REQUIRE(l_dtype == FC_C128 || l_dtype == FC_C64, FC_EARG, "cd_integrals: l_dtype must be FC_C128 or FC_C64");
     FC_REQUIRE(precision >= FC_FP64 && precision <= FC_SPLIT_FP16, FC_EARG, "cd_integrals: bad precision");

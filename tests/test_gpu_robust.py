@@ -57,3 +57,24 @@ def test_default_tolerance_follows_precision(gpu_ctx, inst):
     assert res["split-bf16"][1] <= it_tight
     assert np.abs(res["split-bf16"][2] - res["fp64"][2]).max() < 1e-5
     assert abs(res["split-bf16"][0] - res["fp64"][0]) < 1e-5
+
+
+@pytest.mark.parametrize("o,v", [(1, 6), (4, 1)])
+def test_single_occupied_or_virtual_is_rejected(gpu_ctx, o, v):
+    # no doubles amplitudes and no 2h1p space: refused before any device work
+    from paper_2506_06805_amd import fnscc
+    inst = synth.make_instance(max(o, 2), max(v, 2), 8, seed=3, kappa=0.6)
+    n = o + v
+    L = np.ascontiguousarray(inst.L[:, :n, :n])
+    with pytest.raises(fnscc.FcError) as e:
+        fnscc.cd_integrals(gpu_ctx, inst.eps[:n], L, o)
+    assert e.value.code == fnscc.FC_EUNSUPPORTED
+
+
+def test_fns_keeping_one_virtual_is_rejected(gpu_ctx):
+    from paper_2506_06805_amd import fnscc
+    inst = synth.make_instance(4, 10, 30, seed=5, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, 4)
+    with pytest.raises(fnscc.FcError) as e:
+        fnscc.fns_truncate(gpu_ctx, ints, 1e30)
+    assert e.value.code == fnscc.FC_EUNSUPPORTED
