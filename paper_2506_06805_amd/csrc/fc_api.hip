@@ -60,14 +60,16 @@ static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const
     slot = D.order.front();
     D.order.pop_front();
   }
-  FC_HIP(hipMemcpyAsync(D.vec(slot), tnew, sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
-  FC_HIP(hipMemcpyAsync(D.err(slot), tnew, sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
-  axpy(ctx, D.nt, make_double2(-1, 0), told, D.err(slot));
+  diis_push(ctx, D.nt, tnew, told, D.vec(slot), D.err(slot));
   D.order.push_back(slot);
-  for (int s : D.order) {
-    z b = dotc(ctx, D.nt, D.err(slot), D.err(s));
-    D.B[slot * D.size + s] = b;
-    D.B[s * D.size + slot] = make_double2(b.x, -b.y);
+  {
+    const std::vector<int> sl(D.order.begin(), D.order.end());
+    std::vector<z> bs(sl.size());
+    multi_dotc(ctx, D.nt, D.err(slot), D.err(0), D.nt, sl.data(), (int)sl.size(), bs.data());
+    for (size_t k = 0; k < sl.size(); ++k) {
+      D.B[slot * D.size + sl[k]] = bs[k];
+      D.B[sl[k] * D.size + slot] = make_double2(bs[k].x, -bs[k].y);
+    }
   }
   while (D.order.size() >= 2) {
     const int m = (int)D.order.size();
@@ -83,8 +85,8 @@ static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const
     for (int k = 0; k < m; ++k) { A[m * (m + 1) + k] = make_double2(1, 0); A[k * (m + 1) + m] = make_double2(1, 0); }
     rhs[m] = make_double2(1, 0);
     if (cond_herm(m + 1, A) < 1e12 && lin_solve(m + 1, A, rhs)) {
-      fill(ctx, out, D.nt, make_double2(0, 0));
-      for (int k = 0; k < m; ++k) axpy(ctx, D.nt, rhs[k], D.vec(D.order[k]), out);
+      const std::vector<int> sl(D.order.begin(), D.order.end());
+      lincomb(ctx, D.nt, D.vec(0), D.nt, sl.data(), rhs.data(), m, out);
       return;
     }
     D.order.pop_front();  // ill-conditioned: drop the oldest vector
@@ -469,6 +471,7 @@ int ccsd_solve(fc_ctx ctx, int nb, const fc_ints* ints, const fc_ccsd_opts* opts
     fc_ccsd_opts op;
     if (opts) op = *opts; else fc_ccsd_default_opts(&op);
     FC_REQUIRE(op.max_iter >= 1, FC_EARG, "ccsd_solve: max_iter must be >= 1");
+    FC_REQUIRE(op.diis_dim <= 16, FC_EARG, "ccsd_solve: diis_dim must be <= 16");
     int status = FC_OK;
     for (int b = 0; b < nb; ++b) {
       FC_REQUIRE(ints[b], FC_EARG, "ccsd_solve: NULL integral handle");

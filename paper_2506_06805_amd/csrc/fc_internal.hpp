@@ -143,6 +143,12 @@ void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha
 // Dot products with FP64 accumulation in a fixed order (deterministic).
 z dotu(fc_ctx ctx, long n, const z* x, const z* y);    // sum x*y
 z dotc(fc_ctx ctx, long n, const z* x, const z* y);    // sum conj(x)*y
+// Vectors base + slot[k] * stride, k < m <= 16 (DIIS history): out[k] = dotc(x, vector k) on the
+// host (one pass over x, fixed order); out = sum_k c[k] vector k (one pass); v = tnew,
+// e = tnew - told.
+void multi_dotc(fc_ctx ctx, long n, const z* x, const z* base, long stride, const int* slot, int m, z* out);
+void lincomb(fc_ctx ctx, long n, const z* base, long stride, const int* slot, const z* c, int m, z* out);
+void diis_push(fc_ctx ctx, long n, const z* tnew, const z* told, z* v, z* e);
 
 // Scope in which zgemm runs in FP32 arithmetic (the mixed-precision residual).
 struct Fp32Gemms {

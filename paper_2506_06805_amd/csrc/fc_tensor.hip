@@ -220,6 +220,7 @@ __global__ void k_antisym_add(z* __restrict__ r, const z* __restrict__ x, long o
 
 // Deterministic dot product: fixed grid, fixed per-thread striding, fixed tree.
 constexpr int DOT_BLOCKS = 1024;
+constexpr int MAXV = 16;
 __global__ void k_dot_partial(long n, const z* __restrict__ x, const z* __restrict__ y, int conjx, z* part) {
   __shared__ double sr[TPB], si[TPB];
   double ar = 0, ai = 0;
@@ -249,7 +250,100 @@ __global__ void k_dot_final(const z* part, z* out) {
   }
   if (threadIdx.x == 0) *out = make_double2(sr[0], si[0]);
 }
+// Several vectors at once (DIIS): one pass over x for all dot products, one pass over the inputs
+// of a linear combination.  Vector k is base + slot[k] * stride.
+struct MultiArgs {
+  int m;
+  int slot[MAXV];
+  z c[MAXV];
+};
+// part[b * m + k] = sum over this block's fixed stripe of conj(x) * Y_k
+__global__ void k_multi_dot_partial(long n, const z* __restrict__ x, const z* __restrict__ base, long stride,
+                                    MultiArgs a, z* __restrict__ part) {
+  __shared__ double sr[TPB], si[TPB];
+  double ar[MAXV], ai[MAXV];
+#pragma unroll
+  for (int k = 0; k < MAXV; ++k) { ar[k] = 0; ai[k] = 0; }
+  for (long i = blockIdx.x * (long)TPB + threadIdx.x; i < n; i += (long)DOT_BLOCKS * TPB) {
+    const z xv = x[i];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      if (k >= a.m) break;
+      const z y = base[(long)a.slot[k] * stride + i];
+      ar[k] += xv.x * y.x + xv.y * y.y;
+      ai[k] += xv.x * y.y - xv.y * y.x;
+    }
+  }
+  for (int k = 0; k < a.m; ++k) {
+    sr[threadIdx.x] = ar[k]; si[threadIdx.x] = ai[k];
+    __syncthreads();
+    for (int s = TPB / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)blockIdx.x * a.m + k] = make_double2(sr[0], si[0]);
+    __syncthreads();
+  }
+}
+// out[k] = sum over blocks of part[b * m + k], one workgroup per k, fixed tree
+__global__ void k_multi_dot_final(const z* __restrict__ part, int m, z* __restrict__ out) {
+  __shared__ double sr[TPB], si[TPB];
+  const int k = blockIdx.x;
+  double ar = 0, ai = 0;
+  for (int b = threadIdx.x; b < DOT_BLOCKS; b += TPB) { ar += part[(long)b * m + k].x; ai += part[(long)b * m + k].y; }
+  sr[threadIdx.x] = ar; si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) { sr[threadIdx.x] += sr[threadIdx.x + s]; si[threadIdx.x] += si[threadIdx.x + s]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[k] = make_double2(sr[0], si[0]);
+}
+__global__ void k_lincomb(long n, const z* __restrict__ base, long stride, MultiArgs a, z* __restrict__ out) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    z acc = make_double2(0, 0);
+    for (int k = 0; k < a.m; ++k) acc = cadd(acc, cmul(a.c[k], base[(long)a.slot[k] * stride + i]));
+    out[i] = acc;
+  }
+}
+// v = tnew, e = tnew - told
+__global__ void k_diis_push(long n, const z* __restrict__ tnew, const z* __restrict__ told, z* __restrict__ v,
+                            z* __restrict__ e) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const z a = tnew[i], b = told[i];
+    v[i] = a;
+    e[i] = make_double2(a.x - b.x, a.y - b.y);
+  }
+}
 }  // namespace
+
+void multi_dotc(fc_ctx ctx, long n, const z* x, const z* base, long stride, const int* slot, int m, z* out) {
+  FC_REQUIRE(m >= 1 && m <= MAXV, FC_EARG, "multi_dotc: 1..16 vectors");
+  MultiArgs a{};
+  a.m = m;
+  for (int k = 0; k < m; ++k) a.slot[k] = slot[k];
+  DBuf part(ctx, sizeof(z) * ((size_t)DOT_BLOCKS * m + m));
+  z* fin = part.as<z>() + (size_t)DOT_BLOCKS * m;
+  hipLaunchKernelGGL(k_multi_dot_partial, dim3(DOT_BLOCKS), dim3(TPB), 0, ctx->stream, n, x, base, stride, a,
+                     part.as<z>());
+  hipLaunchKernelGGL(k_multi_dot_final, dim3(m), dim3(TPB), 0, ctx->stream, part.as<z>(), m, fin);
+  FC_HIP(hipGetLastError());
+  FC_HIP(hipMemcpyAsync(out, fin, sizeof(z) * m, hipMemcpyDeviceToHost, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+}
+void lincomb(fc_ctx ctx, long n, const z* base, long stride, const int* slot, const z* c, int m, z* out) {
+  FC_REQUIRE(m >= 1 && m <= MAXV, FC_EARG, "lincomb: 1..16 vectors");
+  MultiArgs a{};
+  a.m = m;
+  for (int k = 0; k < m; ++k) { a.slot[k] = slot[k]; a.c[k] = c[k]; }
+  hipLaunchKernelGGL(k_lincomb, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, base, stride, a, out);
+  FC_HIP(hipGetLastError());
+}
+void diis_push(fc_ctx ctx, long n, const z* tnew, const z* told, z* v, z* e) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_diis_push, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, tnew, told, v, e);
+  FC_HIP(hipGetLastError());
+}
 
 void fill(fc_ctx ctx, z* p, long n, z value) {
   if (n <= 0) return;
