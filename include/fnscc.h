@@ -115,7 +115,7 @@ int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v
 typedef struct fc_mlp_s* fc_mlp;
 
 /* Options of ccsd_solve. Jacobi update t += Omega/D with complex DIIS (FP64) over the last
- * diis_dim iterates (default 8, at most 16; <= 1 turns DIIS off). Converged when
+ * diis_dim iterates (default 10, at most 16; <= 1 turns DIIS off). Converged when
  * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol; e_tol, r_tol <= 0 (the defaults)
  * select 1e-10 and 1e-9 for FC_FP64 and 1e-8 and 1e-7 for the split precisions, whose product
  * errors move the IPs by ~1e-7 Eh anyway. learned = 1 with mlp != NULL uses

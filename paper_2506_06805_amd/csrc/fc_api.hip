@@ -459,7 +459,7 @@ void fc_ccsd_default_opts(fc_ccsd_opts* op) {
   op->e_tol = 0;   // 0: by precision (FP64 1e-10 / 1e-9, split 1e-8 / 1e-7)
   op->r_tol = 0;
   op->max_iter = 200;
-  op->diis_dim = 8;
+  op->diis_dim = 10;
   op->learned = 0;
   op->precision = -1;  // inherit from the integral handle
   op->stall_window = 3;
