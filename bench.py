@@ -53,9 +53,11 @@ def run_gpu(args, inst, wl, precision, mlp=None, ctx=None):
 
     def step():
         ints = fnscc.cd_integrals(ctx, inst.eps, L_dev, o, precision=precision)
+        if args.fns is not None:   # frozen natural spinors inside the timed step, as in the method
+            ints, _ = fnscc.fns_truncate(ctx, ints, args.fns)
         e, it, amps = fnscc.ccsd_solve(ctx, ints, precision=precision, **extra)
         w, its = fnscc.ipeom_davidson(ctx, ints, amps, k)
-        last.update(ints=ints, amps=amps)
+        last.update(ints=ints, amps=amps, v_kept=ints.v)
         return e, it, w, its
 
     for _ in range(args.warmup):
@@ -279,6 +281,11 @@ def main():
                     help="pass the Cholesky vectors from host memory (PCIe-inclusive time-to-IPs; not the metric)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune GEMM tiles during the warmup steps (cached for the timed steps)")
+    ap.add_argument("--fns", type=float, default=None,
+                    help="frozen-natural-spinor occupation threshold applied inside each step (Eq. 24-28)")
+    ap.add_argument("--fns-gamma", type=float, default=6.0,
+                    help="decay of the FNS-structured generator used with --fns")
+    ap.add_argument("--c64", action="store_true", help="complex64 Cholesky vectors (FP64 arithmetic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -325,7 +332,9 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     o, v, N = wl["o"], wl["v"], wl["ncd"]
     kappa = synth.kappa_for(v, N)
-    inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=kappa)
+    inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=kappa,
+                               dtype=np.complex64 if args.c64 else np.complex128,
+                               fns_gamma=args.fns_gamma if args.fns is not None else None)
     F = ladder_flops(o, v, N)
     if args.ladder_only:
         r = run_ladder_only(args, inst)
@@ -340,9 +349,11 @@ def main():
 
     ctx = fnscc.Context(0)
     r = run_gpu(args, inst, wl, args.precision, ctx=ctx)
+    vk = r.pop("v_kept", v)
+    F = ladder_flops(o, vk, N)     # the ladder runs over the kept virtual spinors
     achieved = F / (r["ladder_ms"] * 1e-3) / 1e12 if r["ladder_ms"] > 0 else 0.0
     peak = PEAK[args.precision]
-    dim = o + o * (o - 1) // 2 * v
+    dim = o + o * (o - 1) // 2 * vk
     line = {
         "metric": "time-to-IPs (s) + ladder TFLOP/s",
         "value": r["ms_per_step"] / 1000.0,
@@ -356,11 +367,16 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "c128/f64", "split-bf16": "c128 + split-bf16 ladder", "split-fp16": "c128 + split-fp16 ladder"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"CCSD + IP-EOM-CCSD o={o} v={v} N_CD={N} complex128, {wl['roots']} roots, kappa={kappa:.4f}",
+        "config": {"workload": f"CCSD + IP-EOM-CCSD o={o} v={v} N_CD={N} {'complex64' if args.c64 else 'complex128'}, "
+                               f"{wl['roots']} roots, kappa={kappa:.4f}"
+                               + (f", FNS threshold {args.fns:g} on the generator with decay {args.fns_gamma:g}: "
+                                  f"v'={vk}" if args.fns is not None else ""),
                    "precision": args.precision, "eom_dim": dim,
                    "inputs": "host memory (PCIe-inclusive)" if args.host_inputs else "HBM"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": LADDER_TRAFFIC_BYTES.get((args.workload, args.precision)),
+                     "frac": achieved / peak,
+                     "traffic": None if (args.fns is not None or args.c64)
+                     else LADDER_TRAFFIC_BYTES.get((args.workload, args.precision)),
                      "kernel": "particle-particle ladder (assembly GEMM + contraction GEMM per ab tile)",
                      "flop_per_launch": F, "ms_per_launch": r["ladder_ms"], "launches": r["ladder_calls"]},
         "result": {"e_corr": [r["e"].real, r["e"].imag], "ccsd_iters": r["iters"], "eom_iters": r["eom_iters"],
@@ -392,7 +408,7 @@ def main():
             cmp[name]["training_s"] = t_train
         cmp["split-bf16+learned"]["training"] = info
         line["compare"] = cmp
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.fns is None:   # the oracle baseline covers untruncated solves
         line["cpu_baseline"] = cpu_baseline(inst, wl, r["iters"])
     print(json.dumps(line), flush=True)
 
