@@ -206,8 +206,9 @@ void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int
       Wps.kp = Ts.kp;
       Wps.rows_pad = (max_slots + 127) / 128 * 128 + 128;
       Wps.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp);
-      // the contraction padding (pef >= nv) is never written by the chunks: clear it once
-      FC_HIP(hipMemsetAsync(Wps.buf.p, 0, sizeof(u16) * 4 * (size_t)Wps.rows_pad * Wps.kp, ctx->stream));
+      // the contraction padding (pef >= nv) is never written by the chunks: clear it once.  Rows
+      // past a chunk's valid pairs reach only output rows that are never stored.
+      split_zero_kpad(ctx, Wps, nv);
     } else {
       Wp64 = DBuf(ctx, sizeof(z) * (size_t)max_slots * nv);
     }

@@ -59,6 +59,15 @@ __global__ void k_split(const z* __restrict__ X, long rows, long K, long ldx, lo
   }
 }
 
+// planes[p][r][k] = 0 for k0 <= k < kp, every row r < rows_pad of the four planes
+__global__ void k_zero_kpad(u16* __restrict__ planes, long rows_pad, long kp, long k0) {
+  const long w = kp - k0, total = 4 * rows_pad * w;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long r = t / w;   // plane-major rows: r = p * rows_pad + row
+    planes[r * kp + k0 + (t - r * w)] = 0;
+  }
+}
+
 __global__ void k_maxabs(const z* __restrict__ X, long rows, long K, long ldx, unsigned* out) {
   __shared__ float s[256];
   float m = 0.f;
@@ -305,6 +314,15 @@ SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long 
     k_split<FC_SPLIT_FP16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, s.rows_pad, s.kp, s.scale, (int)conj, s.buf.as<u16>());
   FC_HIP(hipGetLastError());
   return s;
+}
+
+void split_zero_kpad(fc_ctx ctx, SplitOp& S, long k0) {
+  FC_REQUIRE(k0 >= 0 && k0 <= S.kp, FC_EARG, "split_zero_kpad: column out of range");
+  const long total = 4 * S.rows_pad * (S.kp - k0);
+  if (total == 0) return;
+  unsigned nb = (unsigned)std::max(1L, std::min(65536L, (total + 255) / 256));
+  k_zero_kpad<<<nb, 256, 0, ctx->stream>>>(S.buf.as<u16>(), S.rows_pad, S.kp, k0);
+  FC_HIP(hipGetLastError());
 }
 
 void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N, z alpha,

@@ -14,6 +14,8 @@ struct SplitOp {
 
 // Split X[r * ldx + k] (r < rows, k < K), conjugated when conj.
 SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, bool conj = false);
+// Zero the contraction columns [k0, kp) of every (padded) row of the four planes.
+void split_zero_kpad(fc_ctx ctx, SplitOp& S, long k0);
 // C[m][n] = alpha sum_k A[a_row0 + m][k] B[b_row0 + n][k] + beta C[m][n]
 void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N, z alpha,
                    z beta, z* C, long ldc);
