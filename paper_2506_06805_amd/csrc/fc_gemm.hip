@@ -1,9 +1,10 @@
 // Complex GEMM on the FP64 matrix cores of gfx950.
 //
-// A complex product is four real products on v_mfma_f64_16x16x4f64:
+// In FP64 a complex product is four real products on v_mfma_f64_16x16x4f64:
 //   Cre += Are*Bre - Aim*Bim,   Cim += Are*Bim + Aim*Bre
-// (the "4M" form; no cancellation-prone 3M trick in FP64).  Operands are staged through LDS
-// with their real and imaginary parts in separate planes, conjugation applied at staging time,
+// (the "4M" form).  With FP32 arithmetic (the mixed-precision residual) it is Gauss's three
+// (3M): Are*Bre, Aim*Bim and (Are + Aim)(Bre + Bim) on v_mfma_f32_16x16x4f32.  Operands are
+// staged through LDS as interleaved complex rows, conjugation applied at staging time,
 // double-buffered so the next K slice loads while the current one feeds the matrix cores.
 //
 // Tile shapes 64 x 64 (4 waves of 32 x 32), 128 x 64 (4 waves of 64 x 32) and 128 x 128 (8 waves
@@ -174,12 +175,24 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
     }                                                                                    \
   } while (0)
 
+  // 4M (FP64): cr = sum ar br - ai bi, ci = sum ar bi + ai br, four real products per complex
+  // one.  3M (Gauss, FP32): cr = sum ar br, ci = sum ai bi, cx = sum (ar + ai)(br + bi), result
+  // cr - ci + i (cx - cr - ci), three real products per complex one (measured: 4096^3 product
+  // 127.6 -> 149.7 complex TFLOP/s).  FP64 keeps 4M: its third accumulator set (8 registers per
+  // 16 x 16 block) spills in the 128 x 128 tiles and halves the occupancy of the 64 x 64 ones.
+  constexpr bool k3M = sizeof(T) == sizeof(float);
   using Acc = typename Mfma<T>::acc;
-  Acc cr[FI][FJ], ci[FI][FJ];
+  Acc cr[FI][FJ], ci[FI][FJ], cx[k3M ? FI : 1][k3M ? FJ : 1];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
     for (int j = 0; j < FJ; ++j) { cr[i][j] = Acc{0, 0, 0, 0}; ci[i][j] = Acc{0, 0, 0, 0}; }
+  if constexpr (k3M) {
+#pragma unroll
+    for (int i = 0; i < FI; ++i)
+#pragma unroll
+      for (int j = 0; j < FJ; ++j) cx[i][j] = Acc{0, 0, 0, 0};
+  }
 
   constexpr bool kEarlyStore = sizeof(T) == sizeof(double);
   const long nk = (khi - klo + BK - 1) / BK;
@@ -206,20 +219,36 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       // (measured: +6-10% on skinny and long-K products, neutral on large ones); FP32 products
       // are twice as fast, too short to cover the global loads, and store after the step instead
       if (kEarlyStore && ks == BK - 4 && kt + 1 < nk) FC_STORE_TILE(buf ^ 1);
+      if constexpr (k3M) {
+        T sa_[FI], sb_[FJ];
 #pragma unroll
-      for (int i = 0; i < FI; ++i)
+        for (int i = 0; i < FI; ++i) sa_[i] = ar[i] + ai[i];
 #pragma unroll
-        for (int j = 0; j < FJ; ++j) {
-          cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
-          ci[i][j] = Mfma<T>::mac(ar[i], bi[j], ci[i][j]);
-        }
+        for (int j = 0; j < FJ; ++j) sb_[j] = br[j] + bi[j];
 #pragma unroll
-      for (int i = 0; i < FI; ++i)
+        for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < FJ; ++j) {
-          cr[i][j] = Mfma<T>::mac(nai[i], bi[j], cr[i][j]);
-          ci[i][j] = Mfma<T>::mac(ai[i], br[j], ci[i][j]);
-        }
+          for (int j = 0; j < FJ; ++j) {
+            cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
+            ci[i][j] = Mfma<T>::mac(ai[i], bi[j], ci[i][j]);
+            cx[i][j] = Mfma<T>::mac(sa_[i], sb_[j], cx[i][j]);
+          }
+      } else {
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FJ; ++j) {
+            cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
+            ci[i][j] = Mfma<T>::mac(ar[i], bi[j], ci[i][j]);
+          }
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+          for (int j = 0; j < FJ; ++j) {
+            cr[i][j] = Mfma<T>::mac(nai[i], bi[j], cr[i][j]);
+            ci[i][j] = Mfma<T>::mac(ai[i], br[j], ci[i][j]);
+          }
+      }
     }
     if (!kEarlyStore && kt + 1 < nk) FC_STORE_TILE(buf ^ 1);
     __syncthreads();
@@ -254,7 +283,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       for (int j = 0; j < FJ; ++j) {
         const long n = n0 + wn + 16 * j + lr;
         if (m >= g.M || n >= g.N) continue;
-        const double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
+        double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
+        if constexpr (k3M) {
+          const double p1 = re, p2 = im;
+          re = p1 - p2;
+          im = (double)cx[i][j][r] - p1 - p2;
+        }
         if (g.part) {  // split-K: raw partial sums, reduced in a fixed order afterwards
           g.part[m * g.N + n] = make_double2(re, im);
           continue;
