@@ -29,8 +29,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
-constexpr int TM = 128, TN = 128, TK = 32, NT = 512, KPAD = 8;   // 8 waves, 2 x 4, each 64 x 32
-constexpr int LDK = TK + KPAD;   // LDS row length (16-bit elements)
+constexpr int TM = 128, TN = 128, TK = 32, NT = 512;   // 8 waves, 2 x 4, each 64 x 32
+constexpr int LDK = TK;   // LDS row length (16-bit elements): 64 bytes, four 16-byte chunks
+// Chunk c of LDS row r is stored at chunk c ^ swz(r).  Fragment reads (16 consecutive rows, one
+// chunk) and staging stores (4 consecutive rows, all chunks) then touch distinct banks whether
+// the LDS serves 8 lanes x 16 bytes or 16 lanes x 16 bytes per cycle (measured on gfx950: bank
+// conflict cycles 50% of LDS-active cycles with rows padded to 80 bytes, 0 with this swizzle).
+// swz depends on r % 16 only, so fragment rows wm + 16 i + lr share the swizzle of lr.
+__device__ __forceinline__ int swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
 
 template <int PREC> __device__ inline u16 to16(float x);
 template <> __device__ inline u16 to16<FC_SPLIT_BF16>(float x) { return __builtin_bit_cast(u16, (__bf16)x); }
@@ -114,7 +120,7 @@ __device__ inline f4 mma(const u16* a, const u16* b, f4 c) {
 
 template <int PREC, int EPI>
 __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
-  // double-buffered: 2 x 80 KB, the whole LDS of a CU
+  // double-buffered: 2 x 64 KB
   __shared__ __attribute__((aligned(16))) u16 sA[2][4][TM][LDK];
   __shared__ __attribute__((aligned(16))) u16 sB[2][4][TN][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -147,6 +153,7 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
   const int srow = (tid & 511) >> 2, skc = 8 * (tid & 3);
   const long goffA = (long)srow * g.kp + skc, goffB = goffA;
+  const int sk = 8 * ((skc >> 3) ^ swz(srow));   // LDS column of this thread's staging chunk
 #define FC_GLOAD(k0)                                                                                 \
   do {                                                                                               \
     ra0 = *reinterpret_cast<const uint4*>(A + 0 * g.a_plane + goffA + (k0));                         \
@@ -160,14 +167,14 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   } while (0)
 #define FC_SSTORE(buf)                                                                               \
   do {                                                                                               \
-    *reinterpret_cast<uint4*>(&sA[buf][0][srow][skc]) = ra0;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][1][srow][skc]) = ra1;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][2][srow][skc]) = ra2;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][3][srow][skc]) = ra3;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][0][srow][skc]) = rb0;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][1][srow][skc]) = rb1;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][2][srow][skc]) = rb2;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][3][srow][skc]) = rb3;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][0][srow][sk]) = ra0;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][1][srow][sk]) = ra1;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][2][srow][sk]) = ra2;                                         \
+    *reinterpret_cast<uint4*>(&sA[buf][3][srow][sk]) = ra3;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][0][srow][sk]) = rb0;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][1][srow][sk]) = rb1;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][2][srow][sk]) = rb2;                                         \
+    *reinterpret_cast<uint4*>(&sB[buf][3][srow][sk]) = rb3;                                         \
   } while (0)
 
   f4 rr[4][2], ii[4][2], im[4][2];
@@ -176,7 +183,7 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) { rr[i][j] = f4{0, 0, 0, 0}; ii[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0}; }
 
-  const int lr = lane & 15, lk = 8 * (lane >> 4);
+  const int lr = lane & 15, lk = 8 * ((lane >> 4) ^ swz(lr));
   // one barrier per K step: the loads of the next slice are issued before the products of this
   // one and stored to the other buffer after them
   if (klo < khi) {
