@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--c64", action="store_true", help="complex64 Cholesky vectors (FP64 arithmetic)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the benchmark measures a single MI355X; --gpus must be 1"}))
         sys.exit(2)
 
     from paper_2506_06805_amd import synth
