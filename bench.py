@@ -27,10 +27,11 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp64": 78.6, "split-bf16": 2516.6, "split-fp16": 2516.6}   # TFLOP/s, MI355X dense MFMA
 
 # HBM bytes per ladder evaluation: rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, on
-# `bench.py --ladder-only --steps 2 --warmup 0 --precision fp64`, summed over the ladder's kernels
+# `bench.py --ladder-only --steps 2 --warmup 0 --precision <p>`, summed over the ladder's kernels
 # and scaled by what each counter reads for a 1 GiB device copy (FETCH x2.0, WRITE x1.0):
-# 32.95 GB fetched + 9.03 GB written.  Only for the kernels and workload it was measured on.
-LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.98e9}
+# FP64 32.95 GB fetched + 9.03 GB written; split-BF16 16.87 + 5.82 GB.  Only for the kernels and
+# workload they were measured on.
+LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.98e9, ("o24v160n500", "split-bf16"): 22.69e9}
 
 
 def ladder_flops(o, v, N):
