@@ -352,9 +352,17 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
   long ksplit = 1;
   const long nks = A.kp / TK;
   if (tiles < 512 && nks >= 16) {
-    ksplit = std::min((512 + tiles - 1) / tiles, nks / 8);
-    const long cap = std::max(1L, (256L << 20) / (long)(sizeof(z) * M * N));
-    ksplit = std::max(1L, std::min({ksplit, cap, 2048L}));
+    // one workgroup per CU (the double-buffered tile takes 128 KB of LDS): pick the split count
+    // k minimising waves(k) x (K slices per split + 4), the 4 standing for a workgroup's fixed
+    // cost, with at least 8 K slices per split, at most 16 splits and 1 GiB of partial sums
+    const long cap = std::max(1L, (1L << 30) / (long)(sizeof(z) * M * N));
+    const long kmax = std::max(1L, std::min({nks / 8, cap, 16L}));
+    double best = 0.0;
+    for (long k = 1; k <= kmax; ++k) {
+      const long waves = (tiles * k + 255) / 256;
+      const double t = (double)waves * ((double)nks / (double)k + 4.0);
+      if (k == 1 || t < best - 1e-9) { best = t; ksplit = k; }
+    }
   }
   g.kchunk = (nks + ksplit - 1) / ksplit * TK;
   ksplit = (A.kp + g.kchunk - 1) / g.kchunk;
