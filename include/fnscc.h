@@ -165,7 +165,9 @@ void fc_free_amps(fc_amps t);
 
 /* ipeom_sigma - sigma = H-bar R on the 1h + 2h1p space (Eq. 17-18) for nvec vectors.
  * R, S: device, nvec x dim complex128 (layout above). The H-bar blocks with at most two virtual
- * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3). */
+ * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3).
+ * nvec = 0 returns FC_OK without touching the device (R and S may be NULL); nvec < 0, or `t`
+ * made from another integral handle: FC_EARG. */
 int ipeom_sigma(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* R, void* S);
 
 /* ipeom_sigma_left - the left product S = Y H-bar (Eq. 19-20): each row of Y holds the

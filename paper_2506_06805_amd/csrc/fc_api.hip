@@ -578,6 +578,7 @@ void fc_free_amps(fc_amps T) { delete T; }
 
 int ipeom_sigma(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* R, void* S) {
   if (!ctx || !I || !T || nvec < 0 || (nvec > 0 && (!R || !S))) return FC_EARG;
+  if (nvec == 0) return T->ints == I ? FC_OK : FC_EARG;   // nothing to compute, no launch
   FC_TRY(ctx, {
     FC_REQUIRE(T->ints == I, FC_EARG, "ipeom_sigma: amplitudes belong to another integral handle");
     sigma_dev(ctx, I, T, nvec, (const z*)R, (z*)S);
@@ -588,6 +589,7 @@ int ipeom_sigma(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* R, void*
 
 int ipeom_sigma_left(fc_ctx ctx, fc_ints I, fc_amps T, int nvec, const void* Y, void* S) {
   if (!ctx || !I || !T || nvec < 0 || (nvec > 0 && (!Y || !S))) return FC_EARG;
+  if (nvec == 0) return T->ints == I ? FC_OK : FC_EARG;   // nothing to compute, no launch
   FC_TRY(ctx, {
     FC_REQUIRE(T->ints == I, FC_EARG, "ipeom_sigma_left: amplitudes belong to another integral handle");
     sigma_dev(ctx, I, T, nvec, (const z*)Y, (z*)S, true);
