@@ -35,3 +35,24 @@ def test_fns_parity(gpu_ctx, thresh, gamma):
     if thresh == 0.0:
         e_can, w_can = _solve_oracle(inst.L, inst.eps, o, k)
         assert abs(e - e_can) < 1e-8 and np.abs(w - w_can).max() < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
+def test_fns_then_split_precision(gpu_ctx, prec):
+    # the mixed-precision path on a truncated space: split products (hi/lo ladder and assembly,
+    # FP32 elsewhere) after FNS give IPs within 1e-5 Eh of the FP64 solve on the same space, and
+    # the truncation itself (FP64 by construction) keeps the same virtual count
+    from paper_2506_06805_amd import fnscc
+    o, v, N, k, thresh = 6, 60, 90, 4, 1e-5
+    inst = synth.make_instance(o, v, N, seed=43, kappa=synth.kappa_for(v, N), fns_gamma=6.0)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    ints2, _ = fnscc.fns_truncate(gpu_ctx, ints, thresh)
+    e, _, amps = fnscc.ccsd_solve(gpu_ctx, ints2)
+    w, _ = fnscc.ipeom_davidson(gpu_ctx, ints2, amps, k)
+    ints_s = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision=prec)
+    ints2_s, _ = fnscc.fns_truncate(gpu_ctx, ints_s, thresh)
+    assert ints2_s.v == ints2.v < v
+    e_s, _, amps_s = fnscc.ccsd_solve(gpu_ctx, ints2_s, precision=prec)
+    w_s, _ = fnscc.ipeom_davidson(gpu_ctx, ints2_s, amps_s, k)
+    assert abs(e_s - e) < 1e-5
+    assert np.abs(w_s - w).max() < 1e-5
