@@ -6,7 +6,9 @@
 * asking for every root (nroots = dim) returns the whole spectrum of the oracle's dense matrix;
 * the degenerate instance without two-electron interaction (L = 0): E_corr = 0 and the IPs are
   the eigenvalues of the then diagonal IP-EOM-CCSD matrix, -eps_i (1h) and
-  eps_a - eps_i - eps_j (2h1p), exactly.
+  eps_a - eps_i - eps_j (2h1p), exactly;
+* complex64 Cholesky vectors, from host or device memory, solve bit for bit like their exact
+  complex128 widening.
 """
 import numpy as np
 import pytest
@@ -82,3 +84,19 @@ def test_no_two_electron_interaction(gpu_ctx):
     w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, k)
     assert np.abs(w.imag).max() < 1e-12
     assert np.abs(w.real - np.sort(levels)[:k]).max() < 1e-10
+
+
+def test_complex64_vectors_equal_their_complex128_upcast(gpu_ctx):
+    # complex64 Cholesky vectors (host or device) are widened exactly when staged, so the solve
+    # matches the one on the same values given as complex128, bit for bit
+    import torch
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 4, 14, 30
+    inst = synth.make_instance(o, v, N, seed=6, kappa=synth.kappa_for(v, N))
+    L64 = inst.L.astype(np.complex64)
+    ref = fnscc.cd_integrals(gpu_ctx, inst.eps, L64.astype(np.complex128), o)
+    e_ref, _, _ = fnscc.ccsd_solve(gpu_ctx, ref)
+    for L in (L64, torch.from_numpy(L64).to("cuda")):
+        ints = fnscc.cd_integrals(gpu_ctx, inst.eps, L, o)
+        e, _, _ = fnscc.ccsd_solve(gpu_ctx, ints)
+        assert e == e_ref
