@@ -56,3 +56,31 @@ def test_fns_then_split_precision(gpu_ctx, prec):
     w_s, _ = fnscc.ipeom_davidson(gpu_ctx, ints2_s, amps_s, k)
     assert abs(e_s - e) < 1e-5
     assert np.abs(w_s - w).max() < 1e-5
+
+
+def test_fns_mid_size_structured_workload(gpu_ctx):
+    # o=16, v=120, N=360 on the FNS-structured generator: threshold 0 reproduces the canonical
+    # solve, 1e-5 truncates, and the split-BF16 solve on the truncated space stays within 1e-5 Eh
+    # of the FP64 one (no oracle at this size: the first two checks are properties of the method)
+    from paper_2506_06805_amd import fnscc
+    w0 = synth.WORKLOADS["o16v120n360"]
+    o, v, N, k = w0["o"], w0["v"], w0["ncd"], 6
+    inst = synth.make_instance(o, v, N, seed=w0["seed"], kappa=synth.kappa_for(v, N), fns_gamma=6.0)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    e_c, _, amps_c = fnscc.ccsd_solve(gpu_ctx, ints)
+    w_c, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps_c, k)
+    ints0, _ = fnscc.fns_truncate(gpu_ctx, ints, 0.0)
+    assert ints0.v == v
+    e0, _, amps0 = fnscc.ccsd_solve(gpu_ctx, ints0)
+    w0_, _ = fnscc.ipeom_davidson(gpu_ctx, ints0, amps0, k)
+    assert abs(e0 - e_c) < 1e-8 and np.abs(w0_ - w_c).max() < 1e-8
+    ints1, _ = fnscc.fns_truncate(gpu_ctx, ints, 1e-5)
+    assert 2 <= ints1.v < v
+    e1, _, amps1 = fnscc.ccsd_solve(gpu_ctx, ints1)
+    w1, _ = fnscc.ipeom_davidson(gpu_ctx, ints1, amps1, k)
+    ints_s = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision="split-bf16")
+    ints1_s, _ = fnscc.fns_truncate(gpu_ctx, ints_s, 1e-5)
+    assert ints1_s.v == ints1.v
+    e1s, _, amps1s = fnscc.ccsd_solve(gpu_ctx, ints1_s, precision="split-bf16")
+    w1s, _ = fnscc.ipeom_davidson(gpu_ctx, ints1_s, amps1s, k)
+    assert abs(e1s - e1) < 1e-5 and np.abs(w1s - w1).max() < 1e-5
