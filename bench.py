@@ -233,15 +233,24 @@ def batch_cpu_baseline(insts, iters, sample=4, rows=4):
 def cpu_baseline(inst, wl, iters, rows=8):
     """The FP64 oracle on a bounded sample of the same workload, scaled to a time-to-IPs figure.
 
-    Sample: the stored integral blocks (<= 2 virtual indices) once, and `rows` of the v rows of
-    the oracle's particle-particle ladder loop; the estimate is blocks + iterations x (ladder
-    rows x v / rows).  Other residual terms and the EOM stage are left out, so it is a lower
-    bound on the oracle's time-to-IPs.
+    Workloads with o^2 v^4 <= 1e10 (o=8, v=32) run whole: the oracle's CCSD solve and the dense
+    IP-EOM-CCSD eigenvalues.  Larger ones: the stored integral blocks (<= 2 virtual indices) once,
+    and `rows` of the v rows of the oracle's particle-particle ladder loop; the estimate is
+    blocks + iterations x (ladder rows x v / rows).  Other residual terms and the EOM stage are
+    left out, so it is a lower bound on the oracle's time-to-IPs.
     """
-    from oracle import ccsd, integrals
+    from oracle import ccsd, eom, integrals
 
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
     o, v = inst.o, inst.v
+    if wl is not None and o * o * v ** 4 <= 1e10:
+        # small enough for the whole oracle time-to-IPs: CCSD, then the dense IP-EOM eigenproblem
+        t0 = time.perf_counter()
+        _, t1, t2, _, _ = ccsd.solve(inst.L, inst.eps, o)
+        eom.dense_roots(eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2), wl["roots"])
+        t_all = time.perf_counter() - t0
+        return {"value": t_all, "unit": "s", "cores": threads, "kind": "oracle",
+                "sample": "the whole workload: oracle CCSD solve and dense IP-EOM-CCSD eigenvalues"}
     g = integrals.Blocks(inst.L, o)
     t0 = time.perf_counter()
     for name in ("oooo", "ooov", "oovv", "ovvo"):
