@@ -12,6 +12,10 @@
 // the 128-row tile, so tile loads need no bounds checks.  C[m][n] = alpha sum_k A[m][k] B[n][k]
 // + beta C[m][n] (FP64 complex output).
 //
+// Tiles are 128 x 128 (8 waves of 64 x 32), K slices of 32, double-buffered in LDS with an XOR
+// chunk swizzle (see swz); with 128 KB of LDS and 222 registers one workgroup fits per CU, which
+// is what the split-K count of skinny products is chosen for.
+//
 // MFMA 16x16x32 (bf16/f16) lane layout on gfx950 (measured): A fragment lane l holds
 // A[row = l % 16][k = 8 (l / 16) + 0..7], B fragment B[k = 8 (l / 16) + 0..7][col = l % 16],
 // accumulator register r holds D[row = 4 (l / 16) + r][col = l % 16].
