@@ -42,7 +42,9 @@ enum { FC_C128 = 0, FC_C64 = 1 };
  * FC_SPLIT_BF16 / FC_SPLIT_FP16: each FP64 operand is split into a hi and a lo part of the
  * 16-bit type, the three products hi*hi + hi*lo + lo*hi run on MFMA with FP32 accumulation; all
  * other products of the CCSD residual then run in FP32 arithmetic (FP64 storage).
- * FC_FP32 is accepted by fc_zgemm only: FP32 arithmetic on FP64 operands and result. */
+ * FC_FP32 is accepted by fc_zgemm only: FP32 arithmetic on FP64 operands and result.
+ * FP32-arithmetic complex products use three real products (Are Bre, Aim Bim and
+ * (Are + Aim)(Bre + Bim)); FP64 ones use four. */
 enum { FC_FP64 = 0, FC_SPLIT_BF16 = 1, FC_SPLIT_FP16 = 2, FC_FP32 = 3 };
 
 /* Create a context on `device`, ordering all work on `hip_stream` (a hipStream_t; NULL = the
