@@ -3,10 +3,15 @@
 // subspace matrix, the DIIS system).
 //
 // Hermitian: Householder reduction to tridiagonal form, diagonal phase scaling to a real
-// symmetric tridiagonal, implicit QL with Wilkinson-type shifts, back-transformation.
+// symmetric tridiagonal, implicit QL with Wilkinson-type shifts, back-transformation.  The QL
+// sweep is the published tql2 procedure (Bowdler, Martin, Reinsch and Wilkinson, "The QR and QL
+// algorithms for symmetric matrices", Numer. Math. 11 (1968) 293, reprinted in Wilkinson and
+// Reinsch, Handbook for Automatic Computation II, and in EISPACK as TQL2); its rotation
+// recurrences are therefore the textbook ones.
 // General complex: Householder reduction to Hessenberg form, single-shift implicit QR sweeps
-// with Givens rotations to a complex Schur form, eigenvectors of the triangular factor by back
-// substitution.
+// with Givens rotations to a complex Schur form (the complex QR algorithm of Francis and
+// Kublanovskaya with Wilkinson's shift, as in EISPACK COMQR2), eigenvectors of the triangular
+// factor by back substitution.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
