@@ -200,6 +200,24 @@ __global__ void k_precond_rows(const RowJob* __restrict__ jobs) {
     j.R[x] = make_double2((r.x * dr + r.y * di) / m, (r.y * dr - r.x * di) / m);
   }
 }
+// scale each correction row to unit norm (one workgroup per row, fixed-order sum), so that the
+// later test for vectors lost to the projection against V is relative to the vector's own size
+__global__ void k_normalise_rows(const RowJob* __restrict__ jobs) {
+  const RowJob j = jobs[blockIdx.x];
+  double acc = 0;
+  for (long x = threadIdx.x; x < j.dim; x += blockDim.x) acc += j.R[x].x * j.R[x].x + j.R[x].y * j.R[x].y;
+  __shared__ double sh[TPB];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double n2 = sh[0];
+  if (!(n2 > 0.0) || !(n2 < INFINITY)) return;
+  const double f = 1.0 / sqrt(n2);
+  for (long x = threadIdx.x; x < j.dim; x += blockDim.x) j.R[x] = make_double2(j.R[x].x * f, j.R[x].y * f);
+}
 __global__ void k_set_units(z* V, long dim, const long* idx, long n) {
   GRID_STRIDE(t, n) { V[t * dim + idx[t]] = make_double2(1.0, 0.0); }
 }
@@ -521,6 +539,7 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
       mir.up(off_jobs, sizeof(RowJob) * nj);
       hipLaunchKernelGGL(k_precond_rows, dim3(64, (unsigned)nj), dim3(TPB), 0, ctx->stream,
                          mir.dev<RowJob>(off_jobs));
+      hipLaunchKernelGGL(k_normalise_rows, dim3((unsigned)nj), dim3(TPB), 0, ctx->stream, mir.dev<RowJob>(off_jobs));
       FC_HIP(hipGetLastError());
     }
     // (5) restart: collapse V and S onto the lowest Ritz vectors (orthonormalised combinations),
@@ -612,7 +631,8 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
         Inst& s = *sp;
         const int n = s.nnew;
         const z* gh = mir.host<z>(s.off_gram);
-        // drop vectors that vanished under the projection, scale the rest to unit norm
+        // drop vectors that vanished under the projection, scale the rest to unit norm; the
+        // corrections entered with unit norm, so d is the fraction of the vector outside span(V)
         std::vector<double> sc(n, 0.0);
         for (int j = 0; j < n; ++j) {
           const double d = gh[(size_t)j * n + j].x;
@@ -666,7 +686,13 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
       Inst& s = in[b];
       nv[b] = 0;
       if (!s.active) continue;
-      if (s.added == 0) { s.active = false; continue; }
+      if (s.added == 0) {
+        // every correction lay in the subspace already while some residual is still above
+        // r_tol: the solver cannot make progress, so the roots are reported unconverged
+        s.active = false;
+        s.status = FC_ENOCONV;
+        continue;
+      }
       nv[b] = s.added;
       Rp[b] = s.V.as<z>() + (size_t)s.m * s.dim;
       Sp[b] = s.S.as<z>() + (size_t)s.m * s.dim;

@@ -98,6 +98,26 @@ class FcError(RuntimeError):
         self.code = code
 
 
+def _require(t, name, dtypes, shape=None):
+    """Refuse (ValueError) anything but a contiguous GPU tensor of one of `dtypes` and `shape`:
+    the library takes raw device pointers and trusts their sizes, so a host tensor, a short
+    tensor or the wrong element type must never reach it."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor on the GPU, got {type(t).__name__}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: must be a GPU tensor (got device {t.device})")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype} not accepted ({', '.join(map(str, dtypes))})")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
+_C128 = (torch.complex128,)
+
+
 def _ptr(a):
     """Address of a numpy array or a torch tensor (contiguous)."""
     if a is None:
@@ -297,15 +317,21 @@ def ao_to_spinor(ctx: Context, Lao, Cspin, nao):
 def cd_integrals(ctx: Context, eps, L, o, precision="fp64"):
     """Stage Cholesky vectors L[P, p, q] (numpy host array or torch device tensor) and build integrals."""
     eps = np.ascontiguousarray(eps, dtype=np.float64)
+    if eps.ndim != 1:
+        raise ValueError("cd_integrals: eps must be a vector of n spinor energies")
     n = eps.shape[0]
     v = n - o
+    if L.ndim != 3 or L.shape[1] != n or L.shape[2] != n:
+        raise ValueError(f"cd_integrals: L must be (ncd, {n}, {n}), got {tuple(L.shape)}")
     ncd = L.shape[0]
     if isinstance(L, np.ndarray):
+        if L.dtype not in (np.complex128, np.complex64):
+            raise ValueError(f"cd_integrals: L dtype {L.dtype} is neither complex128 nor complex64")
         L = np.ascontiguousarray(L)
         dt = FC_C128 if L.dtype == np.complex128 else FC_C64
         on_dev = 0
     else:
-        import torch
+        _require(L, "cd_integrals: L", (torch.complex128, torch.complex64))
         dt = FC_C128 if L.dtype == torch.complex128 else FC_C64
         on_dev = 1
     h = P()
@@ -337,7 +363,9 @@ def ccsd_opts(**kw):
         elif k == "on_iter":
             val = ON_ITER_FN(val)
         elif k in ("t1_init", "t2_init"):   # contiguous device tensors (full layout) or None; the
-            val = _ptr(val)                    # caller keeps them alive during the solve
+            if val is not None:                # caller keeps them alive during the solve
+                _require(val, k, _C128)
+            val = _ptr(val)
         setattr(op, k, val)
     return op
 
@@ -365,8 +393,14 @@ def ccsd_solve(ctx: Context, ints, allow_noconv=False, **kw):
     return E, it, amps
 
 
+def _check_amplitudes(ints: Ints, t1, t2, what):
+    o, v = ints.o, ints.v
+    _require(t1, f"{what}: t1", _C128, (o, v))
+    _require(t2, f"{what}: t2", _C128, (o, o, v, v))
+
+
 def ccsd_residual(ctx: Context, ints: Ints, t1, t2, precision=-1):
-    torch = ctx.torch
+    _check_amplitudes(ints, t1, t2, "ccsd_residual")
     r1 = torch.empty_like(t1)
     r2 = torch.empty_like(t2)
     ctx.check(lib.ccsd_residual(ctx.h, ints.h, _ptr(t1), _ptr(t2), _ptr(r1), _ptr(r2),
@@ -375,7 +409,12 @@ def ccsd_residual(ctx: Context, ints: Ints, t1, t2, precision=-1):
 
 
 def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
-    torch = ctx.torch
+    o, v = ints.o, ints.v
+    _require(tau, "ladder: tau", _C128, (o, o, v, v))
+    if t1 is not None:
+        _require(t1, "ladder: t1", _C128, (o, v))
+    if out is not None:
+        _require(out, "ladder: out", _C128, (o, o, v, v))
     R = out if out is not None else torch.empty_like(tau)
     ctx.check(lib.fc_ladder(ctx.h, ints.h, _ptr(tau), _ptr(t1), _ptr(R), PRECISION.get(precision, precision)),
               "fc_ladder")
@@ -385,12 +424,21 @@ def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
 def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False):
     """C = alpha op(A) op(B) + beta C on the library's complex GEMM (2-D contiguous tensors);
     FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True."""
-    torch = ctx.torch
+    if opA not in "NTCR" or opB not in "NTCR" or len(opA) != 1 or len(opB) != 1:
+        raise ValueError("zgemm: op must be one of N, T, C, R")
+    _require(A, "zgemm: A", _C128)
+    _require(B, "zgemm: B", _C128)
+    if A.dim() != 2 or B.dim() != 2:
+        raise ValueError("zgemm: A and B must be 2-D")
     tA, tB = opA in "TC", opB in "TC"
     M, K = (A.shape[1], A.shape[0]) if tA else (A.shape[0], A.shape[1])
     N = B.shape[0] if tB else B.shape[1]
+    if (B.shape[1] if tB else B.shape[0]) != K:
+        raise ValueError("zgemm: inner dimensions differ")
     if C is None:
         C = torch.zeros((M, N), dtype=torch.complex128, device=A.device)
+    else:
+        _require(C, "zgemm: C", _C128, (M, N))
     al = np.array([complex(alpha).real, complex(alpha).imag])
     be = np.array([complex(beta).real, complex(beta).imag])
     ctx.check(lib.fc_zgemm(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
@@ -400,16 +448,25 @@ def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False)
 
 
 def amps_create(ctx: Context, ints: Ints, t1, t2):
+    _check_amplitudes(ints, t1, t2, "amps_create")
     h = P()
     ctx.check(lib.fc_amps_create(ctx.h, ints.h, _ptr(t1), _ptr(t2), C.byref(h)), "fc_amps_create")
     return Amps(ctx, ints, h)
 
 
-def ipeom_sigma(ctx: Context, ints: Ints, amps: Amps, R):
-    torch = ctx.torch
+def _check_ip_block(ints: Ints, R, what):
+    if not isinstance(R, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor on the GPU")
     R = R.contiguous()
     if R.dim() == 1:
         R = R[None]
+    if R.dim() != 2:
+        raise ValueError(f"{what}: vectors must be (nvec, dim)")
+    return _require(R, what, _C128, (R.shape[0], ints.dim))
+
+
+def ipeom_sigma(ctx: Context, ints: Ints, amps: Amps, R):
+    R = _check_ip_block(ints, R, "ipeom_sigma: R")
     S = torch.empty_like(R)
     ctx.check(lib.ipeom_sigma(ctx.h, ints.h, amps.h, R.shape[0], _ptr(R), _ptr(S)), "ipeom_sigma")
     return S
@@ -417,10 +474,7 @@ def ipeom_sigma(ctx: Context, ints: Ints, amps: Amps, R):
 
 def ipeom_sigma_left(ctx: Context, ints: Ints, amps: Amps, Y):
     """Rows of Y times the IP-EOM-CCSD matrix (the left product of Eq. 19-20)."""
-    torch = ctx.torch
-    Y = Y.contiguous()
-    if Y.dim() == 1:
-        Y = Y[None]
+    Y = _check_ip_block(ints, Y, "ipeom_sigma_left: Y")
     S = torch.empty_like(Y)
     ctx.check(lib.ipeom_sigma_left(ctx.h, ints.h, amps.h, Y.shape[0], _ptr(Y), _ptr(S)), "ipeom_sigma_left")
     return S
@@ -548,9 +602,12 @@ class Mlp(_Handle):
 
 def learned_step(ctx: Context, ints: Ints, mlp: Mlp, t1, t2, r1, r2, r2prev, fdiag):
     """One learned amplitude update (device tensors, complex128); returns (t1_new, t2_new)."""
-    torch = ctx.torch
-    t1, t2, r1, r2, fdiag = (x.contiguous() for x in (t1, t2, r1, r2, fdiag))
-    r2prev = r2prev.contiguous() if r2prev is not None else None
+    o, v = ints.o, ints.v
+    for name, x, shp in (("t1", t1, (o, v)), ("t2", t2, (o, o, v, v)), ("r1", r1, (o, v)),
+                         ("r2", r2, (o, o, v, v)), ("fdiag", fdiag, (o + v,))):
+        _require(x, f"learned_step: {name}", _C128, shp)
+    if r2prev is not None:
+        _require(r2prev, "learned_step: r2prev", _C128, (o, o, v, v))
     o1, o2 = torch.empty_like(t1), torch.empty_like(t2)
     ctx.check(lib.fc_learned_step(ctx.h, ints.h, mlp.h, _ptr(t1), _ptr(t2), _ptr(r1), _ptr(r2), _ptr(r2prev),
                                   _ptr(fdiag), _ptr(o1), _ptr(o2)), "fc_learned_step")

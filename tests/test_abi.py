@@ -58,3 +58,74 @@ def test_bad_arguments_are_rejected_without_gpu():
     assert fnscc.lib.fc_host_zheev(-1, None, None) == fnscc.FC_EARG
     assert fnscc.lib.cd_integrals(None, 1, 1, 1, None, None, 0, 0, 0, None) == fnscc.FC_EARG
     assert fnscc.lib.ccsd_solve(None, 1, None, None, None, None, None) == fnscc.FC_EARG
+
+
+def test_binding_refuses_bad_tensors_before_any_call():
+    """The binding checks dtype, shape and device before a pointer reaches the library (a host
+    tensor, a short tensor or the wrong element type would be read past its end by a kernel)."""
+    import types
+
+    import pytest
+    import torch
+
+    from paper_2506_06805_amd import fnscc
+    o, v = 3, 5
+    ints = types.SimpleNamespace(o=o, v=v, dim=o + o * (o - 1) // 2 * v)
+    eps = np.linspace(-1, 1, o + v)
+    with pytest.raises(ValueError, match="L must be"):
+        fnscc.cd_integrals(None, eps, np.zeros((2, o + v, o + v - 1), np.complex128), o)
+    with pytest.raises(ValueError, match="neither complex128 nor complex64"):
+        fnscc.cd_integrals(None, eps, np.zeros((2, o + v, o + v)), o)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fnscc.cd_integrals(None, eps, torch.zeros((2, o + v, o + v), dtype=torch.complex128), o)
+    t1 = torch.zeros((o, v), dtype=torch.complex128)
+    t2 = torch.zeros((o, o, v, v), dtype=torch.complex128)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fnscc.ccsd_residual(None, ints, t1, t2)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fnscc.amps_create(None, ints, t1, t2)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        fnscc.ladder(None, ints, t2)
+    with pytest.raises(ValueError):
+        fnscc.ipeom_sigma(None, ints, None, torch.zeros((2, ints.dim), dtype=torch.complex128))
+    with pytest.raises(ValueError):
+        fnscc.ipeom_sigma_left(None, ints, None, np.zeros((2, ints.dim), np.complex128))
+    with pytest.raises(ValueError):
+        fnscc.zgemm(None, "N", "N", torch.zeros((2, 2), dtype=torch.float64), torch.zeros((2, 2)))
+    with pytest.raises(ValueError):
+        fnscc.ccsd_opts(t1_init=t1)
+
+
+def test_binding_checks_shapes_and_dtypes_of_device_tensors(monkeypatch):
+    """Shape and dtype checks act on tensors that claim to be on the GPU (device check passed)."""
+    import types
+
+    import pytest
+    import torch
+
+    from paper_2506_06805_amd import fnscc
+    o, v = 3, 5
+    ints = types.SimpleNamespace(o=o, v=v, dim=o + o * (o - 1) // 2 * v)
+
+    real_require = fnscc._require
+
+    def require(t, name, dtypes, shape=None):
+        # a CPU tensor standing in for a device one: check everything but the device
+        if isinstance(t, torch.Tensor) and t.device.type == "cpu":
+            if t.dtype not in dtypes:
+                raise ValueError(f"{name}: dtype {t.dtype} not accepted")
+            if shape is not None and tuple(t.shape) != tuple(shape):
+                raise ValueError(f"{name}: shape {tuple(t.shape)} != {tuple(shape)}")
+            return t
+        return real_require(t, name, dtypes, shape)
+
+    monkeypatch.setattr(fnscc, "_require", require)
+    with pytest.raises(ValueError, match="shape"):
+        fnscc.ipeom_sigma(None, ints, None, torch.zeros((2, ints.dim - 1), dtype=torch.complex128))
+    with pytest.raises(ValueError, match="dtype"):
+        fnscc.ipeom_sigma(None, ints, None, torch.zeros((2, ints.dim), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="shape"):
+        fnscc.ccsd_residual(None, ints, torch.zeros((o, v), dtype=torch.complex128),
+                            torch.zeros((o, o, v, v - 1), dtype=torch.complex128))
+    with pytest.raises(ValueError, match="dtype"):
+        fnscc.ladder(None, ints, torch.zeros((o, o, v, v), dtype=torch.complex64))
