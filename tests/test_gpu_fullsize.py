@@ -3,8 +3,13 @@ configuration), checked against the oracle where the oracle can afford it:
 
 * the particle-particle ladder on sampled rows of the virtual index a (the oracle's ladder loop,
   one row at a time), with and without T1 dressing;
+* pin P13: the oracle's own residual equations at the GPU's converged amplitudes (Omega1 whole,
+  Omega2 on sampled rows of a, where the oracle's ladder loop is exact) are solved to the
+  convergence tolerance, so those amplitudes are the oracle's fixed point;
 * the correlation energy expression at the GPU's converged amplitudes;
-* every GPU eigenpair against the oracle's H-bar built from those amplitudes;
+* every GPU eigenpair against the oracle's H-bar built from those amplitudes, and the GPU's roots
+  against the lowest roots of the oracle's own Davidson on that H-bar (1e-8 Eh), the
+  split-precision roots against them at 1e-5 Eh;
 * the mixed-precision path against the FP64 path (|dIP| <= 1e-5 Eh);
 * the left eigenvectors (Eq. 19-20): biorthonormality and the left residual projected on random
   probes through the oracle's matrix-free right product.
@@ -66,6 +71,28 @@ def test_ladder_rows_full_size(gpu_ctx, c2, dressed):
         assert err < 1e-11, (a, err)
 
 
+def test_p13_oracle_residual_at_converged_amplitudes(c2):
+    w1, w2 = ccsd.residuals(c2["g"], c2["inst"].eps, c2["t1"], c2["t2"], rows=ROWS)
+    o = c2["inst"].o
+    iu, ju = np.triu_indices(o, 1)
+    exact2 = np.concatenate([w2[iu, ju, a, :].ravel() for a in ROWS])   # rows the ladder loop covered
+    rms = np.sqrt((np.sum(np.abs(w1) ** 2) + np.sum(np.abs(exact2) ** 2)) / (w1.size + exact2.size))
+    assert rms < 1e-9, rms
+    assert np.abs(w1).max() < 1e-8 and np.abs(exact2).max() < 1e-8
+
+
+@pytest.fixture(scope="module")
+def oracle_roots(c2, hbar):
+    w, _, it = eom.davidson(hbar, c2["k"])
+    assert it < 200
+    return w
+
+
+def test_lowest_roots_against_oracle_davidson_full_size(c2, oracle_roots):
+    # the GPU returns the k roots of lowest real part, in ascending order, at 1e-8 Eh
+    assert np.abs(c2["w"] - oracle_roots).max() < 1e-8, np.abs(c2["w"] - oracle_roots).max()
+
+
 def test_energy_expression_full_size(c2):
     e = ccsd.energy(c2["g"], c2["t1"], c2["t2"])
     assert abs(e - c2["e"]) < 1e-10
@@ -79,12 +106,13 @@ def test_eigenpairs_against_oracle_hbar_full_size(c2, hbar):
         assert res < 1e-7, (r, res)
 
 
-def test_mixed_path_within_1e5_full_size(gpu_ctx, c2):
+def test_mixed_path_within_1e5_full_size(gpu_ctx, c2, oracle_roots):
     from paper_2506_06805_amd import fnscc
     inst = c2["inst"]
     ints = fnscc.cd_integrals(gpu_ctx, inst.eps, c2["L"], inst.o, precision="split-bf16")
     e, _, amps = fnscc.ccsd_solve(gpu_ctx, ints, precision="split-bf16")
     w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, c2["k"])
+    assert np.abs(w - oracle_roots).max() < 1e-5
     assert np.abs(np.sort_complex(w) - np.sort_complex(c2["w"])).max() < 1e-5
     assert abs(e - c2["e"]) < 1e-5
 

@@ -80,16 +80,30 @@ def test_mixed_residual_error(gpu_ctx, prec):
         assert rel < LADDER_TOL[prec], rel
 
 
-@pytest.mark.parametrize("prec", ["split-bf16", "split-fp16"])
-def test_mixed_solve_ip_error(gpu_ctx, prec):
-    from paper_2506_06805_amd import fnscc
-    o, v, N, k = 8, 32, 120, 4
-    inst = synth.make_instance(o, v, N, seed=1000, kappa=synth.kappa_for(v, N))
+# o=8, v=32, N=120, 4 roots (the smallest benchmark workload): the whole oracle solve against the
+# plain FP64 path (1e-8 Eh on E_corr and every IP) and against the split precisions (1e-5 Eh on
+# every IP, with the energy error they carry)
+SOLVE_TOL = {"fp64": (1e-8, 1e-8), "split-bf16": (1e-5, 1e-4), "split-fp16": (1e-5, 1e-4)}
+
+
+@pytest.fixture(scope="module")
+def c1_oracle():
+    wl = synth.WORKLOADS["o8v32n120"]
+    o, v, N, k = wl["o"], wl["v"], wl["ncd"], wl["roots"]
+    inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=synth.kappa_for(v, N))
     e_ref, t1, t2, _, conv = ccsd.solve(inst.L, inst.eps, o)
     assert conv
     w_ref, _ = eom.dense_roots(eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2), k)
-    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o, precision=prec)
+    return inst, k, e_ref, w_ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split-bf16", "split-fp16"])
+def test_solve_against_oracle_o8v32(gpu_ctx, c1_oracle, prec):
+    from paper_2506_06805_amd import fnscc
+    inst, k, e_ref, w_ref = c1_oracle
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, inst.o, precision=prec)
     e, _, amps = fnscc.ccsd_solve(gpu_ctx, ints, precision=prec)
     w, _ = fnscc.ipeom_davidson(gpu_ctx, ints, amps, k)
-    assert np.abs(w - w_ref).max() < 1e-5
-    assert abs(e - e_ref) < 1e-4
+    tol_w, tol_e = SOLVE_TOL[prec]
+    assert np.abs(w - w_ref).max() < tol_w, (prec, np.abs(w - w_ref).max())
+    assert abs(e - e_ref) < tol_e, (prec, abs(e - e_ref))
