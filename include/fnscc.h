@@ -160,6 +160,19 @@ int fc_ladder(fc_ctx ctx, fc_ints ints, const void* tau, const void* dress_t1, v
  * and sums). Stream-ordered; returns before completion. */
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
              long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision);
+/* fc_zgemm_noalloc - fc_zgemm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same arguments, layouts
+ * and result as fc_zgemm; it calls no allocator: the split-K partial sums of products with few
+ * output tiles and long K live in a fixed workspace of 128 MiB per device (a static device array
+ * set up by fc_create, held by every device the library runs on until the process ends).  The
+ * tile configuration is always the size heuristic's (or the FNSCC_GEMM_CFG override), never an
+ * autotuned one, so with autotuning off the result equals fc_zgemm's bit for bit.  A product whose
+ * partial sums would exceed the workspace (only possible with a forced large tile) is refused
+ * with FC_EARG before any launch.  Every partial sum is written before it is read, so nothing
+ * needs clearing between calls; all calls on one GPU share the one workspace, so calls that
+ * overlap in time on one GPU (several streams or threads) race. */
+int fc_zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
+                     long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision);
 /* Amplitude handles: create from device arrays (copied), read back into device arrays. */
 int fc_amps_create(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, fc_amps* out);
 int fc_amps_read(fc_amps t, void* t1, void* t2);

@@ -294,6 +294,13 @@ int fc_create(fc_ctx* out, int device, void* stream, fc_alloc_fn alloc, fc_free_
     delete c;
     return FC_EHIP;
   }
+  try {
+    noalloc_scratch_init(device);   // the device address of the fixed workspace, once per device
+  } catch (const fc::Error&) {
+    (void)hipGetLastError();
+    delete c;
+    return FC_EHIP;
+  }
   *out = c;
   return FC_OK;
 }
@@ -524,6 +531,20 @@ int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const doubl
     Fp32Gemms fp32(ctx, precision == FC_FP32);
     zgemm(ctx, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B, ldb,
           make_double2(beta[0], beta[1]), (z*)C, ldc);
+    return FC_OK;
+  })
+}
+
+int fc_zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
+                     long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision) {
+  if (!ctx || !alpha || !beta || M < 0 || N < 0 || K < 0) return FC_EARG;
+  if (precision != FC_FP64 && precision != FC_FP32) return FC_EARG;
+  if (M == 0 || N == 0) return FC_OK;
+  if (!C || (K > 0 && (!A || !B))) return FC_EARG;
+  FC_TRY(ctx, {
+    Fp32Gemms fp32(ctx, precision == FC_FP32);
+    zgemm_noalloc(ctx, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B, ldb,
+                  make_double2(beta[0], beta[1]), (z*)C, ldc);
     return FC_OK;
   })
 }

@@ -17,6 +17,7 @@
 //   accumulator register r: D[row = l / 16 + 4 * r][col = l % 16]  (measured on gfx950).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "fc_internal.hpp"
 #include "fc_gemm.hpp"
@@ -425,9 +426,11 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
 }
 
 // Launch one configuration (split-K decided inside for configurations whose grid cannot fill the chip).
+// fixed_part: when given, split-K partial sums go there (at most NOALLOC_SCRATCH_BYTES) instead
+// of into a buffer from the context's allocator.
 void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
-               const LadderEpilogue* lep);
+               const LadderEpilogue* lep, z* fixed_part = nullptr);
 
 // Shape bucket: operand layouts, sizes rounded to powers of two, batching and epilogue kind.
 std::string bucket(char opA, char opB, long M, long N, long K, int batch, const LadderEpilogue* lep, int fp32) {
@@ -456,16 +459,22 @@ bool cfg_fits(int c, long M, long N) {
   return (CFG_BM[c] <= 64 || M >= 128) && (CFG_BN[c] <= 64 || N >= 96);
 }
 
+// Tuning override: FNSCC_GEMM_CFG selects one configuration for every product it fits.
+int forced_cfg(long M, long N) {
+  static const int forced = [] {
+    const char* e = getenv("FNSCC_GEMM_CFG");
+    return e ? atoi(e) : -1;
+  }();
+  return (forced >= 0 && forced < NCFG && cfg_fits(forced, M, N)) ? forced : -1;
+}
+
 void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B,
                 long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC, const LadderEpilogue* lep) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   int cfg = heuristic_cfg(M, N, K, batch, !lep && ctx->gemm_fp32);
-  static const int forced = [] {
-    const char* e = getenv("FNSCC_GEMM_CFG");   // tuning override: one configuration for every product
-    return e ? atoi(e) : -1;
-  }();
-  if (forced >= 0 && forced < NCFG && cfg_fits(forced, M, N)) {
+  const int forced = forced_cfg(M, N);
+  if (forced >= 0) {
     cfg = forced;
   } else if (ctx->autotune && K > 0) {
     const std::string key = bucket(opA, opB, M, N, K, batch, lep, lep ? 0 : ctx->gemm_fp32);
@@ -476,7 +485,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
       // time every configuration once (after one warm-up launch) on a scratch copy of C, keep the fastest
       const long csz = lep ? (M / lep->v) * lep->nB * lep->v * lep->v
                            : ((long)(batch - 1) * sC + (M - 1) * ldc + N);
-      DBuf scratch(ctx, sizeof(z) * (size_t)std::max(1L, csz));
+      DBuf trial(ctx, sizeof(z) * (size_t)std::max(1L, csz));
       hipEvent_t e0, e1;
       FC_HIP(hipEventCreate(&e0));
       FC_HIP(hipEventCreate(&e1));
@@ -487,9 +496,9 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
           if (!lep && (beta.x != 0.0 || beta.y != 0.0))
-            FC_HIP(hipMemcpyAsync(scratch.p, C, sizeof(z) * csz, hipMemcpyDeviceToDevice, ctx->stream));
+            FC_HIP(hipMemcpyAsync(trial.p, C, sizeof(z) * csz, hipMemcpyDeviceToDevice, ctx->stream));
           FC_HIP(hipEventRecord(e0, ctx->stream));
-          zgemm_run(ctx, c, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, scratch.as<z>(), ldc, batch, sA, sB, sC, lep);
+          zgemm_run(ctx, c, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, trial.as<z>(), ldc, batch, sA, sB, sC, lep);
           FC_HIP(hipEventRecord(e1, ctx->stream));
           FC_HIP(hipEventSynchronize(e1));
           FC_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -507,7 +516,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
 
 void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
-               const LadderEpilogue* lep) {
+               const LadderEpilogue* lep, z* fixed_part) {
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   if (K <= 0) {  // C = beta C
     FC_REQUIRE(!lep, FC_EARG, "zgemm: empty ladder product");
@@ -549,8 +558,16 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   g.part = nullptr;
   DBuf work;
   if (ksplit > 1) {
-    work = DBuf(ctx, sizeof(z) * (size_t)ksplit * M * N);
-    g.part = work.as<z>();
+    const size_t need = sizeof(z) * (size_t)ksplit * M * N;
+    if (fixed_part) {
+      FC_REQUIRE(need <= NOALLOC_SCRATCH_BYTES, FC_EARG,
+                 "fc_zgemm_noalloc: the split-K partial sums of this product need " + std::to_string(need) +
+                     " bytes, more than the " + std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte fixed workspace");
+      g.part = fixed_part;
+    } else {
+      work = DBuf(ctx, need);
+      g.part = work.as<z>();
+    }
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit, (unsigned)batch);
   // FNSCC_VERBOSE >= 3: every product is timed on its own (synchronising) and logged
@@ -794,6 +811,50 @@ void GroupArena::run(const std::vector<GroupGemm>& probs, const GroupTiling& tl)
 }
 
 int gemm_num_configs() { return NCFG; }
+
+// ------------------------------------------------------------------------------------------------
+// Fixed workspace of the allocation-free product.  Each device holds its own copy of this array
+// from module load until the process ends.  Host code never uses the array's name as an address:
+// noalloc_scratch_init looks its device address up once per device (with that device current)
+// and every kernel argument uses that pointer.  Sized for every split the default tile choice
+// makes: fewer than 1024 + tiles - 1 split tiles of at most 64 x 64 outputs each, i.e. under
+// 2048 x 4096 complex partial sums.
+__device__ __align__(256) static double2 scratch[NOALLOC_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+std::mutex g_scratch_mu;
+constexpr int MAX_DEVICES = 64;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  FC_REQUIRE(device >= 0 && device < MAX_DEVICES, FC_EARG, "device index out of range");
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  FC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  FC_REQUIRE(p != nullptr, FC_EHIP, "hipGetSymbolAddress returned no address for the fixed workspace");
+  g_scratch_ptr[device] = p;
+}
+
+void zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+                   const z* B, long ldb, z beta, z* C, long ldc) {
+  if (M <= 0 || N <= 0) return;
+  FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
+  void* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (ctx->device >= 0 && ctx->device < MAX_DEVICES) part = g_scratch_ptr[ctx->device];
+  }
+  FC_REQUIRE(part != nullptr, FC_EHIP, "fc_zgemm_noalloc: fixed workspace not set up on this device");
+  // the size heuristic (or the forced configuration), never the autotuner: timing trial products
+  // needs a buffer of its own
+  int cfg = heuristic_cfg(M, N, K, 1, ctx->gemm_fp32);
+  const int forced = forced_cfg(M, N);
+  if (forced >= 0) cfg = forced;
+  zgemm_run(ctx, cfg, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, 0, 0, 0, nullptr,
+            static_cast<z*>(part));
+}
 
 void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B, long ldb,
            z beta, z* C, long ldc, int batch, long sA, long sB, long sC) {

@@ -16,6 +16,14 @@ struct LadderEpilogue {
 // Number of tile configurations the FP64 product kernels offer (autotuner table entries).
 int gemm_num_configs();
 
+// Allocation-free complex product (fc_zgemm_noalloc): split-K partial sums in a fixed per-device
+// workspace of NOALLOC_SCRATCH_BYTES instead of an allocated buffer.  noalloc_scratch_init looks
+// the workspace address up for `device` (which must be current); fc_create calls it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(128) << 20;
+void noalloc_scratch_init(int device);
+void zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+                   const z* B, long ldb, z beta, z* C, long ldc);
+
 // W = A B^T in the ladder layout, FP64 (A[m * lda + k], B[n * ldb + k]).
 void zgemm_ladder(fc_ctx ctx, long M, long N, long K, const z* A, long lda, const z* B, long ldb, z* W,
                   const LadderEpilogue& lep);

@@ -64,6 +64,8 @@ _sig = {
     "fc_ladder": (C.c_int, [P, P, P, P, P, C.c_int]),
     "fc_zgemm": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P, C.c_long,
                            P, P, C.c_long, C.c_int]),
+    "fc_zgemm_noalloc": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P,
+                                   C.c_long, P, P, C.c_long, C.c_int]),
     "fc_amps_create": (C.c_int, [P, P, P, P, C.POINTER(P)]),
     "fc_amps_read": (C.c_int, [P, P, P]),
     "fc_free_amps": (None, [P]),
@@ -421,9 +423,10 @@ def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
     return R
 
 
-def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False):
+def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False, noalloc=False):
     """C = alpha op(A) op(B) + beta C on the library's complex GEMM (2-D contiguous tensors);
-    FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True."""
+    FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True.  noalloc=True calls
+    fc_zgemm_noalloc (no device allocation inside the library; C must then be given)."""
     if opA not in "NTCR" or opB not in "NTCR" or len(opA) != 1 or len(opB) != 1:
         raise ValueError("zgemm: op must be one of N, T, C, R")
     _require(A, "zgemm: A", _C128)
@@ -436,14 +439,16 @@ def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False)
     if (B.shape[1] if tB else B.shape[0]) != K:
         raise ValueError("zgemm: inner dimensions differ")
     if C is None:
+        if noalloc:
+            raise ValueError("zgemm: the allocation-free product writes into a given C")
         C = torch.zeros((M, N), dtype=torch.complex128, device=A.device)
     else:
         _require(C, "zgemm: C", _C128, (M, N))
     al = np.array([complex(alpha).real, complex(alpha).imag])
     be = np.array([complex(beta).real, complex(beta).imag])
-    ctx.check(lib.fc_zgemm(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
-                           _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1], FC_FP32 if fp32 else FC_FP64),
-              "fc_zgemm")
+    fn, name = (lib.fc_zgemm_noalloc, "fc_zgemm_noalloc") if noalloc else (lib.fc_zgemm, "fc_zgemm")
+    ctx.check(fn(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
+                 _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1], FC_FP32 if fp32 else FC_FP64), name)
     return C
 
 
