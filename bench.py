@@ -32,6 +32,47 @@ PEAK = {"fp64": 78.6, "split-bf16": 2516.6, "split-fp16": 2516.6}   # TFLOP/s, M
 # FP64 32.95 GB fetched + 9.03 GB written; split-BF16 16.87 + 5.82 GB.  Only for the kernels and
 # workload they were measured on.
 LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.98e9, ("o24v160n500", "split-bf16"): 22.69e9}
+TRAFFIC_SOURCE = ("profile constant, not counted in this run: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                  "summed over the ladder kernels of the same kernel version and workload "
+                  "(profiles/ladder_o24v160n500.md), each scaled by its reading for a 1 GiB copy")
+
+
+def host_cpu():
+    """CPU model, physical cores and logical CPUs of this host (from /proc/cpuinfo), and the BLAS
+    threads the oracle runs with (OMP_NUM_THREADS, else every logical CPU)."""
+    model, phys = "unknown", set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cur = {}
+            for line in f:
+                if ":" in line:
+                    k, v = (x.strip() for x in line.split(":", 1))
+                    cur[k] = v
+                    if k == "model name":
+                        model = v
+                elif cur:
+                    phys.add((cur.get("physical id", "0"), cur.get("core id", cur.get("processor"))))
+                    cur = {}
+            if cur:
+                phys.add((cur.get("physical id", "0"), cur.get("core id", cur.get("processor"))))
+    except OSError:
+        pass
+    logical = os.cpu_count() or 1
+    threads = int(os.environ.get("OMP_NUM_THREADS") or logical)
+    return {"threads": threads, "cpu_model": model, "physical_cores": len(phys) or None, "logical_cpus": logical}
+
+
+def _cpu_line(value, sample):
+    h = host_cpu()
+    return {"value": value, "unit": "s", "cores": h["threads"], "kind": "oracle", "sample": sample,
+            "cpu_model": h["cpu_model"], "host_physical_cores": h["physical_cores"],
+            "host_logical_cpus": h["logical_cpus"]}
+
+
+# FP64 ladder rate measured at o=40, v=600, N=1800 (bench.py --ladder-only --workload o40v600n1800
+# --precision fp64): the basis of the extrapolated FP64 time at shapes where an FP64 ladder would
+# take tens of minutes
+FP64_LADDER_RATE = 60.2e12
 
 
 def ladder_flops(o, v, N):
@@ -118,35 +159,72 @@ def train_update_network(ctx, count=16, seed=7):
                                            "epochs": 12, "loss_first": hist[0], "loss_last": hist[-1]}
 
 
-def run_ladder_only(args, inst):
-    """Ladder evaluations alone (random antisymmetric tau, T1-dressed vectors), timed with hipEvents."""
+def run_ladder_only(args, inst, wl):
+    """Ladder evaluations alone (random tau, T1-dressed vectors), timed with hipEvents.
+
+    Workloads drawn on the device (o=40, v=1698, N=4000) keep their complex64 vectors in complex64
+    and run the ladder on packed amplitudes (tau and R over i<j, a<b): their full-layout complex128
+    o^2 v^2 arrays would take 74 GB each."""
     import torch
 
-    from paper_2506_06805_amd import fnscc
+    from paper_2506_06805_amd import fnscc, synth
 
     ctx = fnscc.Context(0)
-    o, v = inst.o, inst.v
-    ints = fnscc.cd_integrals(ctx, inst.eps, torch.from_numpy(inst.L).to("cuda"), o, precision=args.precision)
-    g = torch.Generator(device="cpu").manual_seed(0)
-    tau = 1e-2 * torch.randn((o, o, v, v), dtype=torch.complex128, generator=g)
-    tau = (tau - tau.transpose(0, 1)) - (tau - tau.transpose(0, 1)).transpose(2, 3)
-    tau = tau.contiguous().to("cuda")
-    t1 = (1e-2 * torch.randn((o, v), dtype=torch.complex128, generator=g)).to("cuda")
+    o, v, N = wl["o"], wl["v"], wl["ncd"]
+    torch.cuda.reset_peak_memory_stats()
+    t_setup = time.perf_counter()
+    if wl.get("device"):
+        eps, L = synth.make_instance_device(o, v, N, seed=wl["seed"], kappa=synth.kappa_for(v, N))
+        ints = fnscc.cd_integrals(ctx, eps, L, o, precision=args.precision)
+        del L
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    else:
+        ints = fnscc.cd_integrals(ctx, inst.eps, torch.from_numpy(inst.L).to("cuda"), o, precision=args.precision)
+    packed = bool(wl.get("device")) or args.packed
+    g = torch.Generator(device="cuda").manual_seed(0)
+    if packed:
+        no, nv = o * (o - 1) // 2, v * (v - 1) // 2
+        tau = torch.randn((no, nv), dtype=torch.complex128, device="cuda", generator=g).mul_(1e-2)
+    else:
+        gc = torch.Generator(device="cpu").manual_seed(0)
+        tau = 1e-2 * torch.randn((o, o, v, v), dtype=torch.complex128, generator=gc)
+        tau = (tau - tau.transpose(0, 1)) - (tau - tau.transpose(0, 1)).transpose(2, 3)
+        tau = tau.contiguous().to("cuda")
+    t1 = torch.randn((o, v), dtype=torch.complex128, device="cuda", generator=g).mul_(1e-2)
     R = torch.empty_like(tau)
+
+    def run():
+        if packed:
+            fnscc.ladder_packed(ctx, ints, tau, t1, precision=args.precision, out=R)
+        else:
+            fnscc.ladder(ctx, ints, tau, t1, precision=args.precision, out=R)
+
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
     for _ in range(args.warmup):
-        fnscc.ladder(ctx, ints, tau, t1, precision=args.precision, out=R)
+        run()
     torch.cuda.synchronize()
     ctx.set_timing(2)
     ctx.take_timings()
     t0 = time.perf_counter()
     for s in range(args.steps):
-        fnscc.ladder(ctx, ints, tau, t1, precision=args.precision, out=R)
+        run()
+        print(f"[bench] ladder {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1_ = time.perf_counter()
     tm = ctx.take_timings()
     n = max(tm.get("ladder_events", 0.0), 1.0)
+    props = torch.cuda.get_device_properties(0)
+    mem = {"peak_allocated_GB": torch.cuda.max_memory_allocated() / 1e9,
+           "peak_reserved_GB": torch.cuda.max_memory_reserved() / 1e9,
+           "device_total_GB": props.total_memory / 1e9,
+           "L_vv_GB": v * v * N * (8 if wl.get("device") else 16) / 1e9,
+           "split_planes_GB": 8.0 * v * v * N / 1e9 if args.precision != "fp64" else 0.0,
+           "tau_GB": tau.numel() * 16 / 1e9, "R_GB": R.numel() * 16 / 1e9,
+           "amplitude_layout": "packed i<j, a<b" if packed else "full o x o x v x v"}
     return dict(ms_per_step=(t1_ - t0) * 1000.0 / args.steps, ladder_ms=tm.get("ladder_event_ms", 0.0) / n,
-                ladder_calls=n)
+                ladder_calls=n, memory=mem, setup_s=t_setup)
 
 
 def run_batch(args, bw):
@@ -224,10 +302,8 @@ def batch_cpu_baseline(insts, iters, sample=4, rows=4):
         per.append(b["value"] / (x.o ** 2 * x.v ** 4 + x.ncd * x.v ** 4))
     scale = float(np.median(per))
     est = sum(scale * (x.o ** 2 * x.v ** 4 + x.ncd * x.v ** 4) for x in insts)
-    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle lower bound (stored blocks + sampled ladder rows) on instances {pick}, "
-                       f"scaled to the batch by the o^2 v^4 + N v^4 ladder cost; other terms and EOM not included")}
+    return _cpu_line(est, (f"oracle lower bound (stored blocks + sampled ladder rows) on instances {pick}, "
+                           f"scaled to the batch by the o^2 v^4 + N v^4 ladder cost; other terms and EOM not included"))
 
 
 def cpu_baseline(inst, wl, iters, rows=8, other_terms=True):
@@ -241,7 +317,6 @@ def cpu_baseline(inst, wl, iters, rows=8, other_terms=True):
     """
     from oracle import ccsd, eom, integrals
 
-    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
     o, v = inst.o, inst.v
     if wl is not None and o * o * v ** 4 <= 1e10:
         # small enough for the whole oracle time-to-IPs: CCSD, then the dense IP-EOM eigenproblem
@@ -249,8 +324,7 @@ def cpu_baseline(inst, wl, iters, rows=8, other_terms=True):
         _, t1, t2, _, _ = ccsd.solve(inst.L, inst.eps, o)
         eom.dense_roots(eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2), wl["roots"])
         t_all = time.perf_counter() - t0
-        return {"value": t_all, "unit": "s", "cores": threads, "kind": "oracle",
-                "sample": "the whole workload: oracle CCSD solve and dense IP-EOM-CCSD eigenvalues"}
+        return _cpu_line(t_all, "the whole workload: oracle CCSD solve and dense IP-EOM-CCSD eigenvalues")
     g = integrals.Blocks(inst.L, o)
     t0 = time.perf_counter()
     for name in ("oooo", "ooov", "oovv", "ovvo"):
@@ -268,10 +342,9 @@ def cpu_baseline(inst, wl, iters, rows=8, other_terms=True):
     t_ladder = t_rows * v / rows
     if not other_terms:
         est = t_blocks + iters * t_ladder
-        return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
-                "sample": (f"stored integral blocks {t_blocks:.1f} s + oracle ladder on {rows} of {v} rows "
-                           f"{t_rows:.1f} s, scaled to {t_ladder:.1f} s per iteration x {iters} CCSD iterations; "
-                           "other residual terms and the EOM stage not included (lower bound)")}
+        return _cpu_line(est, (f"stored integral blocks {t_blocks:.1f} s + oracle ladder on {rows} of {v} rows "
+                               f"{t_rows:.1f} s, scaled to {t_ladder:.1f} s per iteration x {iters} CCSD iterations; "
+                               "other residual terms and the EOM stage not included (lower bound)"))
     # every other term of one residual: the residual with an empty ladder row set, twice; the first
     # call also forms the three-virtual blocks, a one-time cost of the solve
     t0 = time.perf_counter()
@@ -282,11 +355,10 @@ def cpu_baseline(inst, wl, iters, rows=8, other_terms=True):
     t_rest = time.perf_counter() - t0
     t_once = t_blocks + max(0.0, t_first - t_rest)
     est = t_once + iters * (t_ladder + t_rest)
-    return {"value": est, "unit": "s", "cores": threads, "kind": "oracle",
-            "sample": (f"integral blocks {t_once:.1f} s once + per CCSD iteration the oracle ladder "
-                       f"({rows} of {v} rows in {t_rows:.1f} s, scaled to {t_ladder:.1f} s) and the other "
-                       f"residual terms ({t_rest:.1f} s), x {iters} iterations; the EOM stage not included "
-                       "(lower bound)")}
+    return _cpu_line(est, (f"integral blocks {t_once:.1f} s once + per CCSD iteration the oracle ladder "
+                           f"({rows} of {v} rows in {t_rows:.1f} s, scaled to {t_ladder:.1f} s) and the other "
+                           f"residual terms ({t_rest:.1f} s), x {iters} iterations; the EOM stage not included "
+                           "(lower bound)"))
 
 
 def main():
@@ -312,6 +384,8 @@ def main():
     ap.add_argument("--fns-gamma", type=float, default=6.0,
                     help="decay of the FNS-structured generator used with --fns")
     ap.add_argument("--c64", action="store_true", help="complex64 Cholesky vectors (FP64 arithmetic)")
+    ap.add_argument("--packed", action="store_true",
+                    help="with --ladder-only: the ladder on packed amplitudes (fc_ladder_packed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "one GPU only: the benchmark measures a single MI355X; --gpus must be 1"}))
@@ -358,18 +432,33 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     o, v, N = wl["o"], wl["v"], wl["ncd"]
     kappa = synth.kappa_for(v, N)
-    inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=kappa,
-                               dtype=np.complex64 if args.c64 else np.complex128,
-                               fns_gamma=args.fns_gamma if args.fns is not None else None)
     F = ladder_flops(o, v, N)
+    if wl.get("device") and not args.ladder_only:
+        print(json.dumps({"error": f"{args.workload}: only --ladder-only runs at this shape (the CCSD residual's "
+                                   "other terms still use full o^2 v^2 intermediates, 74 GB each)"}))
+        sys.exit(2)
+    inst = None
+    if not wl.get("device"):
+        inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=kappa,
+                                   dtype=np.complex64 if args.c64 else np.complex128,
+                                   fns_gamma=args.fns_gamma if args.fns is not None else None)
     if args.ladder_only:
-        r = run_ladder_only(args, inst)
+        r = run_ladder_only(args, inst, wl)
         achieved = F / (r["ladder_ms"] * 1e-3) / 1e12
-        print(json.dumps({"metric": "ladder TFLOP/s (algorithmic)", "value": achieved, "unit": "TFLOP/s",
-                          "ms_per_launch": r["ladder_ms"], "launches": r["ladder_calls"],
-                          "flop_per_launch": F, "precision": args.precision,
-                          "frac": achieved / PEAK[args.precision],
-                          "config": {"workload": f"ladder o={o} v={v} N_CD={N}"}}), flush=True)
+        line = {"metric": "ladder TFLOP/s (algorithmic)", "value": achieved, "unit": "TFLOP/s",
+                "ms_per_launch": r["ladder_ms"], "launches": r["ladder_calls"],
+                "flop_per_launch": F, "precision": args.precision,
+                "frac": achieved / PEAK[args.precision],
+                "config": {"workload": f"ladder o={o} v={v} N_CD={N}"
+                           + (", complex64 vectors drawn on the device, packed tau and R" if wl.get("device") else ""),
+                           "kappa": kappa},
+                "memory": r["memory"], "setup_s": r["setup_s"]}
+        if args.precision != "fp64":
+            line["fp64_extrapolated_s"] = {
+                "value": F / FP64_LADDER_RATE, "note": ("extrapolated, not measured: this ladder's flops at the FP64 "
+                                                        f"ladder rate measured at o=40 v=600 N=1800 "
+                                                        f"({FP64_LADDER_RATE / 1e12:.1f} TFLOP/s)")}
+        print(json.dumps(line), flush=True)
         return
     from paper_2506_06805_amd import fnscc
 
@@ -380,6 +469,7 @@ def main():
     achieved = F / (r["ladder_ms"] * 1e-3) / 1e12 if r["ladder_ms"] > 0 else 0.0
     peak = PEAK[args.precision]
     dim = o + o * (o - 1) // 2 * vk
+    traffic = None if (args.fns is not None or args.c64) else LADDER_TRAFFIC_BYTES.get((args.workload, args.precision))
     line = {
         "metric": "time-to-IPs (s) + ladder TFLOP/s",
         "value": r["ms_per_step"] / 1000.0,
@@ -401,13 +491,24 @@ def main():
                    "inputs": "host memory (PCIe-inclusive)" if args.host_inputs else "HBM"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": None if (args.fns is not None or args.c64)
-                     else LADDER_TRAFFIC_BYTES.get((args.workload, args.precision)),
+                     "traffic": traffic,
+                     "traffic_source": (TRAFFIC_SOURCE if traffic is not None else
+                                        "no counter profile of this kernel version on this workload"),
                      "kernel": "particle-particle ladder (assembly GEMM + contraction GEMM per ab tile)",
                      "flop_per_launch": F, "ms_per_launch": r["ladder_ms"], "launches": r["ladder_calls"]},
         "result": {"e_corr": [r["e"].real, r["e"].imag], "ccsd_iters": r["iters"], "eom_iters": r["eom_iters"],
                    "ips": [float(x) for x in np.real(r["w"])]},
     }
+    if not args.host_inputs and args.steps > 0:
+        # the same step with the Cholesky vectors handed over from host memory (cd_integrals copies
+        # them over PCIe inside the timed region): the PCIe-inclusive figure, never `value`
+        import copy
+        ah = copy.copy(args)
+        ah.host_inputs, ah.warmup, ah.steps = True, 0, min(2, args.steps)
+        rh = run_gpu(ah, inst, wl, args.precision, ctx=ctx)
+        line["host_inputs"] = {"time_to_ips_s": rh["ms_per_step"] / 1000.0, "steps": ah.steps,
+                               "delta_vs_hbm_s": (rh["ms_per_step"] - r["ms_per_step"]) / 1000.0,
+                               "bytes_over_pcie": int(inst.L.nbytes)}
     if args.left:
         line["left_vectors"] = left_vectors(ctx, r, wl["roots"])
     r.pop("ints", None)

@@ -152,6 +152,14 @@ int ccsd_residual(fc_ctx ctx, fc_ints ints, const void* t1, const void* t2, void
  * replaced by L_ae - sum_m t_m^a L_me on both factors. */
 int fc_ladder(fc_ctx ctx, fc_ints ints, const void* tau, const void* dress_t1, void* R,
               int precision);
+/* fc_ladder_packed - the same ladder on the unique amplitudes only, for shapes whose full o^2 v^2
+ * arrays do not fit (o = 40, v = 1698: 74 GB per full complex128 tensor, 18 GB packed).
+ * taup: device, C(o,2) x C(v,2) complex128, taup[pij][pef] = tau_ij^ef for i < j, e < f, pairs in
+ * lexicographic order (p = i (2n - i - 1) / 2 + j - i - 1).  Rp: device, C(o,2) x C(v,2)
+ * complex128, Rp[pij][pab] = R_ij^ab for i < j, a < b (overwritten).  dress_t1 as fc_ladder.
+ * precision: FC_FP64 / FC_SPLIT_BF16 / FC_SPLIT_FP16, or -1 for the handle's.  Synchronises the
+ * context stream before returning. */
+int fc_ladder_packed(fc_ctx ctx, fc_ints ints, const void* taup, const void* dress_t1, void* Rp, int precision);
 /* fc_zgemm - the library's complex FP64 matrix product on the matrix cores (every contraction of
  * Eq. 12-18 and 23 reduces to it): C = alpha op(A) op(B) + beta C, row-major, device pointers to
  * interleaved complex128. opA: 'N' A[m*lda+k], 'T' A[k*lda+m], 'C' conj(A[k*lda+m]),

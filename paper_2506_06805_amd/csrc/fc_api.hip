@@ -31,16 +31,22 @@ __global__ void k_mp2_amp(const z* vvoo, const double* eps, z* t, long o, long v
 }  // namespace
 
 // ------------------------------------------------------------------------------ CCSD driver
+// DIIS history over the unique amplitudes (t1, then t2 for i < j, a < b): a quarter of the doubles
+// of the full layout per vector.  Inner products weight the packed t2 part by 4, so the Gram
+// matrix and the extrapolation are those of the full antisymmetric vectors.
 struct DiisState {
   int size = 8;
-  long nt = 0;
-  DBuf vecs, errs;
+  long o = 0, v = 0, n1 = 0, nt = 0;   // nt: packed length
+  DBuf vecs, errs, tmp;
   std::deque<int> order;          // slots, oldest first
   std::vector<z> B;               // size x size, by slot
-  void init(fc_ctx ctx, int sz, long n) {
-    size = sz; nt = n;
-    vecs = DBuf(ctx, sizeof(z) * (size_t)sz * n);
-    errs = DBuf(ctx, sizeof(z) * (size_t)sz * n);
+  void init(fc_ctx ctx, int sz, long o_, long v_) {
+    size = sz; o = o_; v = v_;
+    n1 = o * v;
+    nt = n1 + (o * (o - 1) / 2) * (v * (v - 1) / 2);
+    vecs = DBuf(ctx, sizeof(z) * (size_t)sz * nt);
+    errs = DBuf(ctx, sizeof(z) * (size_t)sz * nt);
+    tmp = DBuf(ctx, sizeof(z) * (size_t)nt);
     B.assign((size_t)sz * sz, make_double2(0, 0));
     order.clear();
   }
@@ -48,7 +54,7 @@ struct DiisState {
   z* err(int s) { return errs.as<z>() + (size_t)s * nt; }
 };
 
-// push (t_new, t_new - t_old) and write the extrapolated amplitudes into out
+// push (t_new, t_new - t_old) (full layout) and write the extrapolated amplitudes (full layout) into out
 static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const z* told, z* out) {
   int slot;
   if ((int)D.order.size() < D.size) {
@@ -60,15 +66,17 @@ static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const
     slot = D.order.front();
     D.order.pop_front();
   }
-  diis_push(ctx, D.nt, tnew, told, D.vec(slot), D.err(slot));
+  diis_push_packed(ctx, D.o, D.v, tnew, told, D.vec(slot), D.err(slot));
   D.order.push_back(slot);
   {
     const std::vector<int> sl(D.order.begin(), D.order.end());
-    std::vector<z> bs(sl.size());
-    multi_dotc(ctx, D.nt, D.err(slot), D.err(0), D.nt, sl.data(), (int)sl.size(), bs.data());
+    std::vector<z> b1(sl.size()), b2(sl.size());
+    multi_dotc(ctx, D.n1, D.err(slot), D.err(0), D.nt, sl.data(), (int)sl.size(), b1.data());
+    multi_dotc(ctx, D.nt - D.n1, D.err(slot) + D.n1, D.err(0) + D.n1, D.nt, sl.data(), (int)sl.size(), b2.data());
     for (size_t k = 0; k < sl.size(); ++k) {
-      D.B[slot * D.size + sl[k]] = bs[k];
-      D.B[sl[k] * D.size + slot] = make_double2(bs[k].x, -bs[k].y);
+      const z bs = make_double2(b1[k].x + 4.0 * b2[k].x, b1[k].y + 4.0 * b2[k].y);
+      D.B[slot * D.size + sl[k]] = bs;
+      D.B[sl[k] * D.size + slot] = make_double2(bs.x, -bs.y);
     }
   }
   while (D.order.size() >= 2) {
@@ -86,12 +94,13 @@ static void diis_push_extrapolate(fc_ctx ctx, DiisState& D, const z* tnew, const
     rhs[m] = make_double2(1, 0);
     if (cond_herm(m + 1, A) < 1e12 && lin_solve(m + 1, A, rhs)) {
       const std::vector<int> sl(D.order.begin(), D.order.end());
-      lincomb(ctx, D.nt, D.vec(0), D.nt, sl.data(), rhs.data(), m, out);
+      lincomb(ctx, D.nt, D.vec(0), D.nt, sl.data(), rhs.data(), m, D.tmp.as<z>());
+      unpack_amps(ctx, D.o, D.v, D.tmp.as<z>(), out);
       return;
     }
     D.order.pop_front();  // ill-conditioned: drop the oldest vector
   }
-  FC_HIP(hipMemcpyAsync(out, D.vec(D.order.back()), sizeof(z) * D.nt, hipMemcpyDeviceToDevice, ctx->stream));
+  unpack_amps(ctx, D.o, D.v, D.vec(D.order.back()), out);
 }
 
 static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tout, z* ecorr, int* iters) {
@@ -110,7 +119,7 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
     fill(ctx, t.p(), nt, make_double2(0, 0));
   }
   DiisState D;
-  if (op.diis_dim > 1) D.init(ctx, op.diis_dim, nt);
+  if (op.diis_dim > 1) D.init(ctx, op.diis_dim, o, v);
   z e_old = ccsd_energy_dev(ctx, I, t.p(), t.p() + n1);
   const double nuniq = (double)n1 + (double)(o * (o - 1) / 2) * (double)(v * (v - 1) / 2);
   int status = FC_ENOCONV, it;
@@ -193,6 +202,7 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
 // ------------------------------------------------------------------------------ FNS
 static fc_ints fns_impl(fc_ctx ctx, fc_ints I, double thresh, int* v_kept, double* occ_out, void* U_out) {
   StageTimer st(ctx, "fns");
+  ensure_integrals(ctx, I);
   const long o = I->o, v = I->v, N = I->ncd;
   const z one = make_double2(1, 0), zero = make_double2(0, 0);
   ZTensor t(ctx, {o, o, v, v}), Dv(ctx, {v, v});
@@ -253,10 +263,10 @@ static fc_ints fns_impl(fc_ctx ctx, fc_ints I, double thresh, int* v_kept, doubl
   J->Lvo = ZTensor(ctx, {vp, o, N});
   zein(ctx, "ak,aiP->kiP", one, Ud, I->Lvo, zero, J->Lvo, true, false);
   ZTensor tmp(ctx, {vp, v, N});
-  zein(ctx, "ak,abP->kbP", one, Ud, I->Lvv, zero, tmp, true, false);
+  zein(ctx, "ak,abP->kbP", one, Ud, lvv(ctx, I), zero, tmp, true, false);
   J->Lvv = ZTensor(ctx, {vp, vp, N});
   zein(ctx, "kbP,bl->klP", one, tmp, Ud, zero, J->Lvv);
-  assemble_integrals(ctx, J);
+  ensure_integrals(ctx, J);
   FC_HIP(hipStreamSynchronize(ctx->stream));
   return J;
 }
@@ -434,7 +444,6 @@ int cd_integrals(fc_ctx ctx, int o, int v, int ncd, const double* eps, const voi
       Lsrc = Ld.p;
     }
     stage_cholesky(ctx, I, Lsrc, l_dtype);
-    assemble_integrals(ctx, I);
     FC_HIP(hipStreamSynchronize(ctx->stream));
     *out = guard.release();
     return FC_OK;
@@ -506,6 +515,17 @@ int fc_ladder(fc_ctx ctx, fc_ints I, const void* tau, const void* t1, void* R, i
   if (!ctx || !I || !tau || !R) return FC_EARG;
   FC_TRY(ctx, {
     ladder_dev(ctx, I, (const z*)tau, (const z*)t1, (z*)R, precision < 0 ? I->precision : precision);
+    return FC_OK;
+  })
+}
+
+int fc_ladder_packed(fc_ctx ctx, fc_ints I, const void* taup, const void* t1, void* Rp, int precision) {
+  if (!ctx || !I || !taup || !Rp) return FC_EARG;
+  FC_TRY(ctx, {
+    const int prec = precision < 0 ? I->precision : precision;
+    FC_REQUIRE(prec >= FC_FP64 && prec <= FC_SPLIT_FP16, FC_EARG, "fc_ladder_packed: bad precision");
+    ladder_packed_dev(ctx, I, (const z*)taup, (const z*)t1, (z*)Rp, prec);
+    FC_HIP(hipStreamSynchronize(ctx->stream));
     return FC_OK;
   })
 }

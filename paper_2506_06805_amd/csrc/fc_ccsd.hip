@@ -88,6 +88,7 @@ __global__ void k_antisym_oooo(z* W, const z* X, long o) {
 }  // namespace
 
 z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
+  ensure_integrals(ctx, I);
   const long o = I->o, v = I->v;
   ZTensor tau(ctx, {o, o, v, v});
   hipLaunchKernelGGL(k_tau, dim3(nblk(tau.size())), dim3(TPB), 0, ctx->stream, t1, t2, tau.p(), (z*)nullptr, o, v);
@@ -97,6 +98,8 @@ z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2) {
 
 void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p, z* r2p, int precision, z* fdiag) {
   StageTimer st(ctx, "residual");
+  ensure_integrals(ctx, I);
+  const ZTensor& Lvv = lvv(ctx, I);
   // mixed precision: every product outside the ladder's split kernels in FP32 arithmetic
   Fp32Gemms fp32(ctx, precision != FC_FP64);
   const long o = I->o, v = I->v, N = I->ncd;
@@ -114,7 +117,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   ZTensor xP(ctx, {N});                 // x_P = sum_mf t_m^f L^P_mf
   zein(ctx, "mf,mfP->P", one, T1, I->Lov, zero, xP);
   ZTensor Y(ctx, {v, o, N});            // Y[a,m,P] = sum_f L^P_af t_m^f
-  zgemm(ctx, 'N', 'N', o, N, v, one, t1p, v, I->Lvv.p(), N, zero, Y.p(), N, (int)v, 0, v * N, o * N);
+  zgemm(ctx, 'N', 'N', o, N, v, one, t1p, v, Lvv.p(), N, zero, Y.p(), N, (int)v, 0, v * N, o * N);
   ZTensor Cm(ctx, {o, o, N});           // C[m,j,P] = sum_f L^P_mf t_j^f
   zgemm(ctx, 'N', 'N', o, N, v, one, t1p, v, I->Lov.p(), N, zero, Cm.p(), N, (int)o, 0, v * N, o * N);
 
@@ -122,7 +125,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   ZTensor Fme(ctx, {o, v}), Fae(ctx, {v, v}), Fmi(ctx, {o, o});
   zein(ctx, "nf,mnef->me", one, T1, I->oovv, zero, Fme);
   // F_ae = sum_mf t_m^f <ma||fe> - 1/2 sum tau~_mn^af <mn||ef>,  <ma||fe> = (mf|ae) - (me|af)
-  zein(ctx, "P,aeP->ae", one, xP, I->Lvv, zero, Fae);
+  zein(ctx, "P,aeP->ae", one, xP, Lvv, zero, Fae);
   zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, Fae);
   zein(ctx, "mnaf,mnef->ae", mhalf, taut, I->oovv, one, Fae);
   // F_mi = sum_ne t_n^e <mn||ie> + 1/2 sum tau~_in^ef <mn||ef>
@@ -141,7 +144,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   ZTensor Wmbej(ctx, {o, v, v, o});
   FC_HIP(hipMemcpyAsync(Wmbej.p(), I->ovvo.p(), sizeof(z) * Wmbej.size(), hipMemcpyDeviceToDevice, ctx->stream));
   zein(ctx, "meP,bjP->mbej", one, I->Lov, Y, one, Wmbej);
-  zein(ctx, "mjP,beP->mbej", mone, Cm, I->Lvv, one, Wmbej);
+  zein(ctx, "mjP,beP->mbej", mone, Cm, Lvv, one, Wmbej);
   zein(ctx, "nb,mnej->mbej", mone, T1, I->oovo, one, Wmbej);
   {
     ZTensor Z(ctx, {o, o, v, v});
@@ -157,7 +160,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   {  // -1/2 sum_mef t_im^ef <ma||ef> = - sum_fP Q[i,f,P] L^P_af,  Q[i,f,P] = sum_me t_im^ef L^P_me
     ZTensor Q(ctx, {o, v, N});
     zein(ctx, "imef,meP->ifP", one, T2, I->Lov, zero, Q);
-    zein(ctx, "ifP,afP->ia", mone, Q, I->Lvv, one, R1);
+    zein(ctx, "ifP,afP->ia", mone, Q, Lvv, one, R1);
   }
   zein(ctx, "mnae,nmei->ia", mhalf, T2, I->oovo, one, R1);
 

@@ -68,13 +68,14 @@ __global__ void k_diag(const z* Fmi, const z* Fae, z* d, long o, long v, long di
 static void wmbij_three_virtual(fc_ctx ctx, fc_ints I, const ZTensor& tau, z* out) {
   const long o = I->o, v = I->v, N = I->ncd;
   const z one = make_double2(1, 0), zero = make_double2(0, 0);
+  const ZTensor& Lvv = lvv(ctx, I);
   const double budget = 1024.0 * 1024 * 1024;
   long mc = std::max(1L, std::min(o, (long)(budget / (16.0 * (double)v * v * v))));
   ZTensor Im(ctx, {mc, v, v, v});
   for (long m0 = 0; m0 < o; m0 += mc) {
     long nm = std::min(mc, o - m0);
     // Im[m,e,b,f] = sum_P L^P_me L^P_bf
-    zgemm(ctx, 'N', 'T', nm * v, v * v, N, one, I->Lov.p() + m0 * v * N, N, I->Lvv.p(), N, zero, Im.p(), v * v);
+    zgemm(ctx, 'N', 'T', nm * v, v * v, N, one, I->Lov.p() + m0 * v * N, N, Lvv.p(), N, zero, Im.p(), v * v);
     ZT Iv(Im.p(), {nm, v, v, v});
     ZT Ov(out + m0 * v * o * o, {nm, v, o, o});
     zein(ctx, "mebf,ijef->mbij", one, Iv, tau, one, Ov);
@@ -83,6 +84,8 @@ static void wmbij_three_virtual(fc_ctx ctx, fc_ints I, const ZTensor& tau, z* ou
 
 void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   StageTimer st(ctx, "hbar");
+  ensure_integrals(ctx, I);
+  const ZTensor& Lvv = lvv(ctx, I);
   HbarBlocks& H = T->hb;
   const long o = I->o, v = I->v, N = I->ncd;
   const z one = make_double2(1, 0), zero = make_double2(0, 0), half = make_double2(0.5, 0),
@@ -93,7 +96,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   hipLaunchKernelGGL(k_tau_full, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, T->t1.p(), T->t2.p(), tau.p(), o, v);
   ZTensor xP(ctx, {N}), Y(ctx, {v, o, N}), Cm(ctx, {o, o, N});
   zein(ctx, "mf,mfP->P", one, T1, I->Lov, zero, xP);
-  zgemm(ctx, 'N', 'N', o, N, v, one, T->t1.p(), v, I->Lvv.p(), N, zero, Y.p(), N, (int)v, 0, v * N, o * N);
+  zgemm(ctx, 'N', 'N', o, N, v, one, T->t1.p(), v, Lvv.p(), N, zero, Y.p(), N, (int)v, 0, v * N, o * N);
   zgemm(ctx, 'N', 'N', o, N, v, one, T->t1.p(), v, I->Lov.p(), N, zero, Cm.p(), N, (int)o, 0, v * N, o * N);
 
   H.Fme = ZTensor(ctx, {o, v});
@@ -103,7 +106,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   zein(ctx, "inef,mnef->mi", half, tau, I->oovv, one, H.Fmi);
   hipLaunchKernelGGL(k_add_diag, dim3(1), dim3(TPB), 0, ctx->stream, H.Fmi.p(), I->eps_d.as<double>(), o);
   H.Fae = ZTensor(ctx, {v, v});
-  zein(ctx, "P,aeP->ae", one, xP, I->Lvv, zero, H.Fae);
+  zein(ctx, "P,aeP->ae", one, xP, Lvv, zero, H.Fae);
   zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, H.Fae);
   zein(ctx, "mnaf,mnef->ae", mhalf, tau, I->oovv, one, H.Fae);
   hipLaunchKernelGGL(k_add_diag, dim3(nblk(v)), dim3(TPB), 0, ctx->stream, H.Fae.p(), I->eps_d.as<double>() + o, v);
@@ -124,7 +127,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   H.Wmbej = ZTensor(ctx, {o, v, v, o});
   FC_HIP(hipMemcpyAsync(H.Wmbej.p(), I->ovvo.p(), sizeof(z) * H.Wmbej.size(), hipMemcpyDeviceToDevice, ctx->stream));
   zein(ctx, "meP,bjP->mbej", one, I->Lov, Y, one, H.Wmbej);
-  zein(ctx, "mjP,beP->mbej", mone, Cm, I->Lvv, one, H.Wmbej);
+  zein(ctx, "mjP,beP->mbej", mone, Cm, Lvv, one, H.Wmbej);
   zein(ctx, "nb,mnej->mbej", mone, T1, I->oovo, one, H.Wmbej);
   {
     ZTensor Z(ctx, {o, o, v, v});

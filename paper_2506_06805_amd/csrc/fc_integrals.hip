@@ -9,37 +9,68 @@ namespace fc {
 namespace {
 constexpr int TPB = 256;
 
-// in: L[P][p][q] (complex128 or complex64), out: block [p - p0][q - q0][P] as complex128.
-template <class T>
+// in: L[P][p][q] (complex128 or complex64), out: block [p - p0][q - q0][P] (complex128 or
+// complex64: O is double2 or float2)
+template <class T, class O>
 __global__ void k_stage_block(const T* __restrict__ L, long n, long ncd, long p0, long np, long q0, long nq,
-                              z* __restrict__ out) {
+                              O* __restrict__ out) {
   const long total = np * nq * ncd;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     long P = t % ncd, q = (t / ncd) % nq, p = t / (ncd * nq);
     const T v = L[(P * n + p0 + p) * n + q0 + q];
-    out[t] = make_double2((double)v.x, (double)v.y);
+    out[t].x = v.x;
+    out[t].y = v.y;
   }
+}
+__global__ void k_widen(const float2* __restrict__ in, z* __restrict__ out, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    out[t] = make_double2((double)in[t].x, (double)in[t].y);
 }
 }  // namespace
 
-// Stage the four L blocks from L[P][p][q] (device, complex128 or complex64).
+const ZTensor& lvv(fc_ctx ctx, fc_ints I) {
+  if (!I->Lvv.p()) {
+    FC_REQUIRE(I->Lvv64.p, FC_EARG, "no virtual-virtual Cholesky block staged");
+    const long v = I->v, N = I->ncd, n = v * v * N;
+    I->Lvv = ZTensor(ctx, {v, v, N});
+    hipLaunchKernelGGL(k_widen, dim3((unsigned)std::min<long>(1048576, (n + TPB * 4 - 1) / (TPB * 4))), dim3(TPB), 0,
+                       ctx->stream, I->Lvv64.as<float2>(), I->Lvv.p(), n);
+    FC_HIP(hipGetLastError());
+  }
+  return I->Lvv;
+}
+
+void ensure_integrals(fc_ctx ctx, fc_ints I) {
+  if (I->assembled) return;
+  assemble_integrals(ctx, I);
+  I->assembled = true;
+}
+
+// Stage the L blocks from L[P][p][q] (device, complex128 or complex64).  The occupied blocks are
+// complex128; L_vv keeps the input type (complex64 vectors: Lvv64, widened only on demand).
 void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype) {
   const long o = I->o, v = I->v, n = o + v, N = I->ncd;
   I->Loo = ZTensor(ctx, {o, o, N});
   I->Lov = ZTensor(ctx, {o, v, N});
   I->Lvo = ZTensor(ctx, {v, o, N});
-  I->Lvv = ZTensor(ctx, {v, v, N});
-  struct B { ZTensor* t; long p0, np, q0, nq; } blocks[4] = {
-      {&I->Loo, 0, o, 0, o}, {&I->Lov, 0, o, o, v}, {&I->Lvo, o, v, 0, o}, {&I->Lvv, o, v, o, v}};
+  const bool c64 = l_dtype == FC_C64;
+  if (c64) I->Lvv64 = DBuf(ctx, sizeof(float2) * (size_t)v * v * N);
+  else I->Lvv = ZTensor(ctx, {v, v, N});
+  struct B { void* out; bool f32; long p0, np, q0, nq; } blocks[4] = {
+      {I->Loo.p(), false, 0, o, 0, o}, {I->Lov.p(), false, 0, o, o, v}, {I->Lvo.p(), false, o, v, 0, o},
+      {c64 ? I->Lvv64.p : (void*)I->Lvv.p(), c64, o, v, o, v}};
   for (auto& b : blocks) {
     long total = b.np * b.nq * N;
     unsigned g = (unsigned)std::min<long>(1048576, (total + TPB * 4 - 1) / (TPB * 4));
-    if (l_dtype == FC_C128)
-      hipLaunchKernelGGL(k_stage_block<double2>, dim3(g), dim3(TPB), 0, ctx->stream, (const double2*)Ldev, n, N,
-                         b.p0, b.np, b.q0, b.nq, b.t->p());
+    if (!c64)
+      hipLaunchKernelGGL((k_stage_block<double2, double2>), dim3(g), dim3(TPB), 0, ctx->stream, (const double2*)Ldev,
+                         n, N, b.p0, b.np, b.q0, b.nq, (double2*)b.out);
+    else if (b.f32)
+      hipLaunchKernelGGL((k_stage_block<float2, float2>), dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev, n,
+                         N, b.p0, b.np, b.q0, b.nq, (float2*)b.out);
     else
-      hipLaunchKernelGGL(k_stage_block<float2>, dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev, n, N,
-                         b.p0, b.np, b.q0, b.nq, b.t->p());
+      hipLaunchKernelGGL((k_stage_block<float2, double2>), dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev,
+                         n, N, b.p0, b.np, b.q0, b.nq, (double2*)b.out);
     FC_HIP(hipGetLastError());
   }
 }
@@ -78,7 +109,7 @@ void assemble_integrals(fc_ctx ctx, fc_ints I) {
   permute(ctx, J, {0, 2, 3, 1}, mone, one, I->oovv.p());
   // <mb||ej> = (me|bj) - (mj|be);  J[m,e,b,j], J2[m,j,b,e]
   mulliken(ctx, prec, I->Lov, I->Lvo, J);
-  mulliken(ctx, prec, I->Loo, I->Lvv, J2);
+  mulliken(ctx, prec, I->Loo, lvv(ctx, I), J2);
   I->ovvo = ZTensor(ctx, {o, v, v, o});
   permute(ctx, J, {0, 2, 1, 3}, one, zero, I->ovvo.p());     // (m,b,e,j) <- J[m,e,b,j]
   permute(ctx, J2, {0, 2, 3, 1}, mone, one, I->ovvo.p());    // (m,b,e,j) <- J2[m,j,b,e]

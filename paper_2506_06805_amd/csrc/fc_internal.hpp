@@ -144,11 +144,13 @@ void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha
 z dotu(fc_ctx ctx, long n, const z* x, const z* y);    // sum x*y
 z dotc(fc_ctx ctx, long n, const z* x, const z* y);    // sum conj(x)*y
 // Vectors base + slot[k] * stride, k < m <= 16 (DIIS history): out[k] = dotc(x, vector k) on the
-// host (one pass over x, fixed order); out = sum_k c[k] vector k (one pass); v = tnew,
-// e = tnew - told.
+// host (one pass over x, fixed order); out = sum_k c[k] vector k (one pass).
 void multi_dotc(fc_ctx ctx, long n, const z* x, const z* base, long stride, const int* slot, int m, z* out);
 void lincomb(fc_ctx ctx, long n, const z* base, long stride, const int* slot, const z* c, int m, z* out);
-void diis_push(fc_ctx ctx, long n, const z* tnew, const z* told, z* v, z* e);
+// Packed amplitude vectors (t1, then t2 over i < j, a < b): pv = pack(tnew), pe = pack(tnew - told)
+// from full-layout t1 | t2 vectors; unpack_amps writes the full layout back (antisymmetric images).
+void diis_push_packed(fc_ctx ctx, long o, long v, const z* tnew, const z* told, z* pv, z* pe);
+void unpack_amps(fc_ctx ctx, long o, long v, const z* packed, z* t);
 
 // Scope in which zgemm runs in FP32 arithmetic (the mixed-precision residual).
 struct Fp32Gemms {

@@ -33,7 +33,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
-constexpr int TM = 128, TN = 128, TK = 32, NT = 512;   // 8 waves, 2 x 4, each 64 x 32
+constexpr int TM = 128, TK = 32;   // row padding unit of split operands (the largest tile), K slice
 constexpr int LDK = TK;   // LDS row length (16-bit elements): 64 bytes, four 16-byte chunks
 // Chunk c of LDS row r is stored at chunk c ^ swz(r).  Fragment reads (16 consecutive rows, one
 // chunk) and staging stores (4 consecutive rows, all chunks) then touch distinct banks whether
@@ -67,6 +67,85 @@ __global__ void k_split(const z* __restrict__ X, long rows, long K, long ldx, lo
     out[2 * plane + t] = ih;
     out[3 * plane + t] = il;
   }
+}
+
+// X[r * ldx + colmap[k]] (colmap[k] < 0 or k >= K: zero) -> planes [4][rows_pad][kp]: the operand
+// with its contraction index permuted (the blocked pair order of the ladder contraction)
+template <int PREC>
+__global__ void k_split_cols(const z* __restrict__ X, long rows, long K, long ldx, const int* __restrict__ colmap,
+                             long rows_pad, long kp, double scale, u16* __restrict__ out) {
+  const long total = rows_pad * kp, plane = rows_pad * kp;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const long r = t / kp, k = t % kp;
+    const int c = (r < rows && k < K) ? colmap[k] : -1;
+    const z x = c >= 0 ? X[r * ldx + c] : make_double2(0.0, 0.0);
+    const double re = x.x * scale, im = x.y * scale;
+    const u16 rh = to16<PREC>((float)re), ih = to16<PREC>((float)im);
+    out[t] = rh;
+    out[plane + t] = to16<PREC>((float)(re - from16<PREC>(rh)));
+    out[2 * plane + t] = ih;
+    out[3 * plane + t] = to16<PREC>((float)(im - from16<PREC>(ih)));
+  }
+}
+
+// T1-dressed virtual Cholesky vectors straight into split planes (the operand of the ladder
+// assembly): planes row a v + e, column P = split(s (L[a][e][P] - sum_m t[m][a] Lov[m][e][P])).
+// One workgroup per (e, 64 columns of P): the o x 64 slice of Lov sits in LDS, thread t owns column
+// P0 + t % 64 and walks a = t / 64, t / 64 + 4, ...  Columns N <= P < kp are written as zeros.
+template <int PREC, class T>
+__global__ __launch_bounds__(256) void k_split_dressed(const T* __restrict__ L, const z* __restrict__ Lov,
+                                                       const z* __restrict__ t1, long o, long v, long N, long kp,
+                                                       long rows_pad, double scale, u16* __restrict__ out) {
+  extern __shared__ z sl[];   // [o][64]
+  const long e = blockIdx.y, P = (long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int a0 = threadIdx.x >> 6;
+  const long plane = rows_pad * kp;
+  if (t1) {
+    for (long i = threadIdx.x; i < o * 64; i += blockDim.x) {
+      const long m = i / 64, q = (long)blockIdx.x * 64 + (i % 64);
+      sl[i] = q < N ? Lov[(m * v + e) * N + q] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  }
+  if (P >= kp) return;
+  for (long a = a0; a < v; a += 4) {
+    double re = 0.0, im = 0.0;
+    if (P < N) {
+      const T x = L[(a * v + e) * N + P];
+      re = x.x;
+      im = x.y;
+      if (t1) {
+        for (long m = 0; m < o; ++m) {
+          const z t = t1[m * v + a], y = sl[m * 64 + (threadIdx.x & 63)];
+          re -= t.x * y.x - t.y * y.y;
+          im -= t.x * y.y + t.y * y.x;
+        }
+      }
+    }
+    re *= scale;
+    im *= scale;
+    const long off = (a * v + e) * kp + P;
+    const u16 rh = to16<PREC>((float)re), ih = to16<PREC>((float)im);
+    out[off] = rh;
+    out[plane + off] = to16<PREC>((float)(re - from16<PREC>(rh)));
+    out[2 * plane + off] = ih;
+    out[3 * plane + off] = to16<PREC>((float)(im - from16<PREC>(ih)));
+  }
+}
+
+template <class T>
+__global__ void k_maxabs_t(const T* __restrict__ X, long n, unsigned* out) {
+  __shared__ float s[256];
+  float m = 0.f;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+    m = fmaxf(m, fmaxf((float)fabs((double)X[t].x), (float)fabs((double)X[t].y)));
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(s[0]));   // non-negative floats order as uints
 }
 
 // planes[p][r][k] = 0 for k0 <= k < kp, every row r < rows_pad of the four planes
@@ -121,15 +200,43 @@ __device__ inline f4 mma(const u16* a, const u16* b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(x, y, c, 0, 0, 0);
   }
 }
+template <int PREC>
+__device__ inline f4 mma_r(const uint4& a, const uint4& b, f4 c) {
+  if constexpr (PREC == FC_SPLIT_BF16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+}
 
-template <int PREC, int EPI>
-__global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
-  // double-buffered: 2 x 64 KB
-  __shared__ __attribute__((aligned(16))) u16 sA[2][4][TM][LDK];
-  __shared__ __attribute__((aligned(16))) u16 sB[2][4][TN][LDK];
+// Output tile of one workgroup: WM x WN waves, each owning WTM x WTN outputs (BI x BJ blocks of
+// 16 x 16).  Staging: the NT threads cover RP = NT / 4 rows of one plane per pass (four 16-byte
+// chunks per 64-byte row), so an operand of TM rows takes PA = TM / RP passes per plane.
+template <int WM_, int WN_, int WTM_, int WTN_>
+struct STile {
+  static constexpr int WM = WM_, WN = WN_, WTM = WTM_, WTN = WTN_;
+  static constexpr int NT = 64 * WM * WN, TM = WM * WTM, TN = WN * WTN;
+  static constexpr int BI = WTM / 16, BJ = WTN / 16, RP = NT / 4;
+  static constexpr int PA = (TM + RP - 1) / RP, PB = (TN + RP - 1) / RP;
+  static_assert(RP % 16 == 0, "staging passes must keep the row swizzle");
+};
+// 8 waves of 64 x 32 at two waves per SIMD (256 registers each)
+using TileW8 = STile<2, 4, 64, 32>;
+// 4 waves of 64 x 64 at one wave per SIMD: the accumulators go to the AGPRs, and each wave reads
+// a third fewer LDS bytes per MFMA than a 64 x 32 wave
+using TileW4 = STile<2, 2, 64, 64>;
+// 4 waves of 64 x 48: 96-column outputs (pair counts near 3 x 96, such as 276)
+using TileW4n96 = STile<2, 2, 64, 48>;
+
+template <int PREC, int EPI, class TL>
+__global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
+  constexpr int TMt = TL::TM, TNt = TL::TN, BI = TL::BI, BJ = TL::BJ, RP = TL::RP;
+  constexpr int PA = TL::PA, PB = TL::PB;
+  // double-buffered planes of both operands
+  __shared__ __attribute__((aligned(16))) u16 sA[2][4][TMt][LDK];
+  __shared__ __attribute__((aligned(16))) u16 sB[2][4][TNt][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 2) * 64, wn = (wave & 3) * 32;
-  const long ntn = (g.N + TN - 1) / TN;
+  const int wm = (wave / TL::WN) * TL::WTM, wn = (wave % TL::WN) * TL::WTN;
+  const long ntn = (g.N + TNt - 1) / TNt;
   // XCD x (= blockIdx.x % 8) walks the contiguous tiles [x * per, (x + 1) * per); the split index
   // rotates the slot so that the splits of one tile spread over all XCDs
   const long per = (g.tiles + 7) / 8;
@@ -142,9 +249,9 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
     const long tm = g.tiles / ntn;
     mi = (mi & 1) ? tm - 1 - (mi >> 1) : (mi >> 1);
   }
-  const long m0 = mi * TM, n0 = (tile % ntn) * TN;
+  const long m0 = mi * TMt, n0 = (tile % ntn) * TNt;
   if (EPI == 1 && g.ltri) {
-    const long amin = m0 / g.lv, bmax = (n0 + TN - 1 < g.N ? n0 + TN - 1 : g.N - 1) / g.lv;
+    const long amin = m0 / g.lv, bmax = (n0 + TNt - 1 < g.N ? n0 + TNt - 1 : g.N - 1) / g.lv;
     if (amin > bmax) return;
   }
   const long klo = (long)blockIdx.y * g.kchunk;
@@ -152,75 +259,121 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   const u16* A = g.A + (g.a_row0 + m0) * g.kp;
   const u16* B = g.B + (g.b_row0 + n0) * g.kp;
 
-  // staging: 2048 16-byte chunks per operand per k-step, 4 per thread; chunk c = tid + NT q is
-  // plane c / 512, row (c % 512) / 4, k offset 8 (c % 4)
-  uint4 ra0, ra1, ra2, ra3, rb0, rb1, rb2, rb3;
-  const int srow = (tid & 511) >> 2, skc = 8 * (tid & 3);
-  const long goffA = (long)srow * g.kp + skc, goffB = goffA;
+  // staging: thread t holds, for each plane and pass, the 16-byte chunk of row (t / 4) + RP pass
+  // at k offset 8 (t % 4); rows past the tile (TM or TN not a multiple of RP) are not loaded
+  const int srow = tid >> 2, skc = 8 * (tid & 3);
+  const long goff = (long)srow * g.kp + skc;
   const int sk = 8 * ((skc >> 3) ^ swz(srow));   // LDS column of this thread's staging chunk
-#define FC_GLOAD(k0)                                                                                 \
-  do {                                                                                               \
-    ra0 = *reinterpret_cast<const uint4*>(A + 0 * g.a_plane + goffA + (k0));                         \
-    ra1 = *reinterpret_cast<const uint4*>(A + 1 * g.a_plane + goffA + (k0));                         \
-    ra2 = *reinterpret_cast<const uint4*>(A + 2 * g.a_plane + goffA + (k0));                         \
-    ra3 = *reinterpret_cast<const uint4*>(A + 3 * g.a_plane + goffA + (k0));                         \
-    rb0 = *reinterpret_cast<const uint4*>(B + 0 * g.b_plane + goffB + (k0));                         \
-    rb1 = *reinterpret_cast<const uint4*>(B + 1 * g.b_plane + goffB + (k0));                         \
-    rb2 = *reinterpret_cast<const uint4*>(B + 2 * g.b_plane + goffB + (k0));                         \
-    rb3 = *reinterpret_cast<const uint4*>(B + 3 * g.b_plane + goffB + (k0));                         \
+  // named staging registers (arrays here end up in scratch or LDS): pass 0 and, for tiles wider
+  // than one pass (PA or PB = 2), pass 1 of each plane
+  static_assert(PA <= 2 && PB <= 2, "at most two staging passes per operand");
+  uint4 a00, a10, a20, a30, a01, a11, a21, a31, b00, b10, b20, b30, b01, b11, b21, b31;
+  const bool a1ok = PA > 1 && (TMt % RP == 0 || srow + RP < TMt);
+  const bool b1ok = PB > 1 && (TNt % RP == 0 || srow + RP < TNt);
+  const long gq = (long)RP * g.kp;   // global offset of the second pass
+#define FC_LD(dst, base, plane_stride, p, q, k0) \
+  dst = *reinterpret_cast<const uint4*>((base) + (p) * (plane_stride) + goff + (q) * gq + (k0))
+#define FC_SGLOAD(k0)                                                                      \
+  do {                                                                                     \
+    FC_LD(a00, A, g.a_plane, 0, 0, k0); FC_LD(a10, A, g.a_plane, 1, 0, k0);                \
+    FC_LD(a20, A, g.a_plane, 2, 0, k0); FC_LD(a30, A, g.a_plane, 3, 0, k0);                \
+    FC_LD(b00, B, g.b_plane, 0, 0, k0); FC_LD(b10, B, g.b_plane, 1, 0, k0);                \
+    FC_LD(b20, B, g.b_plane, 2, 0, k0); FC_LD(b30, B, g.b_plane, 3, 0, k0);                \
+    if (a1ok) {                                                                            \
+      FC_LD(a01, A, g.a_plane, 0, 1, k0); FC_LD(a11, A, g.a_plane, 1, 1, k0);              \
+      FC_LD(a21, A, g.a_plane, 2, 1, k0); FC_LD(a31, A, g.a_plane, 3, 1, k0);              \
+    }                                                                                      \
+    if (b1ok) {                                                                            \
+      FC_LD(b01, B, g.b_plane, 0, 1, k0); FC_LD(b11, B, g.b_plane, 1, 1, k0);              \
+      FC_LD(b21, B, g.b_plane, 2, 1, k0); FC_LD(b31, B, g.b_plane, 3, 1, k0);              \
+    }                                                                                      \
   } while (0)
-#define FC_SSTORE(buf)                                                                               \
-  do {                                                                                               \
-    *reinterpret_cast<uint4*>(&sA[buf][0][srow][sk]) = ra0;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][1][srow][sk]) = ra1;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][2][srow][sk]) = ra2;                                         \
-    *reinterpret_cast<uint4*>(&sA[buf][3][srow][sk]) = ra3;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][0][srow][sk]) = rb0;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][1][srow][sk]) = rb1;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][2][srow][sk]) = rb2;                                         \
-    *reinterpret_cast<uint4*>(&sB[buf][3][srow][sk]) = rb3;                                         \
+#define FC_ST(arr, buf, p, row, val) *reinterpret_cast<uint4*>(&arr[buf][p][row][sk]) = val
+#define FC_SSTORE(buf)                                                                     \
+  do {                                                                                     \
+    FC_ST(sA, buf, 0, srow, a00); FC_ST(sA, buf, 1, srow, a10);                            \
+    FC_ST(sA, buf, 2, srow, a20); FC_ST(sA, buf, 3, srow, a30);                            \
+    FC_ST(sB, buf, 0, srow, b00); FC_ST(sB, buf, 1, srow, b10);                            \
+    FC_ST(sB, buf, 2, srow, b20); FC_ST(sB, buf, 3, srow, b30);                            \
+    if (a1ok) {                                                                            \
+      FC_ST(sA, buf, 0, srow + RP, a01); FC_ST(sA, buf, 1, srow + RP, a11);                \
+      FC_ST(sA, buf, 2, srow + RP, a21); FC_ST(sA, buf, 3, srow + RP, a31);                \
+    }                                                                                      \
+    if (b1ok) {                                                                            \
+      FC_ST(sB, buf, 0, srow + RP, b01); FC_ST(sB, buf, 1, srow + RP, b11);                \
+      FC_ST(sB, buf, 2, srow + RP, b21); FC_ST(sB, buf, 3, srow + RP, b31);                \
+    }                                                                                      \
   } while (0)
 
-  f4 rr[4][2], ii[4][2], im[4][2];
+  f4 rr[BI][BJ], ii[BI][BJ], im[BI][BJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) { rr[i][j] = f4{0, 0, 0, 0}; ii[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0}; }
+    for (int j = 0; j < BJ; ++j) { rr[i][j] = f4{0, 0, 0, 0}; ii[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0}; }
 
   const int lr = lane & 15, lk = 8 * ((lane >> 4) ^ swz(lr));
   // one barrier per K step: the loads of the next slice are issued before the products of this
   // one and stored to the other buffer after them
   if (klo < khi) {
-    FC_GLOAD(klo);
+    FC_SGLOAD(klo);
     FC_SSTORE(0);
   }
   __syncthreads();
   int buf = 0;
   for (long k0 = klo; k0 < khi; k0 += TK, buf ^= 1) {
     const bool more = k0 + TK < khi;
-    if (more) FC_GLOAD(k0 + TK);
+    if (more) FC_SGLOAD(k0 + TK);
+    if constexpr (TL::NT == 512) {
+      // two waves per SIMD: fragments read per block pair, the other wave covers the latency
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ra_ = wm + 16 * i + lr;
-      const u16 *aRh = &sA[buf][0][ra_][lk], *aRl = &sA[buf][1][ra_][lk], *aIh = &sA[buf][2][ra_][lk],
-                *aIl = &sA[buf][3][ra_][lk];
+      for (int i = 0; i < BI; ++i) {
+        const int ra_ = wm + 16 * i + lr;
+        const u16 *aRh = &sA[buf][0][ra_][lk], *aRl = &sA[buf][1][ra_][lk], *aIh = &sA[buf][2][ra_][lk],
+                  *aIl = &sA[buf][3][ra_][lk];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int rb_ = wn + 16 * j + lr;
-        const u16 *bRh = &sB[buf][0][rb_][lk], *bRl = &sB[buf][1][rb_][lk], *bIh = &sB[buf][2][rb_][lk],
-                  *bIl = &sB[buf][3][rb_][lk];
-        rr[i][j] = mma<PREC>(aRh, bRh, rr[i][j]);
-        rr[i][j] = mma<PREC>(aRh, bRl, rr[i][j]);
-        rr[i][j] = mma<PREC>(aRl, bRh, rr[i][j]);
-        ii[i][j] = mma<PREC>(aIh, bIh, ii[i][j]);
-        ii[i][j] = mma<PREC>(aIh, bIl, ii[i][j]);
-        ii[i][j] = mma<PREC>(aIl, bIh, ii[i][j]);
-        im[i][j] = mma<PREC>(aRh, bIh, im[i][j]);
-        im[i][j] = mma<PREC>(aRh, bIl, im[i][j]);
-        im[i][j] = mma<PREC>(aRl, bIh, im[i][j]);
-        im[i][j] = mma<PREC>(aIh, bRh, im[i][j]);
-        im[i][j] = mma<PREC>(aIh, bRl, im[i][j]);
-        im[i][j] = mma<PREC>(aIl, bRh, im[i][j]);
+        for (int j = 0; j < BJ; ++j) {
+          const int rb_ = wn + 16 * j + lr;
+          const u16 *bRh = &sB[buf][0][rb_][lk], *bRl = &sB[buf][1][rb_][lk], *bIh = &sB[buf][2][rb_][lk],
+                    *bIl = &sB[buf][3][rb_][lk];
+          rr[i][j] = mma<PREC>(aRh, bRh, rr[i][j]);
+          rr[i][j] = mma<PREC>(aRh, bRl, rr[i][j]);
+          rr[i][j] = mma<PREC>(aRl, bRh, rr[i][j]);
+          ii[i][j] = mma<PREC>(aIh, bIh, ii[i][j]);
+          ii[i][j] = mma<PREC>(aIh, bIl, ii[i][j]);
+          ii[i][j] = mma<PREC>(aIl, bIh, ii[i][j]);
+          im[i][j] = mma<PREC>(aRh, bIh, im[i][j]);
+          im[i][j] = mma<PREC>(aRh, bIl, im[i][j]);
+          im[i][j] = mma<PREC>(aRl, bIh, im[i][j]);
+          im[i][j] = mma<PREC>(aIh, bRh, im[i][j]);
+          im[i][j] = mma<PREC>(aIh, bRl, im[i][j]);
+          im[i][j] = mma<PREC>(aIl, bRh, im[i][j]);
+        }
+      }
+    } else {
+      // one wave per SIMD: every fragment of the slice in registers first (hi planes, then lo), then
+      // the products term by term so consecutive MFMAs feed different accumulators
+      uint4 fa[4][BI], fb[4][BJ];
+#pragma unroll
+      for (int pp = 0; pp < 4; ++pp) {
+        const int p = ((pp & 1) << 1) | (pp >> 1);   // 0, 2, 1, 3: the hi planes first
+#pragma unroll
+        for (int i = 0; i < BI; ++i) fa[p][i] = *reinterpret_cast<const uint4*>(&sA[buf][p][wm + 16 * i + lr][lk]);
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) fb[p][j] = *reinterpret_cast<const uint4*>(&sB[buf][p][wn + 16 * j + lr][lk]);
+      }
+      // planes: 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; terms hi*hi, hi*lo, lo*hi
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int pa = t == 2 ? 1 : 0, pb = t == 1 ? 1 : 0;   // plane offsets of the lo factor
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j) {
+            rr[i][j] = mma_r<PREC>(fa[0 + pa][i], fb[0 + pb][j], rr[i][j]);
+            ii[i][j] = mma_r<PREC>(fa[2 + pa][i], fb[2 + pb][j], ii[i][j]);
+            im[i][j] = mma_r<PREC>(fa[0 + pa][i], fb[2 + pb][j], im[i][j]);
+            im[i][j] = mma_r<PREC>(fa[2 + pa][i], fb[0 + pb][j], im[i][j]);
+          }
       }
     }
     if (more) FC_SSTORE(buf ^ 1);
@@ -231,17 +384,18 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
   const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
   // ladder layout ((a nB + b) v + e) v + f as a row part plus a column part, one 32-bit division
   // per row or column of the lane
-  long coff[2] = {0, 0};
-  if (EPI == 1) {
-    const unsigned lv = (unsigned)g.lv;
+  long coff[BJ];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < BJ; ++j) {
+    coff[j] = 0;
+    if (EPI == 1) {
+      const unsigned lv = (unsigned)g.lv;
       const unsigned n = (unsigned)(n0 + wn + 16 * j + ocol), b = n / lv;
       coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
     }
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const long m = m0 + wm + 16 * i + orow + r;
@@ -251,7 +405,7 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
         roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < BJ; ++j) {
         const long n = n0 + wn + 16 * j + ocol;
         if (m >= g.M || n >= g.N) continue;
         double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * g.inv_scale, imv = (double)im[i][j][r] * g.inv_scale;
@@ -273,6 +427,10 @@ __global__ __launch_bounds__(NT) void k_gemm_split(SArgs g) {
       }
     }
 }
+#undef FC_SGLOAD
+#undef FC_SSTORE
+#undef FC_LD
+#undef FC_ST
 
 __global__ void k_split_reduce(const z* __restrict__ P, int ns, long M, long N, z* __restrict__ C, long ldc, z alpha,
                                z beta) {
@@ -291,7 +449,34 @@ __global__ void k_split_reduce(const z* __restrict__ P, int ns, long M, long N, 
     C[m * ldc + n] = out;
   }
 }
+template <int EPI, class TL>
+void launch_split_t(int prec, dim3 grid, const SArgs& g, hipStream_t st) {
+  if (prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+  else k_gemm_split<FC_SPLIT_FP16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+  FC_HIP(hipGetLastError());
+}
 }  // namespace
+
+// Tile of a split product: 0 = 8 waves of 64 x 32 (128 x 128), 1 = 4 waves of 64 x 64 (128 x 128),
+// 2 = 4 waves of 64 x 48 (128 x 96, for output widths that 96 pads much less than 128).  n = 0: the
+// ladder assembly (any width).
+// FNSCC_SPLIT_TILE=0/1 selects the 128 x 128 tile (a measurement switch).
+int split_tile_cfg(long n) {
+  static const int base = [] {
+    const char* e = getenv("FNSCC_SPLIT_TILE");
+    return e ? (atoi(e) == 1 ? 1 : 0) : 0;
+  }();
+  // 96-wide tiles when they pad at least 15% less than 128-wide ones (N = 276: 288 against 384)
+  if (base == 1 && n > 96 && 100 * ((n + 95) / 96 * 96) < 85 * ((n + 127) / 128 * 128)) return 2;
+  return base;
+}
+long tile_tn(int cfg) { return cfg == 2 ? 96 : 128; }
+template <int EPI>
+void launch_split(int cfg, int prec, dim3 grid, const SArgs& g, hipStream_t st) {
+  if (cfg == 1) launch_split_t<EPI, TileW4>(prec, grid, g, st);
+  else if (cfg == 2) launch_split_t<EPI, TileW4n96>(prec, grid, g, st);
+  else launch_split_t<EPI, TileW8>(prec, grid, g, st);
+}
 
 SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, bool conj) {
   FC_REQUIRE(prec == FC_SPLIT_BF16 || prec == FC_SPLIT_FP16, FC_EARG, "split_operand: bad precision");
@@ -327,6 +512,100 @@ SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long 
   return s;
 }
 
+template <class T>
+static float device_maxabs(fc_ctx ctx, const T* X, long n) {
+  if (n <= 0) return 0.f;
+  DBuf mx(ctx, sizeof(unsigned));
+  FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned), ctx->stream));
+  const unsigned nb = (unsigned)std::max(1L, std::min(2048L, (n + 255) / 256));
+  k_maxabs_t<T><<<nb, 256, 0, ctx->stream>>>(X, n, mx.as<unsigned>());
+  FC_HIP(hipGetLastError());
+  unsigned h = 0;
+  FC_HIP(hipMemcpyAsync(&h, mx.p, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  float m;
+  std::memcpy(&m, &h, sizeof(m));
+  return m;
+}
+
+SplitOp split_operand_cols(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, const int* colmap) {
+  FC_REQUIRE(prec == FC_SPLIT_BF16 || prec == FC_SPLIT_FP16, FC_EARG, "split_operand_cols: bad precision");
+  SplitOp s;
+  s.prec = prec;
+  s.rows = rows;
+  s.rows_pad = (rows + TM - 1) / TM * TM + TM;
+  s.kp = std::max<long>(TK, (K + TK - 1) / TK * TK);
+  s.scale = 1.0;
+  if (prec == FC_SPLIT_FP16) {
+    // the permutation leaves the largest entry unchanged
+    const float m = rows > 0 && K > 0 ? device_maxabs(ctx, X, rows * ldx) : 0.f;
+    if (m > 0) s.scale = std::ldexp(1.0, 13 - std::ilogb((double)m));
+  }
+  s.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)s.rows_pad * s.kp);
+  const long total = s.rows_pad * s.kp;
+  const unsigned nb = (unsigned)std::max(1L, std::min(1048576L, (total + 1023) / 1024));
+  if (prec == FC_SPLIT_BF16)
+    k_split_cols<FC_SPLIT_BF16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, colmap, s.rows_pad, s.kp, s.scale, s.buf.as<u16>());
+  else
+    k_split_cols<FC_SPLIT_FP16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, colmap, s.rows_pad, s.kp, s.scale, s.buf.as<u16>());
+  FC_HIP(hipGetLastError());
+  return s;
+}
+
+SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const z* Lov, const z* t1, long o, long v,
+                          long N) {
+  FC_REQUIRE(prec == FC_SPLIT_BF16 || prec == FC_SPLIT_FP16, FC_EARG, "split_lvv_dressed: bad precision");
+  FC_REQUIRE(!t1 || o <= 64, FC_EUNSUPPORTED, "split_lvv_dressed: dressing needs o <= 64 (LDS slice of L_ov)");
+  SplitOp s;
+  s.prec = prec;
+  s.rows = v * v;
+  s.rows_pad = (s.rows + TM - 1) / TM * TM + TM;
+  s.kp = std::max<long>(TK, (N + TK - 1) / TK * TK);
+  s.scale = 1.0;
+  if (prec == FC_SPLIT_FP16) {
+    // |L_ae - sum_m t_m^a L_me| <= max|L_vv| + max_a sum_m |t_m^a| max|L_ov|
+    double bound = l_c64 ? device_maxabs(ctx, (const float2*)L, v * v * N) : device_maxabs(ctx, (const z*)L, v * v * N);
+    if (t1) {
+      std::vector<z> th((size_t)o * v);
+      FC_HIP(hipMemcpyAsync(th.data(), t1, sizeof(z) * o * v, hipMemcpyDeviceToHost, ctx->stream));
+      FC_HIP(hipStreamSynchronize(ctx->stream));
+      double tmax = 0;
+      for (long a = 0; a < v; ++a) {
+        double sa = 0;
+        for (long m = 0; m < o; ++m) sa += std::hypot(th[m * v + a].x, th[m * v + a].y);
+        tmax = std::max(tmax, sa);
+      }
+      bound += tmax * (double)device_maxabs(ctx, Lov, o * v * N) * std::sqrt(2.0);
+    }
+    if (bound > 0) s.scale = std::ldexp(1.0, 13 - std::ilogb(bound));
+  }
+  s.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)s.rows_pad * s.kp);
+  // rows past v^2 are padding: zero them (the columns past N are zeroed by the kernel)
+  const size_t plane = (size_t)s.rows_pad * s.kp;
+  for (int p = 0; p < 4; ++p)
+    FC_HIP(hipMemsetAsync(s.buf.as<u16>() + p * plane + (size_t)s.rows * s.kp, 0,
+                          sizeof(u16) * (size_t)(s.rows_pad - s.rows) * s.kp, ctx->stream));
+  const dim3 grid((unsigned)((s.kp + 63) / 64), (unsigned)v);
+  const size_t shm = t1 ? sizeof(z) * 64 * (size_t)o : 0;
+  if (prec == FC_SPLIT_BF16) {
+    if (l_c64)
+      k_split_dressed<FC_SPLIT_BF16, float2><<<grid, 256, shm, ctx->stream>>>((const float2*)L, Lov, t1, o, v, N, s.kp,
+                                                                              s.rows_pad, s.scale, s.buf.as<u16>());
+    else
+      k_split_dressed<FC_SPLIT_BF16, double2><<<grid, 256, shm, ctx->stream>>>((const double2*)L, Lov, t1, o, v, N, s.kp,
+                                                                               s.rows_pad, s.scale, s.buf.as<u16>());
+  } else {
+    if (l_c64)
+      k_split_dressed<FC_SPLIT_FP16, float2><<<grid, 256, shm, ctx->stream>>>((const float2*)L, Lov, t1, o, v, N, s.kp,
+                                                                              s.rows_pad, s.scale, s.buf.as<u16>());
+    else
+      k_split_dressed<FC_SPLIT_FP16, double2><<<grid, 256, shm, ctx->stream>>>((const double2*)L, Lov, t1, o, v, N, s.kp,
+                                                                               s.rows_pad, s.scale, s.buf.as<u16>());
+  }
+  FC_HIP(hipGetLastError());
+  return s;
+}
+
 void split_zero_kpad(fc_ctx ctx, SplitOp& S, long k0) {
   FC_REQUIRE(k0 >= 0 && k0 <= S.kp, FC_EARG, "split_zero_kpad: column out of range");
   const long total = 4 * S.rows_pad * (S.kp - k0);
@@ -350,7 +629,8 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = C; g.ldc = ldc; g.alpha = alpha; g.beta = beta;
   g.inv_scale = 1.0 / (A.scale * B.scale);
-  const long tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  const int tcfg = split_tile_cfg(N);
+  const long tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.tiles = tiles;
   g.W = nullptr; g.lv = 1; g.lnB = 1; g.ltri = 0;
   long ksplit = 1;
@@ -377,9 +657,7 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
     g.part = work.as<z>();
   }
   dim3 grid((unsigned)((tiles + 7) / 8 * 8), (unsigned)ksplit);
-  if (A.prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, 0><<<grid, NT, 0, ctx->stream>>>(g);
-  else k_gemm_split<FC_SPLIT_FP16, 0><<<grid, NT, 0, ctx->stream>>>(g);
-  FC_HIP(hipGetLastError());
+  launch_split<0>(tcfg, A.prec, grid, g, ctx->stream);
   if (ksplit > 1) {
     const long MN = M * N;
     unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 255) / 256));
@@ -401,14 +679,13 @@ void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const 
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = nullptr; g.ldc = 0; g.alpha = make_double2(1, 0); g.beta = make_double2(0, 0);
   g.inv_scale = 1.0 / (A.scale * B.scale);
-  g.tiles = ((M + TM - 1) / TM) * ((N + TN - 1) / TN);
+  const int tcfg = split_tile_cfg(0);
+  g.tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.kchunk = A.kp;
   g.part = nullptr;
   g.W = W; g.lv = lep.v; g.lnB = lep.nB; g.ltri = lep.triangular;
   dim3 grid((unsigned)((g.tiles + 7) / 8 * 8), 1);
-  if (A.prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, 1><<<grid, NT, 0, ctx->stream>>>(g);
-  else k_gemm_split<FC_SPLIT_FP16, 1><<<grid, NT, 0, ctx->stream>>>(g);
-  FC_HIP(hipGetLastError());
+  launch_split<1>(tcfg, A.prec, grid, g, ctx->stream);
 }
 
 // Generic entry: only the layout with both operands contraction-contiguous (opA 'N'/'R', opB 'T'/'C').

@@ -14,6 +14,13 @@ struct SplitOp {
 
 // Split X[r * ldx + k] (r < rows, k < K), conjugated when conj.
 SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, bool conj = false);
+// Split X[r * ldx + colmap[k]] (colmap: device, K entries; negative entries give zero columns).
+SplitOp split_operand_cols(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, const int* colmap);
+// The ladder's assembly operand: rows a v + e, columns P of s (L_ae^P - sum_m t_m^a L_me^P), from L_vv
+// [a][e][P] in complex64 (l_c64) or complex128 and L_ov [m][e][P]; t1 (o x v) may be NULL (no
+// dressing; with dressing o <= 64).  FP16 takes one power-of-two scale from a bound on the dressed entries.
+SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const z* Lov, const z* t1, long o, long v,
+                          long N);
 // Zero the contraction columns [k0, kp) of every (padded) row of the four planes.
 void split_zero_kpad(fc_ctx ctx, SplitOp& S, long k0);
 // C[m][n] = alpha sum_k A[a_row0 + m][k] B[b_row0 + n][k] + beta C[m][n]

@@ -10,6 +10,11 @@ struct fc_ints_s {
   std::vector<double> eps;        // host copy, n entries
   fc::DBuf eps_d;                 // device copy
   fc::ZTensor Loo, Lov, Lvo, Lvv; // L^P_ij, L^P_ia, L^P_ai, L^P_ab as [p][q][P]
+  // complex64 vectors keep L^P_ab in complex64 ([a][b][P], float2); the complex128 copy in Lvv is
+  // made on first use by a complex128 product (fc::lvv), so a ladder-only handle never holds it
+  fc::DBuf Lvv64;
+  // the stored integrals below are assembled on first use (fc::ensure_integrals)
+  bool assembled = false;
   // stored antisymmetrised integrals with <= 2 virtual indices (Sec. 3)
   fc::ZTensor oooo, ooov, oovv, ovvo;  // <mn||ij>, <mn||ie>, <mn||ef>, <mb||ej>
   // the same integrals re-indexed (symmetry copies kept for contiguous GEMM operands)
@@ -57,6 +62,12 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, z* r1, z
 void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision);
 z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2);
 void assemble_integrals(fc_ctx ctx, fc_ints I);
+// fc_integrals.hip: the stored integrals, assembled once on first use
+void ensure_integrals(fc_ctx ctx, fc_ints I);
+// L^P_ab in complex128 ([a][b][P]), widened once from the complex64 copy when that is all there is
+const ZTensor& lvv(fc_ctx ctx, fc_ints I);
+// the ladder with packed amplitudes: taup [i<j][e<f] and Rp [i<j][a<b] (complex128)
+void ladder_packed_dev(fc_ctx ctx, fc_ints I, const z* taup, const z* t1dress, z* Rp, int precision);
 // fc_mlp.hip
 int learned_step(fc_ctx ctx, fc_ints I, const void* mlp, const z* t1, const z* t2, const z* r1, const z* r2,
                  const z* r2prev, const z* fdiag, z* o1, z* o2);

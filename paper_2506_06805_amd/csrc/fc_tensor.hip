@@ -307,15 +307,52 @@ __global__ void k_lincomb(long n, const z* __restrict__ base, long stride, Multi
   }
 }
 // v = tnew, e = tnew - told
-__global__ void k_diis_push(long n, const z* __restrict__ tnew, const z* __restrict__ told, z* __restrict__ v,
-                            z* __restrict__ e) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const z a = tnew[i], b = told[i];
-    v[i] = a;
-    e[i] = make_double2(a.x - b.x, a.y - b.y);
+// Amplitude vectors over the unique entries: t1 (o v), then t2_ij^ab for i < j, a < b in
+// lexicographic pair order, b fastest: packed index o v + pij C(v, 2) + pab with
+// pij = i (2 o - i - 1) / 2 + j - i - 1 and pab likewise.  One thread per entry of the full layout.
+__device__ inline long upair(long i, long j, long n) { return i * (2 * n - i - 1) / 2 + (j - i - 1); }
+// v = pack(tnew), e = pack(tnew) - pack(told)
+__global__ void k_diis_push_packed(long o, long v, const z* __restrict__ tnew, const z* __restrict__ told,
+                                   z* __restrict__ pv, z* __restrict__ pe) {
+  const long n1 = o * v, n2 = o * o * v * v, nvp = v * (v - 1) / 2;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < n1 + n2; x += (long)gridDim.x * blockDim.x) {
+    long k;
+    if (x < n1) {
+      k = x;
+    } else {
+      const long y = x - n1, b = y % v, a = (y / v) % v, j = (y / (v * v)) % o, i = y / (v * v * o);
+      if (!(i < j && a < b)) continue;
+      k = n1 + upair(i, j, o) * nvp + upair(a, b, v);
+    }
+    const z p = tnew[x], q = told[x];
+    pv[k] = p;
+    pe[k] = make_double2(p.x - q.x, p.y - q.y);
+  }
+}
+// full t1 | t2 from the packed vector (antisymmetric images, zeros where i == j or a == b)
+__global__ void k_unpack_amps(long o, long v, const z* __restrict__ pk, z* __restrict__ t) {
+  const long n1 = o * v, n2 = o * o * v * v, nvp = v * (v - 1) / 2;
+  for (long x = blockIdx.x * (long)blockDim.x + threadIdx.x; x < n1 + n2; x += (long)gridDim.x * blockDim.x) {
+    if (x < n1) { t[x] = pk[x]; continue; }
+    const long y = x - n1, b = y % v, a = (y / v) % v, j = (y / (v * v)) % o, i = y / (v * v * o);
+    if (i == j || a == b) { t[x] = make_double2(0, 0); continue; }
+    const bool si = i > j, sa = a > b;
+    const z p = pk[n1 + upair(si ? j : i, si ? i : j, o) * nvp + upair(sa ? b : a, sa ? a : b, v)];
+    t[x] = (si != sa) ? make_double2(-p.x, -p.y) : p;
   }
 }
 }  // namespace
+
+void diis_push_packed(fc_ctx ctx, long o, long v, const z* tnew, const z* told, z* pv, z* pe) {
+  const long n = o * v + o * o * v * v;
+  hipLaunchKernelGGL(k_diis_push_packed, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, o, v, tnew, told, pv, pe);
+  FC_HIP(hipGetLastError());
+}
+void unpack_amps(fc_ctx ctx, long o, long v, const z* packed, z* t) {
+  const long n = o * v + o * o * v * v;
+  hipLaunchKernelGGL(k_unpack_amps, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, o, v, packed, t);
+  FC_HIP(hipGetLastError());
+}
 
 void multi_dotc(fc_ctx ctx, long n, const z* x, const z* base, long stride, const int* slot, int m, z* out) {
   FC_REQUIRE(m >= 1 && m <= MAXV, FC_EARG, "multi_dotc: 1..16 vectors");
@@ -339,12 +376,6 @@ void lincomb(fc_ctx ctx, long n, const z* base, long stride, const int* slot, co
   hipLaunchKernelGGL(k_lincomb, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, base, stride, a, out);
   FC_HIP(hipGetLastError());
 }
-void diis_push(fc_ctx ctx, long n, const z* tnew, const z* told, z* v, z* e) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_diis_push, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, n, tnew, told, v, e);
-  FC_HIP(hipGetLastError());
-}
-
 void fill(fc_ctx ctx, z* p, long n, z value) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_fill, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, p, n, value);

@@ -62,6 +62,7 @@ _sig = {
     "ccsd_solve": (C.c_int, [P, C.c_int, C.POINTER(P), C.POINTER(CcsdOpts), C.POINTER(P), P, P]),
     "ccsd_residual": (C.c_int, [P, P, P, P, P, P, C.c_int]),
     "fc_ladder": (C.c_int, [P, P, P, P, P, C.c_int]),
+    "fc_ladder_packed": (C.c_int, [P, P, P, P, P, C.c_int]),
     "fc_zgemm": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P, C.c_long,
                            P, P, C.c_long, C.c_int]),
     "fc_zgemm_noalloc": (C.c_int, [P, C.c_char, C.c_char, C.c_long, C.c_long, C.c_long, P, P, C.c_long, P,
@@ -420,6 +421,21 @@ def ladder(ctx: Context, ints: Ints, tau, t1=None, precision=-1, out=None):
     R = out if out is not None else torch.empty_like(tau)
     ctx.check(lib.fc_ladder(ctx.h, ints.h, _ptr(tau), _ptr(t1), _ptr(R), PRECISION.get(precision, precision)),
               "fc_ladder")
+    return R
+
+
+def ladder_packed(ctx: Context, ints: Ints, taup, t1=None, precision=-1, out=None):
+    """The ladder on packed amplitudes: taup[pij][pef] (i<j, e<f) -> R[pij][pab] (i<j, a<b)."""
+    o, v = ints.o, ints.v
+    shape = (o * (o - 1) // 2, v * (v - 1) // 2)
+    _require(taup, "ladder_packed: taup", _C128, shape)
+    if t1 is not None:
+        _require(t1, "ladder_packed: t1", _C128, (o, v))
+    if out is not None:
+        _require(out, "ladder_packed: out", _C128, shape)
+    R = out if out is not None else torch.empty(shape, dtype=torch.complex128, device=taup.device)
+    ctx.check(lib.fc_ladder_packed(ctx.h, ints.h, _ptr(taup), _ptr(t1), _ptr(R), PRECISION.get(precision, precision)),
+              "fc_ladder_packed")
     return R
 
 

@@ -92,6 +92,37 @@ def make_instance(o: int, v: int, ncd: int, seed: int, kappa: float = 1.0,
     return Instance(o, v, ncd, eps, L, seed, kappa, fns_gamma)
 
 
+def make_instance_device(o: int, v: int, ncd: int, seed: int, kappa: float = 1.0, complex64: bool = True,
+                         device: str = "cuda", chunk: int = 32):
+    """The same recipe with the Cholesky vectors drawn on the device, for vector sets too large to
+    draw and copy from the host (o=40, v=1698, N=4000: 97 GB in complex64).
+
+    The energies come from numpy's PCG64 stream exactly as in make_instance; B is drawn with
+    torch's counter-based (Philox) generator on the device, seeded with `seed`, P block by P block:
+    the same distributions as make_instance, not the same numbers.  Returns (eps (n,) numpy,
+    L (ncd, n, n) torch tensor on the device)."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    eps_o = np.sort(rng.uniform(-3.0, -0.3, o))
+    eps_v = np.sort(rng.uniform(0.05, 6.0, v))
+    eps = np.concatenate([eps_o, eps_v]).astype(np.float64)
+    n = o + v
+    cdt = torch.complex64 if complex64 else torch.complex128
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    L = torch.empty((ncd, n, n), dtype=cdt, device=device)
+    for P0 in range(0, ncd, chunk):
+        P1 = min(ncd, P0 + chunk)
+        # complex normal with E|B|^2 = 1: real and imaginary parts N(0, 1/2), as (N + iN)/sqrt(2)
+        B = torch.randn((P1 - P0, n, n), dtype=cdt, device=device, generator=g)
+        s = torch.tensor([kappa * 0.3 * math.exp(-4.0 * P / max(ncd, 1)) * 0.5 for P in range(P0, P1)],
+                         dtype=B.real.dtype, device=device)
+        L[P0:P1] = (B + B.transpose(1, 2).conj()) * s[:, None, None]
+        del B
+    return eps, L
+
+
 def gauge_transform(inst: Instance, seed: int) -> Instance:
     """Random spinor phases: L^P_pq -> exp(-i phi_p) L^P_pq exp(i phi_q).
 
@@ -133,6 +164,8 @@ WORKLOADS = {
     "o24v160n500": dict(o=24, v=160, ncd=500, roots=8, seed=2000),
     "o16v120n360": dict(o=16, v=120, ncd=360, roots=8, seed=3500),
     "o40v600n1800": dict(o=40, v=600, ncd=1800, roots=8, seed=3000),
+    # the solvated heavy-anion cluster shape: complex64 vectors drawn on the device
+    "o40v1698n4000": dict(o=40, v=1698, ncd=4000, roots=10, seed=5000, device=True),
 }
 
 
