@@ -377,6 +377,8 @@ def main():
                     help="skip the FP64 + learned, split-BF16 and split-BF16 + learned runs on the same instance")
     ap.add_argument("--host-inputs", action="store_true",
                     help="pass the Cholesky vectors from host memory (PCIe-inclusive time-to-IPs; not the metric)")
+    ap.add_argument("--no-host-inputs", dest="host_compare", action="store_false",
+                    help="skip the extra steps that time the same solve from host-resident vectors")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune GEMM tiles during the warmup steps (cached for the timed steps)")
     ap.add_argument("--fns", type=float, default=None,
@@ -499,7 +501,7 @@ def main():
         "result": {"e_corr": [r["e"].real, r["e"].imag], "ccsd_iters": r["iters"], "eom_iters": r["eom_iters"],
                    "ips": [float(x) for x in np.real(r["w"])]},
     }
-    if not args.host_inputs and args.steps > 0:
+    if args.host_compare and not args.host_inputs and args.steps > 0:
         # the same step with the Cholesky vectors handed over from host memory (cd_integrals copies
         # them over PCIe inside the timed region): the PCIe-inclusive figure, never `value`
         import copy

@@ -9,19 +9,33 @@ namespace fc {
 namespace {
 constexpr int TPB = 256;
 
-// in: L[P][p][q] (complex128 or complex64), out: block [p - p0][q - q0][P] (complex128 or
-// complex64: O is double2 or float2)
+// Staging of one block: out[p - p0][q - q0][P] = L[P][p][q] (complex128 or complex64 in, O = double2
+// or float2 out), as a transpose per bra spinor p: 32 x 32 tiles
+// of (P, q) through LDS so that both the read (q fastest) and the write (P fastest) are coalesced.
+// grid: (ceil(nq / 32), ceil(ncd / 32), np), 256 threads.
 template <class T, class O>
-__global__ void k_stage_block(const T* __restrict__ L, long n, long ncd, long p0, long np, long q0, long nq,
-                              O* __restrict__ out) {
-  const long total = np * nq * ncd;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    long P = t % ncd, q = (t / ncd) % nq, p = t / (ncd * nq);
-    const T v = L[(P * n + p0 + p) * n + q0 + q];
-    out[t].x = v.x;
-    out[t].y = v.y;
+__global__ __launch_bounds__(256) void k_stage_block_t(const T* __restrict__ L, long n, long ncd, long p0, long q0,
+                                                       long nq, O* __restrict__ out) {
+  __shared__ O tile[32][33];
+  const long p = blockIdx.z, qb = (long)blockIdx.x * 32, Pb = (long)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const long P = Pb + r, q = qb + tx;
+    O val{};
+    if (P < ncd && q < nq) {
+      const T x = L[(P * n + p0 + p) * n + q0 + q];
+      val.x = x.x;
+      val.y = x.y;
+    }
+    tile[r][tx] = val;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const long q = qb + r, P = Pb + tx;
+    if (q < nq && P < ncd) out[(p * nq + q) * ncd + P] = tile[tx][r];
   }
 }
+
 __global__ void k_widen(const float2* __restrict__ in, z* __restrict__ out, long n) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
     out[t] = make_double2((double)in[t].x, (double)in[t].y);
@@ -60,17 +74,17 @@ void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype) {
       {I->Loo.p(), false, 0, o, 0, o}, {I->Lov.p(), false, 0, o, o, v}, {I->Lvo.p(), false, o, v, 0, o},
       {c64 ? I->Lvv64.p : (void*)I->Lvv.p(), c64, o, v, o, v}};
   for (auto& b : blocks) {
-    long total = b.np * b.nq * N;
-    unsigned g = (unsigned)std::min<long>(1048576, (total + TPB * 4 - 1) / (TPB * 4));
+    FC_REQUIRE(b.np <= 65535, FC_EARG, "stage_cholesky: more than 65535 spinors in a block");
+    const dim3 grid((unsigned)((b.nq + 31) / 32), (unsigned)((N + 31) / 32), (unsigned)b.np);
     if (!c64)
-      hipLaunchKernelGGL((k_stage_block<double2, double2>), dim3(g), dim3(TPB), 0, ctx->stream, (const double2*)Ldev,
-                         n, N, b.p0, b.np, b.q0, b.nq, (double2*)b.out);
+      hipLaunchKernelGGL((k_stage_block_t<double2, double2>), grid, dim3(TPB), 0, ctx->stream, (const double2*)Ldev,
+                         n, N, b.p0, b.q0, b.nq, (double2*)b.out);
     else if (b.f32)
-      hipLaunchKernelGGL((k_stage_block<float2, float2>), dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev, n,
-                         N, b.p0, b.np, b.q0, b.nq, (float2*)b.out);
+      hipLaunchKernelGGL((k_stage_block_t<float2, float2>), grid, dim3(TPB), 0, ctx->stream, (const float2*)Ldev, n,
+                         N, b.p0, b.q0, b.nq, (float2*)b.out);
     else
-      hipLaunchKernelGGL((k_stage_block<float2, double2>), dim3(g), dim3(TPB), 0, ctx->stream, (const float2*)Ldev,
-                         n, N, b.p0, b.np, b.q0, b.nq, (double2*)b.out);
+      hipLaunchKernelGGL((k_stage_block_t<float2, double2>), grid, dim3(TPB), 0, ctx->stream, (const float2*)Ldev,
+                         n, N, b.p0, b.q0, b.nq, (double2*)b.out);
     FC_HIP(hipGetLastError());
   }
 }

@@ -16,6 +16,7 @@
 // The T1 dressing Lb = L_ae - sum_m t_m^a L_me is folded into the split of L_vv in split precision
 // (complex64 or complex128 vectors, never a dressed copy); in FP64 it is a dressed complex128 copy.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -288,7 +289,16 @@ static void ladder_core(fc_ctx ctx, fc_ints I, const z* taup, const z* t1dress, 
   DBuf slots_d(ctx, sizeof(int2) * max_slots), compact_d(ctx, sizeof(int) * max_slots);
   DBuf mx(ctx, sizeof(unsigned));
   size_t next = 0;
+  // FNSCC_VERBOSE: a line per twentieth of the block pairs (long evaluations at large shapes)
+  const auto t_start = std::chrono::steady_clock::now();
+  size_t reported = 0;
   while (next < bps.size()) {
+    if (ctx->verbose && next >= reported) {
+      const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      fprintf(stderr, "[ladder] block pair %zu of %zu, %.1f s\n", next, bps.size(), s);
+      fflush(stderr);
+      reported = next + std::max<size_t>(1, bps.size() / 20);
+    }
     // gather a chunk of block pairs and run their assembly GEMMs
     std::vector<int2> hslots;
     while (next < bps.size() && (hslots.empty() || (long)hslots.size() + bps[next].nA * bps[next].nB <= cap_slots)) {
