@@ -30,9 +30,20 @@ def unpack(p, n_in=N_IN, n_h=N_H, n_out=N_OUT):
     return out
 
 
-def forward(p, X):
+def round_bf16(x):
+    """Nearest BF16 value (ties to even) of each entry, through its FP32 value."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward(p, X, h1_bf16=False):
+    """y = W3 tanh(W2 h1 + b2) + b3 with h1 = tanh(W1 x + b1); h1_bf16 stores h1 in BF16 first (the
+    precision of the solver's inference, whose hidden product runs on BF16 matrix cores)."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
     h1 = np.tanh(X @ W1.T + b1)
+    if h1_bf16:
+        h1 = round_bf16(h1)
     h2 = np.tanh(h1 @ W2.T + b2)
     return h2 @ W3.T + b3
 

@@ -35,6 +35,7 @@ namespace fc {
 namespace {
 constexpr int NIN = 4, NH = 64, NOUT = 2;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 constexpr long NP = NH * NIN + NH + NH * NH + NH + NOUT * NH + NOUT;
 constexpr int TPB = 256;
 #define GRID_STRIDE(i, n) for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < (n); i += (long)gridDim.x * blockDim.x)
@@ -210,12 +211,13 @@ __device__ inline void pair_of_index(long p, long n, long& i, long& j) {
 }
 
 // t2_new = t2 + (r2 / D)(1 + g(x)) for every unique amplitude (i < j, a < b), written to its four
-// antisymmetric images, with the BF16-rounded weights and FP32 arithmetic; the 64 x 64 hidden
-// layer runs on the FP32 matrix cores.  Each wave takes 64 unique amplitudes (one per lane),
-// forms the features and the first hidden layer per lane,
-// stages h1 as a 64 x 64 block in LDS, and multiplies it by W2^T with v_mfma_f32_16x16x4f32
-// (4 x 4 output blocks, K = 64 in 16 steps; W2 fragments stay in registers for the whole
-// kernel).  tanh and the output layer act on the accumulators in place; the two output sums of a
+// antisymmetric images, with the BF16-rounded weights; the 64 x 64 hidden layer runs on the BF16
+// matrix cores with FP32 accumulation (h1 rounded to BF16), the rest in FP32.  Each wave takes 64
+// unique amplitudes (one per lane), forms the features and the first hidden layer per lane,
+// stages h1 as a 64 x 64 block in LDS, and multiplies it by W2^T with v_mfma_f32_16x16x32_bf16
+// (4 x 4 output blocks, K = 64 in 2 steps; W2 fragments stay in registers for the whole kernel).
+// Lane layout of the 16x16x32 product: A fragment A[l % 16][8 (l / 16) + 0..7], B fragment
+// B[8 (l / 16) + 0..7][l % 16], accumulator r D[4 (l / 16) + r][l % 16].  tanh and the output layer act on the accumulators in place; the two output sums of a
 // sample are reduced over the 16 lanes that hold its columns and handed back to the sample's
 // lane through LDS.  (Evaluating the whole network per lane with weights in LDS took 3.9x as
 // long: 2.5 against 0.64 ms per step at o = 24, v = 160.)
@@ -229,12 +231,14 @@ __global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __rest
   __shared__ float Hs[LW][64 * HS];          // per wave: h1 of its 64 samples, then (y0, y1)
   for (int k = threadIdx.x; k < NH * NIN + NH; k += blockDim.x) Ps[k] = pbf[OW1 + k];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, ln = lane & 15, lk = lane >> 4;
-  // W2 fragments: B[k][n] of step kk and column block pb is W2[pb 16 + n][kk 4 + k]
-  float w2f[4][16];
+  // W2 fragments: B[k][n] of step kk and column block pb is W2[pb 16 + n][kk 32 + k], k = 8 lk + 0..7
+  bf16x8 w2f[4][2];
 #pragma unroll
   for (int pb = 0; pb < 4; ++pb)
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) w2f[pb][kk] = pbf[OW2 + (pb * 16 + ln) * NH + kk * 4 + lk];
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) w2f[pb][kk][e] = (__bf16)pbf[OW2 + (pb * 16 + ln) * NH + kk * 32 + 8 * lk + e];
   float b2c[4], w30[4], w31[4];
 #pragma unroll
   for (int pb = 0; pb < 4; ++pb) {
@@ -284,10 +288,12 @@ __global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __rest
 #pragma unroll
       for (int pb = 0; pb < 4; ++pb) acc[pb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const float av = H[(sb * 16 + ln) * HS + kk * 4 + lk];
+      for (int kk = 0; kk < 2; ++kk) {
+        bf16x8 av;
 #pragma unroll
-        for (int pb = 0; pb < 4; ++pb) acc[pb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, w2f[pb][kk], acc[pb], 0, 0, 0);
+        for (int e = 0; e < 8; ++e) av[e] = (__bf16)H[(sb * 16 + ln) * HS + kk * 32 + 8 * lk + e];
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) acc[pb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w2f[pb][kk], acc[pb], 0, 0, 0);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

@@ -15,10 +15,12 @@ import numpy as np
 from . import fnscc, synth
 
 
-def collect(ctx, instances, per_iter=2048, seed=1, max_iter=40, qmax=1.0):
+def collect(ctx, instances, per_iter=2048, seed=1, max_iter=40, qmax=1.0, log=None):
     torch = ctx.torch
     chunks = []
     for n, inst in enumerate(instances):
+        if log and n % 100 == 0:
+            log(f"collect: instance {n} of {len(instances)}")
         ints = fnscc.cd_integrals(ctx, inst.eps, inst.L, inst.o)
         _, _, amps = fnscc.ccsd_solve(ctx, ints)
         _, t2s = amps.read()
@@ -75,7 +77,9 @@ def train(ctx, data, epochs=20, batch=4096, lr=2e-3, seed=0, mlp=None, log=None)
 
 
 def training_instances(count, seed, o_range=(6, 16), v_range=(30, 80)):
-    """Small instances from the uneven-batch generator (N = 4 v), each with its coupling scale."""
+    """Small instances from the uneven-batch generator (N = 4 v), each with its coupling scale;
+    instance k is drawn with seed 100 seed + k (seed >= 1000 keeps them apart from every
+    benchmark and test instance)."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(count):

@@ -15,6 +15,10 @@ supermatrix and the two-component transform of its vectors on the device.
 
 `python -m paper_2506_06805_amd.profiling sigma` times the right and left IP-EOM sigma products for
 blocks of k trial vectors against the FP64 matrix-core peak.
+
+`python -m paper_2506_06805_amd.profiling learned-curve` trains the learned T2 update on growing
+sets of generated instances and reports what it gains over plain Jacobi + DIIS on the benchmark
+workloads.
 """
 from __future__ import annotations
 
@@ -222,6 +226,77 @@ def sigma_probe(o: int, v: int, ncd: int, ks, reps: int, seed: int) -> None:
                   flush=True)
 
 
+def learned_curve(sizes, seed: int, per_iter_max: int, epochs: int, diis: int) -> None:
+    """Iterations and time-to-IPs with the learned update against plain Jacobi + DIIS(diis), for
+    networks trained on `sizes` generated instances (learn.training_instances: o 6-16, v 30-80,
+    N = 4 v, seeds 100 seed + k), on o=24 v=160 N=500 and on the FNS-structured o=40 v=600 N=1800
+    workload at the threshold 1e-5, in FP64 and split-BF16."""
+    import sys
+    import time
+
+    import numpy as np
+    import torch
+
+    from . import fnscc, learn, synth
+
+    ctx = fnscc.Context(0)
+
+    def log(msg):
+        print(f"[learned-curve] {msg}", file=sys.stderr, flush=True)
+
+    evals = []
+    for name, wl, gamma, thr in (("o24v160n500", synth.WORKLOADS["o24v160n500"], None, None),
+                                 ("o40v600n1800 FNS 1e-5 structured", synth.WORKLOADS["o40v600n1800"], 6.0, 1e-5)):
+        o, v, N = wl["o"], wl["v"], wl["ncd"]
+        inst = synth.make_instance(o, v, N, seed=wl["seed"], kappa=synth.kappa_for(v, N), fns_gamma=gamma,
+                                   dtype=np.complex64 if gamma else np.complex128)
+        evals.append((name, inst, torch.from_numpy(inst.L).cuda(), thr, wl["roots"]))
+
+    def solve(ev, prec, mlp):
+        name, inst, L, thr, roots = ev
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ints = fnscc.cd_integrals(ctx, inst.eps, L, inst.o, precision=prec)
+        if thr is not None:
+            ints, _ = fnscc.fns_truncate(ctx, ints, thr)
+        kw = {"mlp": mlp} if mlp is not None else {}
+        e, it, amps = fnscc.ccsd_solve(ctx, ints, precision=prec, diis_dim=diis, **kw)
+        w, _ = fnscc.ipeom_davidson(ctx, ints, amps, roots)
+        torch.cuda.synchronize()
+        return it, time.perf_counter() - t0, e, np.sort_complex(np.asarray(w))
+
+    base = {}
+    for ev in evals:
+        for prec in ("fp64", "split-bf16"):
+            solve(ev, prec, None)   # warm-up
+            base[(ev[0], prec)] = solve(ev, prec, None)
+            it, t, e, _ = base[(ev[0], prec)]
+            print(json.dumps({"train_instances": 0, "workload": ev[0], "precision": prec, "diis": diis,
+                              "ccsd_iters": it, "time_to_ips_s": round(t, 4)}), flush=True)
+    for n in sizes:
+        per_iter = max(32, min(per_iter_max, per_iter_max * 64 // max(n, 1)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        data = learn.collect(ctx, learn.training_instances(n, seed), per_iter=per_iter, seed=seed, log=log)
+        t_col = time.perf_counter() - t0
+        net, hist = learn.train(ctx, data, epochs=epochs, batch=2048, lr=2e-3, seed=1)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0 - t_col
+        log(f"{n} instances: {int(data[0].shape[0])} samples, collected in {t_col:.1f} s, trained in {t_train:.1f} s")
+        for ev in evals:
+            for prec in ("fp64", "split-bf16"):
+                it, t, e, w = solve(ev, prec, net)
+                it0, t0_, e0, w0 = base[(ev[0], prec)]
+                print(json.dumps({"train_instances": n, "samples": int(data[0].shape[0]), "per_iter": per_iter,
+                                  "collect_s": round(t_col, 1), "train_s": round(t_train, 1),
+                                  "loss_first": hist[0], "loss_last": hist[-1], "workload": ev[0],
+                                  "precision": prec, "diis": diis, "ccsd_iters": it, "plain_iters": it0,
+                                  "time_to_ips_s": round(t, 4), "speedup_vs_plain": round(t0_ / t, 3),
+                                  "max_abs_dIP_vs_plain": float(np.abs(w - w0).max()),
+                                  "abs_dE_vs_plain": abs(e - e0)}), flush=True)
+        del data, net
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -252,6 +327,12 @@ def main() -> None:
     q.add_argument("--ks", type=str, default="1,8,16,32")
     q.add_argument("--reps", type=int, default=5)
     q.add_argument("--seed", type=int, default=1001)
+    lc = sub.add_parser("learned-curve")
+    lc.add_argument("--sizes", type=str, default="16,128,512,2000")
+    lc.add_argument("--seed", type=int, default=1000)
+    lc.add_argument("--per-iter", type=int, default=1024)
+    lc.add_argument("--epochs", type=int, default=12)
+    lc.add_argument("--diis", type=int, default=10)
     args = ap.parse_args()
     if args.cmd == "copy":
         copy_probe(args.mib)
@@ -263,6 +344,8 @@ def main() -> None:
         sigma_probe(args.o, args.v, args.ncd, [int(x) for x in args.ks.split(",")], args.reps, args.seed)
     elif args.cmd == "ao-cd":
         ao_cd(args.nao, args.rank, args.n, args.tau, args.reps, args.seed)
+    elif args.cmd == "learned-curve":
+        learned_curve([int(x) for x in args.sizes.split(",")], args.seed, args.per_iter, args.epochs, args.diis)
 
 
 if __name__ == "__main__":

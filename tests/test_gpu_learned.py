@@ -110,12 +110,22 @@ def test_learned_step_matches_network(gpu_ctx, o, v, prev):
     else:
         rho = np.zeros_like(u)
     X = np.stack([u.real, u.imag, rho.real, rho.imag], 1).astype(np.float32).astype(np.float64)
-    y = omlp.forward(net.params(bf16=True).astype(np.float64), X)
+    pw = net.params(bf16=True).astype(np.float64)
+    y = omlp.forward(pw, X, h1_bf16=True)
     g = y[:, 0] + 1j * y[:, 1]
     q = r2[i, j, a, b] / D
     ref = t2[i, j, a, b] + q * (1 + g)
     got = o2[i, j, a, b]
-    assert np.abs((got - ref) / q).max() < 2e-5
+    err = np.abs((got - ref) / q)
+    # h1 is stored in BF16 for the hidden product: where the FP32 tanh lies within its rounding
+    # error of a BF16 rounding boundary the two sides may round it to neighbouring values; one such
+    # step (at most 2^-8 |h1_k|) moves g by at most 2^-8 sum_n |W3_n| |W2_nk| (tanh' <= 1)
+    W1, b1, W2, b2, W3, b3 = omlp.unpack(pw)
+    step = 2.0 ** -8 * np.max(np.abs(W3).sum(0) @ np.abs(W2))
+    # such flips touch a few percent of the samples (FP32 tanh error ~1e-6 against the BF16 spacing
+    # 2^-8, over 64 activations per sample); the rest agree to FP32 rounding
+    assert np.mean(err < 2e-5) > 0.95, np.mean(err < 2e-5)
+    assert err.max() < 2.0 * step, (err.max(), step)
     assert np.array_equal(o2[j, i, a, b], -got) and np.array_equal(o2[i, j, b, a], -got)
     assert np.array_equal(o2[j, i, b, a], got)
     assert not np.any(o2[np.arange(o), np.arange(o)]) and not np.any(o2[:, :, np.arange(v), np.arange(v)])
