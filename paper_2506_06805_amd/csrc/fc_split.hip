@@ -91,14 +91,24 @@ __global__ void k_split_cols(const z* __restrict__ X, long rows, long K, long ld
 // T1-dressed virtual Cholesky vectors straight into split planes (the operand of the ladder
 // assembly): planes row a v + e, column P = split(s (L[a][e][P] - sum_m t[m][a] Lov[m][e][P])).
 // One workgroup per (e, 64 columns of P): the o x 64 slice of Lov sits in LDS, thread t owns column
-// P0 + t % 64 and walks a = t / 64, t / 64 + 4, ...  Columns N <= P < kp are written as zeros.
+// P0 + t % 64, and wave w takes the a values 4 (w + 4 k) + 0..3, so that each L_ov value read from
+// LDS feeds four products and the t1 values are the same across the wave.  Columns N <= P < kp are
+// written as zeros.
+template <int PREC>
+__device__ inline void put_split(u16* out, long plane, long off, double re, double im) {
+  const u16 rh = to16<PREC>((float)re), ih = to16<PREC>((float)im);
+  out[off] = rh;
+  out[plane + off] = to16<PREC>((float)(re - from16<PREC>(rh)));
+  out[2 * plane + off] = ih;
+  out[3 * plane + off] = to16<PREC>((float)(im - from16<PREC>(ih)));
+}
 template <int PREC, class T>
 __global__ __launch_bounds__(256) void k_split_dressed(const T* __restrict__ L, const z* __restrict__ Lov,
                                                        const z* __restrict__ t1, long o, long v, long N, long kp,
                                                        long rows_pad, double scale, u16* __restrict__ out) {
   extern __shared__ z sl[];   // [o][64]
   const long e = blockIdx.y, P = (long)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int a0 = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const long plane = rows_pad * kp;
   if (t1) {
     for (long i = threadIdx.x; i < o * 64; i += blockDim.x) {
@@ -108,28 +118,31 @@ __global__ __launch_bounds__(256) void k_split_dressed(const T* __restrict__ L, 
     __syncthreads();
   }
   if (P >= kp) return;
-  for (long a = a0; a < v; a += 4) {
-    double re = 0.0, im = 0.0;
+  for (long a0 = 4 * w; a0 < v; a0 += 16) {
+    double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     if (P < N) {
-      const T x = L[(a * v + e) * N + P];
-      re = x.x;
-      im = x.y;
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (a0 + d < v) {
+          const T x = L[((a0 + d) * v + e) * N + P];
+          re[d] = x.x;
+          im[d] = x.y;
+        }
       if (t1) {
         for (long m = 0; m < o; ++m) {
-          const z t = t1[m * v + a], y = sl[m * 64 + (threadIdx.x & 63)];
-          re -= t.x * y.x - t.y * y.y;
-          im -= t.x * y.y + t.y * y.x;
+          const z y = sl[m * 64 + (threadIdx.x & 63)];
+#pragma unroll
+          for (int d = 0; d < 4; ++d) {
+            const z t = a0 + d < v ? t1[m * v + a0 + d] : make_double2(0.0, 0.0);
+            re[d] -= t.x * y.x - t.y * y.y;
+            im[d] -= t.x * y.y + t.y * y.x;
+          }
         }
       }
     }
-    re *= scale;
-    im *= scale;
-    const long off = (a * v + e) * kp + P;
-    const u16 rh = to16<PREC>((float)re), ih = to16<PREC>((float)im);
-    out[off] = rh;
-    out[plane + off] = to16<PREC>((float)(re - from16<PREC>(rh)));
-    out[2 * plane + off] = ih;
-    out[3 * plane + off] = to16<PREC>((float)(im - from16<PREC>(ih)));
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+      if (a0 + d < v) put_split<PREC>(out, plane, ((a0 + d) * v + e) * kp + P, re[d] * scale, im[d] * scale);
   }
 }
 
@@ -226,6 +239,8 @@ using TileW8 = STile<2, 4, 64, 32>;
 using TileW4 = STile<2, 2, 64, 64>;
 // 4 waves of 64 x 48: 96-column outputs (pair counts near 3 x 96, such as 276)
 using TileW4n96 = STile<2, 2, 64, 48>;
+// 8 waves of 32 x 48 at two waves per SIMD: 128 x 96 outputs
+using TileW8n96 = STile<4, 2, 32, 48>;
 
 template <int PREC, int EPI, class TL>
 __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
@@ -458,23 +473,24 @@ void launch_split_t(int prec, dim3 grid, const SArgs& g, hipStream_t st) {
 }  // namespace
 
 // Tile of a split product: 0 = 8 waves of 64 x 32 (128 x 128), 1 = 4 waves of 64 x 64 (128 x 128),
-// 2 = 4 waves of 64 x 48 (128 x 96, for output widths that 96 pads much less than 128).  n = 0: the
-// ladder assembly (any width).
-// FNSCC_SPLIT_TILE=0/1 selects the 128 x 128 tile (a measurement switch).
+// 2 = 4 waves of 64 x 48 (128 x 96), 3 = 8 waves of 32 x 48 (128 x 96).  The 96-wide tiles serve
+// output widths that 96 pads much less than 128.  n = 0: the ladder assembly (any width).
+// FNSCC_SPLIT_TILE=1 selects the 4-wave tiles (a measurement switch; the 8-wave ones are faster).
 int split_tile_cfg(long n) {
   static const int base = [] {
     const char* e = getenv("FNSCC_SPLIT_TILE");
     return e ? (atoi(e) == 1 ? 1 : 0) : 0;
   }();
   // 96-wide tiles when they pad at least 15% less than 128-wide ones (N = 276: 288 against 384)
-  if (base == 1 && n > 96 && 100 * ((n + 95) / 96 * 96) < 85 * ((n + 127) / 128 * 128)) return 2;
+  if (n > 96 && 100 * ((n + 95) / 96 * 96) < 85 * ((n + 127) / 128 * 128)) return base == 1 ? 2 : 3;
   return base;
 }
-long tile_tn(int cfg) { return cfg == 2 ? 96 : 128; }
+long tile_tn(int cfg) { return (cfg == 2 || cfg == 3) ? 96 : 128; }
 template <int EPI>
 void launch_split(int cfg, int prec, dim3 grid, const SArgs& g, hipStream_t st) {
   if (cfg == 1) launch_split_t<EPI, TileW4>(prec, grid, g, st);
   else if (cfg == 2) launch_split_t<EPI, TileW4n96>(prec, grid, g, st);
+  else if (cfg == 3) launch_split_t<EPI, TileW8n96>(prec, grid, g, st);
   else launch_split_t<EPI, TileW8>(prec, grid, g, st);
 }
 
