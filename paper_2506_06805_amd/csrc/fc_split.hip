@@ -275,7 +275,8 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
   const u16* B = g.B + (g.b_row0 + n0) * g.kp;
 
   // staging: thread t holds, for each plane and pass, the 16-byte chunk of row (t / 4) + RP pass
-  // at k offset 8 (t % 4); rows past the tile (TM or TN not a multiple of RP) are not loaded
+  // at k offset 8 (t % 4); rows past the tile (TM or TN not a multiple of RP, or below RP) are
+  // neither loaded nor stored -- a store past the tile's rows would land in the next plane
   const int srow = tid >> 2, skc = 8 * (tid & 3);
   const long goff = (long)srow * g.kp + skc;
   const int sk = 8 * ((skc >> 3) ^ swz(srow));   // LDS column of this thread's staging chunk
@@ -283,6 +284,7 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
   // than one pass (PA or PB = 2), pass 1 of each plane
   static_assert(PA <= 2 && PB <= 2, "at most two staging passes per operand");
   uint4 a00, a10, a20, a30, a01, a11, a21, a31, b00, b10, b20, b30, b01, b11, b21, b31;
+  const bool a0ok = TMt >= RP || srow < TMt, b0ok = TNt >= RP || srow < TNt;
   const bool a1ok = PA > 1 && (TMt % RP == 0 || srow + RP < TMt);
   const bool b1ok = PB > 1 && (TNt % RP == 0 || srow + RP < TNt);
   const long gq = (long)RP * g.kp;   // global offset of the second pass
@@ -290,10 +292,14 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
   dst = *reinterpret_cast<const uint4*>((base) + (p) * (plane_stride) + goff + (q) * gq + (k0))
 #define FC_SGLOAD(k0)                                                                      \
   do {                                                                                     \
-    FC_LD(a00, A, g.a_plane, 0, 0, k0); FC_LD(a10, A, g.a_plane, 1, 0, k0);                \
-    FC_LD(a20, A, g.a_plane, 2, 0, k0); FC_LD(a30, A, g.a_plane, 3, 0, k0);                \
-    FC_LD(b00, B, g.b_plane, 0, 0, k0); FC_LD(b10, B, g.b_plane, 1, 0, k0);                \
-    FC_LD(b20, B, g.b_plane, 2, 0, k0); FC_LD(b30, B, g.b_plane, 3, 0, k0);                \
+    if (a0ok) {                                                                            \
+      FC_LD(a00, A, g.a_plane, 0, 0, k0); FC_LD(a10, A, g.a_plane, 1, 0, k0);              \
+      FC_LD(a20, A, g.a_plane, 2, 0, k0); FC_LD(a30, A, g.a_plane, 3, 0, k0);              \
+    }                                                                                      \
+    if (b0ok) {                                                                            \
+      FC_LD(b00, B, g.b_plane, 0, 0, k0); FC_LD(b10, B, g.b_plane, 1, 0, k0);              \
+      FC_LD(b20, B, g.b_plane, 2, 0, k0); FC_LD(b30, B, g.b_plane, 3, 0, k0);              \
+    }                                                                                      \
     if (a1ok) {                                                                            \
       FC_LD(a01, A, g.a_plane, 0, 1, k0); FC_LD(a11, A, g.a_plane, 1, 1, k0);              \
       FC_LD(a21, A, g.a_plane, 2, 1, k0); FC_LD(a31, A, g.a_plane, 3, 1, k0);              \
@@ -306,10 +312,14 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
 #define FC_ST(arr, buf, p, row, val) *reinterpret_cast<uint4*>(&arr[buf][p][row][sk]) = val
 #define FC_SSTORE(buf)                                                                     \
   do {                                                                                     \
-    FC_ST(sA, buf, 0, srow, a00); FC_ST(sA, buf, 1, srow, a10);                            \
-    FC_ST(sA, buf, 2, srow, a20); FC_ST(sA, buf, 3, srow, a30);                            \
-    FC_ST(sB, buf, 0, srow, b00); FC_ST(sB, buf, 1, srow, b10);                            \
-    FC_ST(sB, buf, 2, srow, b20); FC_ST(sB, buf, 3, srow, b30);                            \
+    if (a0ok) {                                                                            \
+      FC_ST(sA, buf, 0, srow, a00); FC_ST(sA, buf, 1, srow, a10);                          \
+      FC_ST(sA, buf, 2, srow, a20); FC_ST(sA, buf, 3, srow, a30);                          \
+    }                                                                                      \
+    if (b0ok) {                                                                            \
+      FC_ST(sB, buf, 0, srow, b00); FC_ST(sB, buf, 1, srow, b10);                          \
+      FC_ST(sB, buf, 2, srow, b20); FC_ST(sB, buf, 3, srow, b30);                          \
+    }                                                                                      \
     if (a1ok) {                                                                            \
       FC_ST(sA, buf, 0, srow + RP, a01); FC_ST(sA, buf, 1, srow + RP, a11);                \
       FC_ST(sA, buf, 2, srow + RP, a21); FC_ST(sA, buf, 3, srow + RP, a31);                \

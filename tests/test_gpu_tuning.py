@@ -43,6 +43,42 @@ def test_ladder_chunking(gpu_ctx, o, v, N, budget_gb, monkeypatch):
         assert np.abs(R - ref).max() / np.abs(ref).max() < tol, prec
 
 
+def test_split_ladder_on_the_96_wide_contraction_tile(gpu_ctx):
+    # o = 24 gives 276 occupied pairs, a width that the 128 x 96 split tile pads much less than the
+    # 128 x 128 one, so the contraction runs on it (its staging covers 128 rows per pass and must not
+    # store the 32 past the tile); the lo planes' contribution must survive at the FP16 bound
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 24, 12, 20
+    inst = synth.make_instance(o, v, N, seed=41, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    tau = _tau(o, v, 4)
+    ref = _ladder_ref(inst, tau)
+    for prec, tol in (("split-bf16", 2e-4), ("split-fp16", 2e-6)):
+        for _ in range(3):
+            R = fnscc.ladder(gpu_ctx, ints, _dev(tau), precision=prec).cpu().numpy()
+            assert np.abs(R - ref).max() / np.abs(ref).max() < tol, prec
+
+
+@pytest.mark.parametrize("cfg", [2, 8, 9])
+def test_ladder_with_forced_tiles(cfg):
+    # the FP64 ladder's assembly and contraction products, ladder-layout epilogue included, on the
+    # register-staged 128 x 128 tile (2), the direct-to-LDS 128 x 128 tile (8) and the
+    # direct-to-LDS 128 x 64 tile with Gauss's three products (9)
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 4, 129, 16
+    inst = synth.make_instance(o, v, N, seed=5 + v, kappa=0.6)
+    tau = _tau(o, v, 1)
+    ref = _ladder_ref(inst, tau)
+    ctx = fnscc.Context(0)
+    try:
+        ctx.set_gemm_config(cfg)
+        ints = fnscc.cd_integrals(ctx, inst.eps, inst.L, o)
+        R = fnscc.ladder(ctx, ints, _dev(tau), precision="fp64").cpu().numpy()
+        assert np.abs(R - ref).max() / np.abs(ref).max() < 1e-11
+    finally:
+        ctx.close()
+
+
 def test_autotune_keeps_results_and_roundtrips(gpu_ctx, tmp_path):
     from paper_2506_06805_amd import fnscc
     o, v, N = 7, 90, 60
