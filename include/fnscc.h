@@ -69,6 +69,13 @@ int fc_autotune_save(fc_ctx ctx, const char* path);
 int fc_autotune_load(fc_ctx ctx, const char* path);
 int fc_autotune_size(fc_ctx ctx);
 
+/* fc_set_gemm_config - forces tile configuration cfg (0 <= cfg < fc_gemm_num_configs()) on every
+ * single complex product of this context whose output it fits, in place of the size heuristic and
+ * the autotuner; cfg = -1 restores them.  Results of a product do not depend on the configuration
+ * beyond rounding order.  FC_EARG for a cfg outside [-1, fc_gemm_num_configs()). */
+int fc_set_gemm_config(fc_ctx ctx, int cfg);
+int fc_gemm_num_configs(void);
+
 /* cd_ao_pivoted - single-step pivoted Cholesky of the AO two-electron supermatrix (Eq. 21):
  * M ~= sum_P l_P l_P^T.  Each step takes as pivot the largest remaining diagonal entry (the lowest
  * index among equal ones), forms l = (M[p, :] - sum_{earlier P} l_P[p] l_P) / sqrt(d_p) and

@@ -393,6 +393,14 @@ int fc_autotune_load(fc_ctx ctx, const char* path) {
 
 int fc_autotune_size(fc_ctx ctx) { return ctx ? (int)ctx->tune.size() : 0; }
 
+int fc_set_gemm_config(fc_ctx ctx, int cfg) {
+  if (!ctx || cfg < -1 || cfg >= gemm_num_configs()) return FC_EARG;
+  ctx->gemm_cfg = cfg;
+  return FC_OK;
+}
+
+int fc_gemm_num_configs(void) { return gemm_num_configs(); }
+
 int cd_ao_pivoted(fc_ctx ctx, long m, const double* M, double tau, int max_vec, double* L, int* nvec, int* piv) {
   if (!ctx || m < 1 || !M || !L || !nvec || max_vec < 1 || !(tau > 0)) return FC_EARG;
   FC_TRY(ctx, {

@@ -1,15 +1,20 @@
 // Complex GEMM on the FP64 matrix cores of gfx950.
 //
-// In FP64 a complex product is four real products on v_mfma_f64_16x16x4f64:
+// A complex product is four real products on the matrix cores (the "4M" form):
 //   Cre += Are*Bre - Aim*Bim,   Cim += Are*Bim + Aim*Bre
-// (the "4M" form).  With FP32 arithmetic (the mixed-precision residual) it is Gauss's three
-// (3M): Are*Bre, Aim*Bim and (Are + Aim)(Bre + Bim) on v_mfma_f32_16x16x4f32.  Operands are
-// staged through LDS as interleaved complex rows, conjugation applied at staging time,
-// double-buffered so the next K slice loads while the current one feeds the matrix cores.
+// or Gauss's three (3M): Are*Bre, Aim*Bim and (Are + Aim)(Bre + Bim), giving Cre = P1 - P2 and
+// Cim = P3 - P1 - P2.  3M issues a quarter fewer products; its error bound has the same form with
+// (|Are| + |Aim|)(|Bre| + |Bim|) in place of |A||B| (Higham, "Stability of a method for multiplying
+// complex matrices with three real matrix multiplications", SIAM J. Matrix Anal. Appl. 13, 1992).
+// FP32 arithmetic (the mixed-precision residual) always uses 3M on v_mfma_f32_16x16x4f32; FP64
+// (v_mfma_f64_16x16x4f64) uses 3M on its large products and 4M on the rest.
 //
-// Tile shapes 64 x 64 (4 waves of 32 x 32), 128 x 64 (4 waves of 64 x 32) and 128 x 128 (8 waves
-// of 64 x 32), with K slices of 8 or 16 per pipeline step; a heuristic or the autotuner picks one
-// per product shape.  Workgroups are numbered so that each of the 8 XCDs walks a contiguous band
+// Register-staged tiles: operands staged through LDS as interleaved complex rows, conjugation
+// applied at staging time, double-buffered so the next K slice loads while the current one feeds
+// the matrix cores; shapes 64 x 64 (4 waves of 32 x 32), 128 x 64 (4 waves of 64 x 32) and
+// 128 x 128 (8 waves of 64 x 32), with K slices of 8 or 16 per pipeline step.  FP64 tiles staged by
+// direct-to-LDS loads: 128 x 128 (4M) and 128 x 64 (3M, 8 waves of 32 x 32), three buffers.  A
+// heuristic or the autotuner picks one per product shape.  Workgroups are numbered so that each of the 8 XCDs walks a contiguous band
 // of output tiles (consecutive tiles share a row of A in that XCD's L2).
 //
 // MFMA f64 16x16x4 lane layout (lane l of a 64-wide wave):
@@ -125,6 +130,64 @@ struct TileJob {
   long lv, lnB;   // ladder epilogue (EPI == 1)
 };
 
+// Writes a finished tile: alpha, beta and the output layout (row-major C, the ladder layout, or
+// raw split-K partial sums).  cr/ci hold the real/imaginary sums (FP64 4M), or with FP32 3M tiles
+// cr = sum ar br, ci = sum ai bi and cx = sum (ar + ai)(br + bi).
+template <int BM, int BN, int WGM, int WGN, int EPI, typename T, bool k3M, typename Acc, int FI, int FJ, int XI,
+          int XJ>
+__device__ __forceinline__ void tile_epilogue(const TileJob& g, const Acc (&cr)[FI][FJ], const Acc (&ci)[FI][FJ],
+                                              const Acc (&cx)[XI][XJ], int wm, int wn, int lr, int lk) {
+  const long m0 = g.m0, n0 = g.n0;
+  z* __restrict__ C = g.C;
+  const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
+  // Ladder layout: off = ((a nB + b) v + e) v + f = (a nB v + e) v + (b v^2 + f) splits into a row
+  // part and a column part, each formed once per row or column of the lane with 32-bit division
+  // (a per-element 64-bit division cost more than a tenth of the assembly's time).
+  long coff[FJ];
+  if (EPI == 1) {
+    const unsigned lv = (unsigned)g.lv;
+#pragma unroll
+    for (int j = 0; j < FJ; ++j) {
+      const unsigned n = (unsigned)(n0 + wn + 16 * j + lr), b = n / lv;
+      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < FI; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long m = m0 + wm + 16 * i + Mfma<T>::row(lk, r);
+      long roff = 0;
+      if (EPI == 1) {
+        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
+        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
+      }
+#pragma unroll
+      for (int j = 0; j < FJ; ++j) {
+        const long n = n0 + wn + 16 * j + lr;
+        if (m >= g.M || n >= g.N) continue;
+        double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
+        if constexpr (k3M) {
+          const double p1 = re, p2 = im;
+          re = p1 - p2;
+          im = (double)cx[i][j][r] - p1 - p2;
+        }
+        if (g.part) {  // split-K: raw partial sums, reduced in a fixed order afterwards
+          g.part[m * g.N + n] = make_double2(re, im);
+          continue;
+        }
+        const long off = EPI == 1 ? roff + coff[j] : m * g.ldc + n;
+        z out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
+        if (use_beta) {
+          z c0 = C[off];
+          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+        }
+        C[off] = out;
+      }
+    }
+}
+
 // Computes one tile with the whole workgroup, operands rounded to T at staging, products and
 // sums in T, the result written in FP64.  The LDS buffers are free again on return.
 template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T = double>
@@ -139,7 +202,6 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
   const long m0 = g.m0, n0 = g.n0, klo = g.klo, khi = g.khi;
   const z* __restrict__ A = g.A;
   const z* __restrict__ B = g.B;
-  z* __restrict__ C = g.C;
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
 
   z ra[LA], rb[LB];
@@ -257,58 +319,215 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 #undef FC_LOAD_TILE
 #undef FC_STORE_TILE
 
-  const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
-  // Ladder layout: off = ((a nB + b) v + e) v + f = (a nB v + e) v + (b v^2 + f) splits into a row
-  // part and a column part, each formed once per row or column of the lane with 32-bit division
-  // (a per-element 64-bit division cost more than a tenth of the assembly's time).
-  long coff[FJ];
-  if (EPI == 1) {
-    const unsigned lv = (unsigned)g.lv;
+  tile_epilogue<BM, BN, WGM, WGN, EPI, T, k3M>(g, cr, ci, cx, wm, wn, lr, lk);
+}
+
+// ------------------------------------------------------------------------------------------------
+// FP64 tiles fed by direct-to-LDS loads (global_load_lds_dwordx4).  Each lane moves 16 bytes -- one
+// complex FP64 element -- from global memory into LDS without passing through vector registers:
+// lane i of the wave writes slot i of a 64-slot (1 KiB) run whose base (M0) is uniform over the
+// wave.  Which element a lane fetches therefore fixes the LDS layout of a K slice (8 deep):
+//  * K-contiguous operand (A 'N'/'R', B 'T'/'C'): a run covers 8 rows x 8 K, the 8 lanes of a row
+//    fetching its 128-byte line; row m keeps its elements at slots 8m + (k ^ sw(m)), where sw puts
+//    the 16 rows of a fragment read on distinct 16-byte bank groups whether LDS serves 8 or 16
+//    lanes of a 128-bit read per pass.
+//  * M-contiguous operand (A 'T'/'C', B 'N'/'R'): a run covers 64 consecutive rows of one k.
+// LDS receives the raw elements, so conjugation flips the sign of the imaginary part in the
+// fragments.  Elements outside the product (rows >= M, k >= the split's end) come from a zero.
+//
+// Three LDS buffers, loads two slices ahead, fragments one K quarter ahead: step kt requests
+// slice kt + 2 into the buffer slice kt - 1 left, reads the fragments of slice kt's second quarter,
+// runs the first quarter's products, waits (own loads of slice kt + 1, then a workgroup barrier),
+// reads slice kt + 1's first quarter and runs the second quarter's products.  The loads are issued
+// from inline assembly: the compiler would otherwise make every later LDS read wait for all of
+// them, and the waits here are explicit.
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+__device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
+
+template <int BM, int BN>
+struct DmaSmem {
+  __attribute__((aligned(16))) z A[3][BM * 8];
+  __attribute__((aligned(16))) z B[3][BN * 8];
+};
+
+__device__ __forceinline__ int dma_sw(int m) { return ((m >> 1) & 7) ^ ((m & 1) << 2); }
+
+// LDS slot of element (row m, k) of a slice whose operand tile has R rows
+template <bool KC, int R>
+__device__ __forceinline__ int dma_slot(int m, int k) { return KC ? 8 * m + (k ^ dma_sw(m)) : k * R + m; }
+
+// the element of run r that lane `lane` fetches: row m and k within the slice
+template <bool KC, int R>
+__device__ __forceinline__ void dma_elem(int r, int lane, int& m, int& k) {
+  if (KC) { m = 8 * r + (lane >> 3); k = (lane & 7) ^ dma_sw(m); }
+  else { k = r / (R / 64); m = (r % (R / 64)) * 64 + lane; }
+}
+
+// 16 bytes per lane from src into LDS bytes [lds + 16 lane, lds + 16 lane + 16); lds uniform.
+// No register receives data, so nothing the compiler allocates is written late; M0 is restored.
+__device__ __forceinline__ void lds_dma16(const z* src, const z* lds) {
+  const unsigned dst = (unsigned)(unsigned long)(lds_ptr_t)(lds);
+  unsigned saved;
+  asm volatile(
+      "s_mov_b32 %0, m0\n\t"
+      "s_mov_b32 m0, %1\n\t"
+      "s_nop 0\n\t"
+      "global_load_lds_dwordx4 %2, off\n\t"
+      "s_mov_b32 m0, %0\n\t"
+      "s_nop 0"
+      : "=&s"(saved)
+      : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
+      : "memory");
+}
+
+__device__ __forceinline__ double flip_sign(double x, unsigned long long mask) {
+  return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) ^ mask);
+}
+
+template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI, bool G3M>
+__device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN>& sm) {
+  constexpr int BK = 8;
+  constexpr int NW = WGM * WGN;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
+  constexpr int FI = WTM / 16, FJ = WTN / 16;             // MFMA tiles per wave
+  constexpr int QA = BM / 8 / NW, QB = BN / 8 / NW;       // runs per wave and K slice
+  static_assert(QA * NW * 8 == BM && QB * NW * 8 == BN && BM % 64 == 0 && BN % 64 == 0, "run split");
+  constexpr bool KCA = !TA, KCB = TB;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = (wave / WGN) * WTM, wn = (wave % WGN) * WTN;
+  const long klo = g.klo, khi = g.khi;
+
+  // per-lane load plan: the element of each run at K slice 0, its k, whether its row exists
+  const z* pa[QA]; const z* pb[QB];
+  long ka[QA], kb[QB];
+  bool oka[QA], okb[QB];
 #pragma unroll
-    for (int j = 0; j < FJ; ++j) {
-      const unsigned n = (unsigned)(n0 + wn + 16 * j + lr), b = n / lv;
-      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
-    }
+  for (int q = 0; q < QA; ++q) {
+    int m, k;
+    dma_elem<KCA, BM>(wave + NW * q, lane, m, k);
+    long gm = g.m0 + m;
+    oka[q] = gm < g.M;
+    if (!oka[q]) gm = g.M - 1;
+    ka[q] = klo + k;
+    pa[q] = KCA ? g.A + gm * g.lda + ka[q] : g.A + ka[q] * g.lda + gm;
   }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    int n, k;
+    dma_elem<KCB, BN>(wave + NW * q, lane, n, k);
+    long gn = g.n0 + n;
+    okb[q] = gn < g.N;
+    if (!okb[q]) gn = g.N - 1;
+    kb[q] = klo + k;
+    pb[q] = KCB ? g.B + gn * g.ldb + kb[q] : g.B + kb[q] * g.ldb + gn;
+  }
+  const long stepA = KCA ? BK : BK * g.lda, stepB = KCB ? BK : BK * g.ldb;
+#define FC_DMA_SLICE(s, buf)                                                                       \
+  do {                                                                                             \
+    _Pragma("unroll") for (int q = 0; q < QA; ++q)                                                 \
+      lds_dma16((oka[q] && ka[q] + (s) * BK < khi) ? pa[q] + (s) * stepA : g_dma_zero,             \
+                &sm.A[buf][64 * (wave + NW * q)]);                                                 \
+    _Pragma("unroll") for (int q = 0; q < QB; ++q)                                                 \
+      lds_dma16((okb[q] && kb[q] + (s) * BK < khi) ? pb[q] + (s) * stepB : g_dma_zero,             \
+                &sm.B[buf][64 * (wave + NW * q)]);                                                 \
+  } while (0)
+
+  using Acc = d4;
+  Acc cr[FI][FJ], ci[FI][FJ], cx[G3M ? FI : 1][G3M ? FJ : 1];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long m = m0 + wm + 16 * i + Mfma<T>::row(lk, r);
-      long roff = 0;
-      if (EPI == 1) {
-        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
-        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
-      }
-#pragma unroll
-      for (int j = 0; j < FJ; ++j) {
-        const long n = n0 + wn + 16 * j + lr;
-        if (m >= g.M || n >= g.N) continue;
-        double re = (double)cr[i][j][r], im = (double)ci[i][j][r];
-        if constexpr (k3M) {
-          const double p1 = re, p2 = im;
-          re = p1 - p2;
-          im = (double)cx[i][j][r] - p1 - p2;
-        }
-        if (g.part) {  // split-K: raw partial sums, reduced in a fixed order afterwards
-          g.part[m * g.N + n] = make_double2(re, im);
-          continue;
-        }
-        const long off = EPI == 1 ? roff + coff[j] : m * g.ldc + n;
-        z out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
-        if (use_beta) {
-          z c0 = C[off];
-          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
-          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
-        }
-        C[off] = out;
-      }
+    for (int j = 0; j < FJ; ++j) {
+      cr[i][j] = Acc{0, 0, 0, 0};
+      ci[i][j] = Acc{0, 0, 0, 0};
+      if constexpr (G3M) cx[i][j] = Acc{0, 0, 0, 0};
     }
+
+  const unsigned long long cmA = g.conjA ? 0x8000000000000000ull : 0ull;
+  const unsigned long long cmB = g.conjB ? 0x8000000000000000ull : 0ull;
+  const int lr = lane & 15, lk = lane >> 4;
+  const long nk = (khi - klo + BK - 1) / BK;
+  // fragments of one K quarter: A rows (re, im), B columns (re, im)
+  struct Frag { double ar[FI], ai[FI], br[FJ], bi[FJ]; };
+#define FC_DMA_READ(buf, h, F)                                                                     \
+  do {                                                                                             \
+    _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                               \
+      const z v = sm.A[buf][dma_slot<KCA, BM>(wm + 16 * i + lr, 4 * (h) + lk)];                    \
+      F.ar[i] = v.x;                                                                               \
+      F.ai[i] = flip_sign(v.y, cmA);                                                               \
+    }                                                                                              \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                               \
+      const z v = sm.B[buf][dma_slot<KCB, BN>(wn + 16 * j + lr, 4 * (h) + lk)];                    \
+      F.br[j] = v.x;                                                                               \
+      F.bi[j] = flip_sign(v.y, cmB);                                                               \
+    }                                                                                              \
+  } while (0)
+  // 4M: cr += ar br - ai bi, ci += ar bi + ai br, the minus sign on bi (the same products as -ai
+  // times bi, bit for bit).  3M: cr += ar br, ci += ai bi, cx += (ar + ai)(br + bi).
+#define FC_DMA_MAC(F)                                                                              \
+  do {                                                                                             \
+    if constexpr (G3M) {                                                                           \
+      double sa_[FI], sb_[FJ];                                                                     \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = F.ar[i] + F.ai[i];                   \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) sb_[j] = F.br[j] + F.bi[j];                   \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
+          cr[i][j] = Mfma<double>::mac(F.ar[i], F.br[j], cr[i][j]);                                \
+          ci[i][j] = Mfma<double>::mac(F.ai[i], F.bi[j], ci[i][j]);                                \
+          cx[i][j] = Mfma<double>::mac(sa_[i], sb_[j], cx[i][j]);                                  \
+        }                                                                                          \
+    } else {                                                                                       \
+      double nbi[FJ];                                                                              \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) nbi[j] = -F.bi[j];                            \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
+          cr[i][j] = Mfma<double>::mac(F.ar[i], F.br[j], cr[i][j]);                                \
+          ci[i][j] = Mfma<double>::mac(F.ar[i], F.bi[j], ci[i][j]);                                \
+        }                                                                                          \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
+          cr[i][j] = Mfma<double>::mac(F.ai[i], nbi[j], cr[i][j]);                                 \
+          ci[i][j] = Mfma<double>::mac(F.ai[i], F.br[j], ci[i][j]);                                \
+        }                                                                                          \
+    }                                                                                              \
+  } while (0)
+
+  FC_DMA_SLICE(0, 0);
+  if (nk > 1) {
+    FC_DMA_SLICE(1, 1);
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
+  } else {
+    asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+  }
+  Frag f0, f1;
+  FC_DMA_READ(0, 0, f0);
+  int buf = 0;
+  for (long kt = 0; kt < nk; ++kt) {
+    const int nbuf = buf == 2 ? 0 : buf + 1;
+    if (kt + 2 < nk) FC_DMA_SLICE(kt + 2, nbuf == 2 ? 0 : nbuf + 1);
+    FC_DMA_READ(buf, 1, f1);
+    FC_DMA_MAC(f0);
+    if (kt + 1 < nk) {
+      // own loads of slice kt + 1 done (those of slice kt + 2 may still run), own reads of slice
+      // kt done; then every wave's
+      if (kt + 2 < nk) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
+      else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+      FC_DMA_READ(nbuf, 0, f0);
+    }
+    FC_DMA_MAC(f1);
+    buf = nbuf;
+  }
+#undef FC_DMA_SLICE
+#undef FC_DMA_READ
+#undef FC_DMA_MAC
+  tile_epilogue<BM, BN, WGM, WGN, EPI, double, G3M>(g, cr, ci, cx, wm, wn, lr, lk);
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T, int DMA = 0>
 __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
-  __shared__ TileSmem<BM, BN, BK, T> sm;
   // The x extent is a multiple of 8, so a workgroup runs on XCD blockIdx.x % 8 whatever its split
   // (y) and batch (z) index.  Rotating x by those indices spreads the splits and batch entries
   // of a product with few tiles over all XCDs instead of stacking them on the XCD of tile 0.
@@ -341,7 +560,13 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
   j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
   j.lv = g.lv; j.lnB = g.lnB;
-  gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
+  if constexpr (DMA) {
+    __shared__ DmaSmem<BM, BN> sm;
+    gemm_tile_dma<BM, BN, WGM, WGN, TA, TB, EPI, DMA == 2>(j, sm);
+  } else {
+    __shared__ TileSmem<BM, BN, BK, T> sm;
+    gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
+  }
 }
 
 // C = alpha * sum_s P[s] + beta * C.  Lane x of a workgroup owns output t = 64 b + x; its W waves
@@ -393,23 +618,26 @@ void splitk_reduce(hipStream_t st, const z* part, long ns, long M, long N, z* C,
   else k_splitk_reduce<1><<<nb, 64, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK, int EPI, typename T>
+template <int BM, int BN, int WGM, int WGN, int BK, int EPI, typename T, int DMA = 0>
 void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
   constexpr int NT = WGM * WGN * 64;
-  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, false, EPI, T><<<grid, NT, 0, s>>>(g);
-  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, true, EPI, T><<<grid, NT, 0, s>>>(g);
-  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, false, EPI, T><<<grid, NT, 0, s>>>(g);
-  else zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, true, EPI, T><<<grid, NT, 0, s>>>(g);
+  if (!ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, false, EPI, T, DMA><<<grid, NT, 0, s>>>(g);
+  else if (!ta && tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, false, true, EPI, T, DMA><<<grid, NT, 0, s>>>(g);
+  else if (ta && !tb) zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, false, EPI, T, DMA><<<grid, NT, 0, s>>>(g);
+  else zgemm_f64_kernel<BM, BN, WGM, WGN, BK, true, true, EPI, T, DMA><<<grid, NT, 0, s>>>(g);
 }
 
 // Tile configurations: 64 x 64 (4 waves), 128 x 64 (4 waves) and 128 x 128 (8 waves), each with
 // K slices of 8 (configurations 0-2) or 16 (3-5) complex elements per pipeline step; 128 x 96
 // (4 waves of 64 x 48, configuration 6) for outputs about 300 columns wide, whose 64- and 128-wide
 // tiles leave up to a third of the last column of tiles idle; 32 x 32 (one wave, configuration 7)
-// for outputs of a few hundred elements with long K, which a 64 x 64 tile would mostly pad.
-constexpr int NCFG = 8;
-constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32},
-              CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32};
+// for outputs of a few hundred elements with long K, which a 64 x 64 tile would mostly pad;
+// with direct-to-LDS staging: 128 x 128, 8 waves of 64 x 32, four real products per complex one
+// (configuration 8), and 128 x 64, 8 waves of 32 x 32, Gauss's three (configuration 9) -- FP64
+// arithmetic only; with FP32 arithmetic they run configurations 2 and 1.
+constexpr int NCFG = 10;
+constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32, 128, 128},
+              CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32, 128, 64};
 
 template <int EPI, typename T>
 void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
@@ -421,7 +649,12 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
     case 4: launch<128, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s); break;
     case 5: launch<128, 128, 2, 4, 16, EPI, T>(g, ta, tb, grid, s); break;
     case 6: launch<128, 96, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
-    default: launch<32, 32, 1, 1, 8, EPI, T>(g, ta, tb, grid, s); break;
+    case 7: launch<32, 32, 1, 1, 8, EPI, T>(g, ta, tb, grid, s); break;
+    case 8: launch<128, 128, 2, 4, 8, EPI, T, sizeof(T) == sizeof(double) ? 1 : 0>(g, ta, tb, grid, s); break;
+    default:
+      if constexpr (sizeof(T) == sizeof(double)) launch<128, 64, 4, 2, 8, EPI, T, 2>(g, ta, tb, grid, s);
+      else launch<128, 64, 2, 2, 8, EPI, T>(g, ta, tb, grid, s);
+      break;
   }
 }
 
@@ -442,11 +675,17 @@ std::string bucket(char opA, char opB, long M, long N, long K, int batch, const 
 }
 
 // Default tile choice, from timing every configuration on the hot path's shapes: 32 x 32 for
-// tiny outputs; 128 x 128 when there are enough such tiles to fill the chip; otherwise 64 x 64,
-// with 16-element K slices in FP64 when K is long (skinny and split-K products), and 128 x 96 in
-// FP32 for outputs about 300 columns wide.
+// tiny outputs; in FP64 the direct-to-LDS 128 x 64 tile with Gauss's three products when its
+// tiles fill the chip and pad the output by at most a quarter (4096^3 66 -> 77 complex TFLOP/s,
+// the ladder's assembly 64 -> 74 and contraction 54 -> 68); 128 x 128 when there are enough such
+// tiles to fill the chip; otherwise 64 x 64, with 16-element K slices in FP64 when K is long
+// (skinny and split-K products), and 128 x 96 in FP32 for outputs about 300 columns wide.
 int heuristic_cfg(long M, long N, long K, int batch, bool fp32) {
   if (M <= 32 && N <= 32) return 7;
+  if (!fp32) {
+    const long tm = (M + 127) / 128, tn = (N + 63) / 64;
+    if (M >= 256 && N >= 64 && tm * tn * batch >= 256 && 4 * (tm * 128) * (tn * 64) <= 5 * M * N) return 9;
+  }
   const long t128 = ((M + 127) / 128) * ((N + 127) / 128), t64 = ((M + 63) / 64) * ((N + 63) / 64);
   // 128 x 128 unless its padding costs a quarter more work than 64 x 64 tiles (e.g. 300 x 300)
   const bool big = M >= 256 && N >= 256 && t128 * (long)batch >= 512 && 4 * t128 * 4 <= 5 * t64;
@@ -459,12 +698,14 @@ bool cfg_fits(int c, long M, long N) {
   return (CFG_BM[c] <= 64 || M >= 128) && (CFG_BN[c] <= 64 || N >= 96);
 }
 
-// Tuning override: FNSCC_GEMM_CFG selects one configuration for every product it fits.
-int forced_cfg(long M, long N) {
-  static const int forced = [] {
+// Tuning override: the context's configuration (fc_set_gemm_config), else FNSCC_GEMM_CFG, selects
+// one configuration for every product it fits.
+int forced_cfg(fc_ctx ctx, long M, long N) {
+  static const int env = [] {
     const char* e = getenv("FNSCC_GEMM_CFG");
     return e ? atoi(e) : -1;
   }();
+  const int forced = ctx->gemm_cfg >= 0 ? ctx->gemm_cfg : env;
   return (forced >= 0 && forced < NCFG && cfg_fits(forced, M, N)) ? forced : -1;
 }
 
@@ -473,7 +714,7 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
   if (M <= 0 || N <= 0 || batch <= 0) return;
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   int cfg = heuristic_cfg(M, N, K, batch, !lep && ctx->gemm_fp32);
-  const int forced = forced_cfg(M, N);
+  const int forced = forced_cfg(ctx, M, N);
   if (forced >= 0) {
     cfg = forced;
   } else if (ctx->autotune && K > 0) {
@@ -850,7 +1091,7 @@ void zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alp
   // the size heuristic (or the forced configuration), never the autotuner: timing trial products
   // needs a buffer of its own
   int cfg = heuristic_cfg(M, N, K, 1, ctx->gemm_fp32);
-  const int forced = forced_cfg(M, N);
+  const int forced = forced_cfg(ctx, M, N);
   if (forced >= 0) cfg = forced;
   zgemm_run(ctx, cfg, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, 1, 0, 0, 0, nullptr,
             static_cast<z*>(part));

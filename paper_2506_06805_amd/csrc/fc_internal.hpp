@@ -61,6 +61,8 @@ struct fc_ctx_s {
   // GEMM autotuning: shape bucket -> chosen configuration (and its measured time in ms)
   int autotune = 0;
   std::map<std::string, std::pair<int, float>> tune;
+  // forced tile configuration of single products (-1: heuristic or autotuner)
+  int gemm_cfg = -1;
 };
 
 namespace fc {

@@ -49,6 +49,8 @@ _sig = {
     "fc_set_timing": (C.c_int, [P, C.c_int]),
     "fc_take_timings": (C.c_int, [P, C.c_char_p, C.c_size_t]),
     "fc_set_autotune": (C.c_int, [P, C.c_int]),
+    "fc_set_gemm_config": (C.c_int, [P, C.c_int]),
+    "fc_gemm_num_configs": (C.c_int, []),
     "fc_autotune_save": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_load": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_size": (C.c_int, [P]),
@@ -223,6 +225,14 @@ class Context:
 
     def autotune_size(self):
         return int(lib.fc_autotune_size(self.h))
+
+    def set_gemm_config(self, cfg):
+        """Force GEMM tile configuration `cfg` on every product it fits (-1: size heuristic)."""
+        self.check(lib.fc_set_gemm_config(self.h, int(cfg)), "fc_set_gemm_config")
+
+    @staticmethod
+    def gemm_num_configs():
+        return int(lib.fc_gemm_num_configs())
 
     def take_timings(self):
         buf = C.create_string_buffer(1 << 16)

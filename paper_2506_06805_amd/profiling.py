@@ -47,7 +47,7 @@ GEMM_SHAPES = [("square4096", 4096, 4096, 4096, "N", "N"), ("assembly_T64", 1024
                ("fae_o24v160", 160, 160, 92160, "N", "N")]
 
 
-def gemm_probe(reps: int, tune: bool = False, save: str = "") -> None:
+def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1) -> None:
     """TFLOP/s of the library's complex GEMM (FP64 and FP32 arithmetic) on the listed shapes, next
     to torch's complex128 matmul on the same operands (a vendor-library reference point).  With
     `tune` the library's autotuner times every tile configuration first and keeps the fastest."""
@@ -58,6 +58,8 @@ def gemm_probe(reps: int, tune: bool = False, save: str = "") -> None:
     ctx = fnscc.Context(0)
     if tune:
         ctx.set_autotune(True)
+    if cfg >= 0:
+        ctx.set_gemm_config(cfg)
 
     def timed(fn):
         fn()
@@ -306,6 +308,7 @@ def main() -> None:
     g.add_argument("--reps", type=int, default=5)
     g.add_argument("--tune", action="store_true")
     g.add_argument("--save", type=str, default="", help="with --tune: write the tuned table to this file")
+    g.add_argument("--cfg", type=int, default=-1, help="force this tile configuration where it fits")
     f = sub.add_parser("fns-presets")
     f.add_argument("--o", type=int, default=24)
     f.add_argument("--v", type=int, default=300)
@@ -337,7 +340,7 @@ def main() -> None:
     if args.cmd == "copy":
         copy_probe(args.mib)
     elif args.cmd == "gemm":
-        gemm_probe(args.reps, args.tune, args.save)
+        gemm_probe(args.reps, args.tune, args.save, args.cfg)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
     elif args.cmd == "sigma":

@@ -66,3 +66,55 @@ def test_zgemm_fp32_arithmetic(gpu_ctx, M, N, K):
         assert err < 4 * 2.0 ** -24 * np.sqrt(K), (opA, opB, err)
         # and it is not FP64 arithmetic in disguise
         assert err > 2.0 ** -40
+
+
+# the tiles staged by direct-to-LDS loads (configuration 8: 128 x 128, four real products per
+# complex one; 9: 128 x 64, Gauss's three) against the register-staged 128 x 128 tile
+# (configuration 2) and numpy: every operand layout, ragged rows, columns and K
+# (elements outside the product are fetched as zeros), split K (140 x 200, K = 3000)
+@pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 9), (256, 384, 520), (140, 200, 3000)])
+def test_zgemm_direct_to_lds_tile(M, N, K):
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(7 * M + N + K)
+    alpha, beta = 0.4 + 0.3j, 0.8 - 0.1j
+    ctx = fnscc.Context(0)
+    try:
+        for opA, opB in itertools.product(OPS, OPS):
+            A = _rand((K, M) if opA in "TC" else (M, K), rng)
+            B = _rand((N, K) if opB in "TC" else (K, N), rng)
+            C0 = _rand((M, N), rng)
+            ref = alpha * (_op(A, opA) @ _op(B, opB)) + beta * C0
+            out, raw = {}, {}
+            dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+            for cfg in (2, 8, 9):
+                ctx.set_gemm_config(cfg)
+                C = torch.from_numpy(C0.copy()).cuda()
+                fnscc.zgemm(ctx, opA, opB, dA, dB, alpha, beta, C)
+                out[cfg] = C.cpu().numpy()
+                raw[cfg] = fnscc.zgemm(ctx, opA, opB, dA, dB).cpu().numpy()
+            for cfg in (8, 9):
+                err = np.abs(out[cfg] - ref).max() / np.abs(ref).max()
+                assert err < 1e-13, (cfg, opA, opB, err)
+            # configuration 8 sums the same products in the same order as the register-staged tile
+            # (the alpha/beta epilogue may fuse its multiply-adds differently in the two kernels)
+            assert np.array_equal(raw[8], raw[2]), (opA, opB, np.abs(raw[8] - raw[2]).max())
+            # configuration 9 (Gauss's three real products): error bounded like the four-product
+            # form's up to a small factor, |error| <~ K eps (|ar| + |ai|)(|br| + |bi|)
+            scale = (np.abs(_op(A, opA).real) + np.abs(_op(A, opA).imag)) @ \
+                    (np.abs(_op(B, opB).real) + np.abs(_op(B, opB).imag))
+            e9 = (np.abs(raw[9] - _op(A, opA) @ _op(B, opB)) / scale).max()
+            assert e9 < 4 * K * 2.0 ** -53, (opA, opB, e9)
+    finally:
+        ctx.close()
+
+
+def test_gemm_config_override_is_validated(gpu_ctx):
+    from paper_2506_06805_amd import fnscc
+    n = fnscc.Context.gemm_num_configs()
+    assert n >= 9
+    with pytest.raises(RuntimeError):
+        gpu_ctx.set_gemm_config(n)
+    with pytest.raises(RuntimeError):
+        gpu_ctx.set_gemm_config(-2)
+    gpu_ctx.set_gemm_config(-1)
