@@ -31,7 +31,7 @@ PEAK = {"fp64": 78.6, "split-bf16": 2516.6, "split-fp16": 2516.6}   # TFLOP/s, M
 # (from its first fill on) and scaled by what each counter reads for a 1 GiB device copy (FETCH
 # x2.0, WRITE x1.0): FP64 33.13 GB fetched + 9.09 GB written; split-BF16 16.70 + 5.00 GB.  Only
 # for the kernels and workload they were measured on.
-LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 42.22e9, ("o24v160n500", "split-bf16"): 21.70e9}
+LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.88e9, ("o24v160n500", "split-bf16"): 21.57e9}
 TRAFFIC_SOURCE = ("profile constant, not counted in this run: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
                   "summed over the ladder kernels of the same kernel version and workload "
                   "(profiles/ladder_o24v160n500.md), each scaled by its reading for a 1 GiB copy")
@@ -72,7 +72,7 @@ def _cpu_line(value, sample):
 # FP64 ladder rate measured at o=40, v=600, N=1800 (bench.py --ladder-only --workload o40v600n1800
 # --precision fp64): the basis of the extrapolated FP64 time at shapes where an FP64 ladder would
 # take tens of minutes
-FP64_LADDER_RATE = 60.2e12
+FP64_LADDER_RATE = 68.9e12
 
 
 def ladder_flops(o, v, N):

@@ -13,8 +13,8 @@
 // applied at staging time, double-buffered so the next K slice loads while the current one feeds
 // the matrix cores; shapes 64 x 64 (4 waves of 32 x 32), 128 x 64 (4 waves of 64 x 32) and
 // 128 x 128 (8 waves of 64 x 32), with K slices of 8 or 16 per pipeline step.  FP64 tiles staged by
-// direct-to-LDS loads: 128 x 128 (4M) and 128 x 64 (3M, 8 waves of 32 x 32), three buffers.  A
-// heuristic or the autotuner picks one per product shape.  Workgroups are numbered so that each of the 8 XCDs walks a contiguous band
+// direct-to-LDS loads: 128 x 128 (4M) and 128 x 64 (3M, 8 waves of 32 x 32, K slices of 8 or 16),
+// three buffers.  A heuristic or the autotuner picks one per product shape.  Workgroups are numbered so that each of the 8 XCDs walks a contiguous band
 // of output tiles (consecutive tiles share a row of A in that XCD's L2).
 //
 // MFMA f64 16x16x4 lane layout (lane l of a 64-wide wave):
@@ -346,22 +346,28 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 __device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
 
-template <int BM, int BN>
+template <int BM, int BN, int BK>
 struct DmaSmem {
-  __attribute__((aligned(16))) z A[3][BM * 8];
-  __attribute__((aligned(16))) z B[3][BN * 8];
+  __attribute__((aligned(16))) z A[3][BM * BK];
+  __attribute__((aligned(16))) z B[3][BN * BK];
 };
 
-__device__ __forceinline__ int dma_sw(int m) { return ((m >> 1) & 7) ^ ((m & 1) << 2); }
+// bank spread of a K-contiguous row of BK elements (see above); with BK = 16 a row is 256 bytes and
+// the row index itself spreads the 16 rows of a fragment read
+template <int BK>
+__device__ __forceinline__ int dma_sw(int m) {
+  if constexpr (BK == 8) return ((m >> 1) & 7) ^ ((m & 1) << 2);
+  else return m & 15;
+}
 
 // LDS slot of element (row m, k) of a slice whose operand tile has R rows
-template <bool KC, int R>
-__device__ __forceinline__ int dma_slot(int m, int k) { return KC ? 8 * m + (k ^ dma_sw(m)) : k * R + m; }
+template <bool KC, int R, int BK>
+__device__ __forceinline__ int dma_slot(int m, int k) { return KC ? BK * m + (k ^ dma_sw<BK>(m)) : k * R + m; }
 
 // the element of run r that lane `lane` fetches: row m and k within the slice
-template <bool KC, int R>
+template <bool KC, int R, int BK>
 __device__ __forceinline__ void dma_elem(int r, int lane, int& m, int& k) {
-  if (KC) { m = 8 * r + (lane >> 3); k = (lane & 7) ^ dma_sw(m); }
+  if (KC) { m = (64 / BK) * r + lane / BK; k = (lane % BK) ^ dma_sw<BK>(m); }
   else { k = r / (R / 64); m = (r % (R / 64)) * 64 + lane; }
 }
 
@@ -386,14 +392,16 @@ __device__ __forceinline__ double flip_sign(double x, unsigned long long mask) {
   return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) ^ mask);
 }
 
-template <int BM, int BN, int WGM, int WGN, bool TA, bool TB, int EPI, bool G3M>
-__device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN>& sm) {
-  constexpr int BK = 8;
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, bool G3M>
+__device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, BK>& sm) {
+  static_assert(BK == 8 || BK == 16, "K slices of 8 or 16");
+  constexpr int NQ = BK / 4;                              // K quarters (one MFMA deep) per slice
   constexpr int NW = WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
   constexpr int FI = WTM / 16, FJ = WTN / 16;             // MFMA tiles per wave
-  constexpr int QA = BM / 8 / NW, QB = BN / 8 / NW;       // runs per wave and K slice
-  static_assert(QA * NW * 8 == BM && QB * NW * 8 == BN && BM % 64 == 0 && BN % 64 == 0, "run split");
+  constexpr int QA = BM * BK / 64 / NW, QB = BN * BK / 64 / NW;   // runs per wave and K slice
+  static_assert(QA * NW * 64 == BM * BK && QB * NW * 64 == BN * BK && BM % 64 == 0 && BN % 64 == 0,
+                "run split");
   constexpr bool KCA = !TA, KCB = TB;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -402,36 +410,35 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN>&
 
   // per-lane load plan: the element of each run at K slice 0, its k, whether its row exists
   const z* pa[QA]; const z* pb[QB];
-  long ka[QA], kb[QB];
+  int ka[QA], kb[QB];
   bool oka[QA], okb[QB];
 #pragma unroll
   for (int q = 0; q < QA; ++q) {
-    int m, k;
-    dma_elem<KCA, BM>(wave + NW * q, lane, m, k);
+    int m;
+    dma_elem<KCA, BM, BK>(wave + NW * q, lane, m, ka[q]);
     long gm = g.m0 + m;
     oka[q] = gm < g.M;
     if (!oka[q]) gm = g.M - 1;
-    ka[q] = klo + k;
-    pa[q] = KCA ? g.A + gm * g.lda + ka[q] : g.A + ka[q] * g.lda + gm;
+    pa[q] = KCA ? g.A + gm * g.lda + klo + ka[q] : g.A + (klo + ka[q]) * g.lda + gm;
   }
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
-    int n, k;
-    dma_elem<KCB, BN>(wave + NW * q, lane, n, k);
+    int n;
+    dma_elem<KCB, BN, BK>(wave + NW * q, lane, n, kb[q]);
     long gn = g.n0 + n;
     okb[q] = gn < g.N;
     if (!okb[q]) gn = g.N - 1;
-    kb[q] = klo + k;
-    pb[q] = KCB ? g.B + gn * g.ldb + kb[q] : g.B + kb[q] * g.ldb + gn;
+    pb[q] = KCB ? g.B + gn * g.ldb + klo + kb[q] : g.B + (klo + kb[q]) * g.ldb + gn;
   }
   const long stepA = KCA ? BK : BK * g.lda, stepB = KCB ? BK : BK * g.ldb;
+  const long kspan = khi - klo;
 #define FC_DMA_SLICE(s, buf)                                                                       \
   do {                                                                                             \
     _Pragma("unroll") for (int q = 0; q < QA; ++q)                                                 \
-      lds_dma16((oka[q] && ka[q] + (s) * BK < khi) ? pa[q] + (s) * stepA : g_dma_zero,             \
+      lds_dma16((oka[q] && ka[q] + (s) * BK < kspan) ? pa[q] + (s) * stepA : g_dma_zero,           \
                 &sm.A[buf][64 * (wave + NW * q)]);                                                 \
     _Pragma("unroll") for (int q = 0; q < QB; ++q)                                                 \
-      lds_dma16((okb[q] && kb[q] + (s) * BK < khi) ? pb[q] + (s) * stepB : g_dma_zero,             \
+      lds_dma16((okb[q] && kb[q] + (s) * BK < kspan) ? pb[q] + (s) * stepB : g_dma_zero,           \
                 &sm.B[buf][64 * (wave + NW * q)]);                                                 \
   } while (0)
 
@@ -455,12 +462,12 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN>&
 #define FC_DMA_READ(buf, h, F)                                                                     \
   do {                                                                                             \
     _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                               \
-      const z v = sm.A[buf][dma_slot<KCA, BM>(wm + 16 * i + lr, 4 * (h) + lk)];                    \
+      const z v = sm.A[buf][dma_slot<KCA, BM, BK>(wm + 16 * i + lr, 4 * (h) + lk)];                \
       F.ar[i] = v.x;                                                                               \
       F.ai[i] = flip_sign(v.y, cmA);                                                               \
     }                                                                                              \
     _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                               \
-      const z v = sm.B[buf][dma_slot<KCB, BN>(wn + 16 * j + lr, 4 * (h) + lk)];                    \
+      const z v = sm.B[buf][dma_slot<KCB, BN, BK>(wn + 16 * j + lr, 4 * (h) + lk)];                \
       F.br[j] = v.x;                                                                               \
       F.bi[j] = flip_sign(v.y, cmB);                                                               \
     }                                                                                              \
@@ -502,22 +509,26 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN>&
   } else {
     asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
   }
-  Frag f0, f1;
-  FC_DMA_READ(0, 0, f0);
+  // fragments ping-pong between two sets, one K quarter ahead of the products
+  Frag f[2];
+  FC_DMA_READ(0, 0, f[0]);
   int buf = 0;
   for (long kt = 0; kt < nk; ++kt) {
     const int nbuf = buf == 2 ? 0 : buf + 1;
     if (kt + 2 < nk) FC_DMA_SLICE(kt + 2, nbuf == 2 ? 0 : nbuf + 1);
-    FC_DMA_READ(buf, 1, f1);
-    FC_DMA_MAC(f0);
-    if (kt + 1 < nk) {
-      // own loads of slice kt + 1 done (those of slice kt + 2 may still run), own reads of slice
-      // kt done; then every wave's
-      if (kt + 2 < nk) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
-      else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
-      FC_DMA_READ(nbuf, 0, f0);
+#pragma unroll
+    for (int h = 0; h < NQ; ++h) {
+      if (h + 1 < NQ) {
+        FC_DMA_READ(buf, h + 1, f[(h + 1) & 1]);
+      } else if (kt + 1 < nk) {
+        // own loads of slice kt + 1 done (those of slice kt + 2 may still run), own reads of
+        // slice kt done; then every wave's
+        if (kt + 2 < nk) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        FC_DMA_READ(nbuf, 0, f[(h + 1) & 1]);
+      }
+      FC_DMA_MAC(f[h & 1]);
     }
-    FC_DMA_MAC(f1);
     buf = nbuf;
   }
 #undef FC_DMA_SLICE
@@ -561,8 +572,8 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
   j.lv = g.lv; j.lnB = g.lnB;
   if constexpr (DMA) {
-    __shared__ DmaSmem<BM, BN> sm;
-    gemm_tile_dma<BM, BN, WGM, WGN, TA, TB, EPI, DMA == 2>(j, sm);
+    __shared__ DmaSmem<BM, BN, BK> sm;
+    gemm_tile_dma<BM, BN, WGM, WGN, BK, TA, TB, EPI, DMA == 2>(j, sm);
   } else {
     __shared__ TileSmem<BM, BN, BK, T> sm;
     gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
@@ -633,11 +644,12 @@ void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
 // tiles leave up to a third of the last column of tiles idle; 32 x 32 (one wave, configuration 7)
 // for outputs of a few hundred elements with long K, which a 64 x 64 tile would mostly pad;
 // with direct-to-LDS staging: 128 x 128, 8 waves of 64 x 32, four real products per complex one
-// (configuration 8), and 128 x 64, 8 waves of 32 x 32, Gauss's three (configuration 9) -- FP64
-// arithmetic only; with FP32 arithmetic they run configurations 2 and 1.
-constexpr int NCFG = 10;
-constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32, 128, 128},
-              CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32, 128, 64};
+// (configuration 8), and 128 x 64, 8 waves of 32 x 32, Gauss's three, with K slices of 8 (9) or
+// 16 (10) -- FP64 arithmetic only; with FP32 arithmetic they run the register-staged 128 x 128 and
+// 128 x 64 tiles.
+constexpr int NCFG = 11;
+constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32, 128, 128, 128},
+              CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32, 128, 64, 64};
 
 template <int EPI, typename T>
 void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
@@ -651,9 +663,13 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
     case 6: launch<128, 96, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
     case 7: launch<32, 32, 1, 1, 8, EPI, T>(g, ta, tb, grid, s); break;
     case 8: launch<128, 128, 2, 4, 8, EPI, T, sizeof(T) == sizeof(double) ? 1 : 0>(g, ta, tb, grid, s); break;
-    default:
+    case 9:
       if constexpr (sizeof(T) == sizeof(double)) launch<128, 64, 4, 2, 8, EPI, T, 2>(g, ta, tb, grid, s);
       else launch<128, 64, 2, 2, 8, EPI, T>(g, ta, tb, grid, s);
+      break;
+    default:
+      if constexpr (sizeof(T) == sizeof(double)) launch<128, 64, 4, 2, 16, EPI, T, 2>(g, ta, tb, grid, s);
+      else launch<128, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s);
       break;
   }
 }
@@ -675,16 +691,17 @@ std::string bucket(char opA, char opB, long M, long N, long K, int batch, const 
 }
 
 // Default tile choice, from timing every configuration on the hot path's shapes: 32 x 32 for
-// tiny outputs; in FP64 the direct-to-LDS 128 x 64 tile with Gauss's three products when its
-// tiles fill the chip and pad the output by at most a quarter (4096^3 66 -> 77 complex TFLOP/s,
-// the ladder's assembly 64 -> 74 and contraction 54 -> 68); 128 x 128 when there are enough such
+// tiny outputs; in FP64 the direct-to-LDS 128 x 64 tile with Gauss's three products and K slices
+// of 16 when its tiles fill the chip and pad the output by at most a quarter (4096^3 66 -> 81
+// complex TFLOP/s, the ladder's assembly 64 -> 76 and contraction 54 -> 70); 128 x 128 when there
+// are enough such
 // tiles to fill the chip; otherwise 64 x 64, with 16-element K slices in FP64 when K is long
 // (skinny and split-K products), and 128 x 96 in FP32 for outputs about 300 columns wide.
 int heuristic_cfg(long M, long N, long K, int batch, bool fp32) {
   if (M <= 32 && N <= 32) return 7;
   if (!fp32) {
     const long tm = (M + 127) / 128, tn = (N + 63) / 64;
-    if (M >= 256 && N >= 64 && tm * tn * batch >= 256 && 4 * (tm * 128) * (tn * 64) <= 5 * M * N) return 9;
+    if (M >= 256 && N >= 64 && tm * tn * batch >= 256 && 4 * (tm * 128) * (tn * 64) <= 5 * M * N) return 10;
   }
   const long t128 = ((M + 127) / 128) * ((N + 127) / 128), t64 = ((M + 63) / 64) * ((N + 63) / 64);
   // 128 x 128 unless its padding costs a quarter more work than 64 x 64 tiles (e.g. 300 x 300)

@@ -69,7 +69,7 @@ def test_zgemm_fp32_arithmetic(gpu_ctx, M, N, K):
 
 
 # the tiles staged by direct-to-LDS loads (configuration 8: 128 x 128, four real products per
-# complex one; 9: 128 x 64, Gauss's three) against the register-staged 128 x 128 tile
+# complex one; 9 and 10: 128 x 64, Gauss's three, K slices of 8 and 16) against the register-staged 128 x 128 tile
 # (configuration 2) and numpy: every operand layout, ragged rows, columns and K
 # (elements outside the product are fetched as zeros), split K (140 x 200, K = 3000)
 @pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 9), (256, 384, 520), (140, 200, 3000)])
@@ -87,24 +87,26 @@ def test_zgemm_direct_to_lds_tile(M, N, K):
             ref = alpha * (_op(A, opA) @ _op(B, opB)) + beta * C0
             out, raw = {}, {}
             dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
-            for cfg in (2, 8, 9):
+            for cfg in (2, 8, 9, 10):
                 ctx.set_gemm_config(cfg)
                 C = torch.from_numpy(C0.copy()).cuda()
                 fnscc.zgemm(ctx, opA, opB, dA, dB, alpha, beta, C)
                 out[cfg] = C.cpu().numpy()
                 raw[cfg] = fnscc.zgemm(ctx, opA, opB, dA, dB).cpu().numpy()
-            for cfg in (8, 9):
+            for cfg in (8, 9, 10):
                 err = np.abs(out[cfg] - ref).max() / np.abs(ref).max()
                 assert err < 1e-13, (cfg, opA, opB, err)
             # configuration 8 sums the same products in the same order as the register-staged tile
             # (the alpha/beta epilogue may fuse its multiply-adds differently in the two kernels)
             assert np.array_equal(raw[8], raw[2]), (opA, opB, np.abs(raw[8] - raw[2]).max())
-            # configuration 9 (Gauss's three real products): error bounded like the four-product
-            # form's up to a small factor, |error| <~ K eps (|ar| + |ai|)(|br| + |bi|)
+            # configurations 9 and 10 (Gauss's three real products, K slices of 8 and 16): error
+            # bounded like the four-product form's up to a small factor,
+            # |error| <~ K eps (|ar| + |ai|)(|br| + |bi|)
             scale = (np.abs(_op(A, opA).real) + np.abs(_op(A, opA).imag)) @ \
                     (np.abs(_op(B, opB).real) + np.abs(_op(B, opB).imag))
-            e9 = (np.abs(raw[9] - _op(A, opA) @ _op(B, opB)) / scale).max()
-            assert e9 < 4 * K * 2.0 ** -53, (opA, opB, e9)
+            for cfg in (9, 10):
+                e3 = (np.abs(raw[cfg] - _op(A, opA) @ _op(B, opB)) / scale).max()
+                assert e3 < 4 * K * 2.0 ** -53, (cfg, opA, opB, e3)
     finally:
         ctx.close()
 

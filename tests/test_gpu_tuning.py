@@ -59,11 +59,11 @@ def test_split_ladder_on_the_96_wide_contraction_tile(gpu_ctx):
             assert np.abs(R - ref).max() / np.abs(ref).max() < tol, prec
 
 
-@pytest.mark.parametrize("cfg", [2, 8, 9])
+@pytest.mark.parametrize("cfg", [2, 8, 9, 10])
 def test_ladder_with_forced_tiles(cfg):
     # the FP64 ladder's assembly and contraction products, ladder-layout epilogue included, on the
     # register-staged 128 x 128 tile (2), the direct-to-LDS 128 x 128 tile (8) and the
-    # direct-to-LDS 128 x 64 tile with Gauss's three products (9)
+    # direct-to-LDS 128 x 64 tiles with Gauss's three products (9, 10)
     from paper_2506_06805_amd import fnscc
     o, v, N = 4, 129, 16
     inst = synth.make_instance(o, v, N, seed=5 + v, kappa=0.6)
