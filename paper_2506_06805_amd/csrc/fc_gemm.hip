@@ -392,9 +392,10 @@ __device__ __forceinline__ double flip_sign(double x, unsigned long long mask) {
   return __builtin_bit_cast(double, __builtin_bit_cast(unsigned long long, x) ^ mask);
 }
 
-template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, bool G3M>
+template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, bool G3M, typename T>
 __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, BK>& sm) {
   static_assert(BK == 8 || BK == 16, "K slices of 8 or 16");
+  static_assert(G3M || sizeof(T) == sizeof(double), "FP32 arithmetic uses the three-product form");
   constexpr int NQ = BK / 4;                              // K quarters (one MFMA deep) per slice
   constexpr int NW = WGM * WGN;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;           // wave tile
@@ -442,7 +443,7 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
                 &sm.B[buf][64 * (wave + NW * q)]);                                                 \
   } while (0)
 
-  using Acc = d4;
+  using Acc = typename Mfma<T>::acc;
   Acc cr[FI][FJ], ci[FI][FJ], cx[G3M ? FI : 1][G3M ? FJ : 1];
 #pragma unroll
   for (int i = 0; i < FI; ++i)
@@ -457,19 +458,20 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
   const unsigned long long cmB = g.conjB ? 0x8000000000000000ull : 0ull;
   const int lr = lane & 15, lk = lane >> 4;
   const long nk = (khi - klo + BK - 1) / BK;
-  // fragments of one K quarter: A rows (re, im), B columns (re, im)
-  struct Frag { double ar[FI], ai[FI], br[FJ], bi[FJ]; };
+  // fragments of one K quarter: A rows (re, im), B columns (re, im), rounded to T (LDS holds the
+  // FP64 elements)
+  struct Frag { T ar[FI], ai[FI], br[FJ], bi[FJ]; };
 #define FC_DMA_READ(buf, h, F)                                                                     \
   do {                                                                                             \
     _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                               \
       const z v = sm.A[buf][dma_slot<KCA, BM, BK>(wm + 16 * i + lr, 4 * (h) + lk)];                \
-      F.ar[i] = v.x;                                                                               \
-      F.ai[i] = flip_sign(v.y, cmA);                                                               \
+      F.ar[i] = (T)v.x;                                                                            \
+      F.ai[i] = (T)flip_sign(v.y, cmA);                                                            \
     }                                                                                              \
     _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                               \
       const z v = sm.B[buf][dma_slot<KCB, BN, BK>(wn + 16 * j + lr, 4 * (h) + lk)];                \
-      F.br[j] = v.x;                                                                               \
-      F.bi[j] = flip_sign(v.y, cmB);                                                               \
+      F.br[j] = (T)v.x;                                                                            \
+      F.bi[j] = (T)flip_sign(v.y, cmB);                                                            \
     }                                                                                              \
   } while (0)
   // 4M: cr += ar br - ai bi, ci += ar bi + ai br, the minus sign on bi (the same products as -ai
@@ -477,17 +479,17 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
 #define FC_DMA_MAC(F)                                                                              \
   do {                                                                                             \
     if constexpr (G3M) {                                                                           \
-      double sa_[FI], sb_[FJ];                                                                     \
+      T sa_[FI], sb_[FJ];                                                                          \
       _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = F.ar[i] + F.ai[i];                   \
       _Pragma("unroll") for (int j = 0; j < FJ; ++j) sb_[j] = F.br[j] + F.bi[j];                   \
       _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
         _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
-          cr[i][j] = Mfma<double>::mac(F.ar[i], F.br[j], cr[i][j]);                                \
-          ci[i][j] = Mfma<double>::mac(F.ai[i], F.bi[j], ci[i][j]);                                \
-          cx[i][j] = Mfma<double>::mac(sa_[i], sb_[j], cx[i][j]);                                  \
+          cr[i][j] = Mfma<T>::mac(F.ar[i], F.br[j], cr[i][j]);                                     \
+          ci[i][j] = Mfma<T>::mac(F.ai[i], F.bi[j], ci[i][j]);                                     \
+          cx[i][j] = Mfma<T>::mac(sa_[i], sb_[j], cx[i][j]);                                       \
         }                                                                                          \
     } else {                                                                                       \
-      double nbi[FJ];                                                                              \
+      T nbi[FJ];                                                                                   \
       _Pragma("unroll") for (int j = 0; j < FJ; ++j) nbi[j] = -F.bi[j];                            \
       _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
         _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
@@ -534,7 +536,7 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
 #undef FC_DMA_SLICE
 #undef FC_DMA_READ
 #undef FC_DMA_MAC
-  tile_epilogue<BM, BN, WGM, WGN, EPI, double, G3M>(g, cr, ci, cx, wm, wn, lr, lk);
+  tile_epilogue<BM, BN, WGM, WGN, EPI, T, G3M>(g, cr, ci, cx, wm, wn, lr, lk);
 }
 
 template <int BM, int BN, int WGM, int WGN, int BK, bool TA, bool TB, int EPI, typename T, int DMA = 0>
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.lv = g.lv; j.lnB = g.lnB;
   if constexpr (DMA) {
     __shared__ DmaSmem<BM, BN, BK> sm;
-    gemm_tile_dma<BM, BN, WGM, WGN, BK, TA, TB, EPI, DMA == 2>(j, sm);
+    gemm_tile_dma<BM, BN, WGM, WGN, BK, TA, TB, EPI, DMA == 2, T>(j, sm);
   } else {
     __shared__ TileSmem<BM, BN, BK, T> sm;
     gemm_tile<BM, BN, WGM, WGN, BK, TA, TB, EPI, T>(j, sm);
@@ -643,10 +645,9 @@ void launch(const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStream_t s) {
 // (4 waves of 64 x 48, configuration 6) for outputs about 300 columns wide, whose 64- and 128-wide
 // tiles leave up to a third of the last column of tiles idle; 32 x 32 (one wave, configuration 7)
 // for outputs of a few hundred elements with long K, which a 64 x 64 tile would mostly pad;
-// with direct-to-LDS staging: 128 x 128, 8 waves of 64 x 32, four real products per complex one
-// (configuration 8), and 128 x 64, 8 waves of 32 x 32, Gauss's three, with K slices of 8 (9) or
-// 16 (10) -- FP64 arithmetic only; with FP32 arithmetic they run the register-staged 128 x 128 and
-// 128 x 64 tiles.
+// with direct-to-LDS staging: 128 x 128, 8 waves of 64 x 32 (configuration 8: four real products
+// per complex one in FP64, Gauss's three in FP32), and 128 x 64, 8 waves of 32 x 32, Gauss's three,
+// with K slices of 8 (9) or 16 (10).
 constexpr int NCFG = 11;
 constexpr int CFG_BM[NCFG] = {64, 128, 128, 64, 128, 128, 128, 32, 128, 128, 128},
               CFG_BN[NCFG] = {64, 64, 128, 64, 64, 128, 96, 32, 128, 64, 64};
@@ -662,15 +663,9 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
     case 5: launch<128, 128, 2, 4, 16, EPI, T>(g, ta, tb, grid, s); break;
     case 6: launch<128, 96, 2, 2, 8, EPI, T>(g, ta, tb, grid, s); break;
     case 7: launch<32, 32, 1, 1, 8, EPI, T>(g, ta, tb, grid, s); break;
-    case 8: launch<128, 128, 2, 4, 8, EPI, T, sizeof(T) == sizeof(double) ? 1 : 0>(g, ta, tb, grid, s); break;
-    case 9:
-      if constexpr (sizeof(T) == sizeof(double)) launch<128, 64, 4, 2, 8, EPI, T, 2>(g, ta, tb, grid, s);
-      else launch<128, 64, 2, 2, 8, EPI, T>(g, ta, tb, grid, s);
-      break;
-    default:
-      if constexpr (sizeof(T) == sizeof(double)) launch<128, 64, 4, 2, 16, EPI, T, 2>(g, ta, tb, grid, s);
-      else launch<128, 64, 2, 2, 16, EPI, T>(g, ta, tb, grid, s);
-      break;
+    case 8: launch<128, 128, 2, 4, 8, EPI, T, sizeof(T) == sizeof(double) ? 1 : 2>(g, ta, tb, grid, s); break;
+    case 9: launch<128, 64, 4, 2, 8, EPI, T, 2>(g, ta, tb, grid, s); break;
+    default: launch<128, 64, 4, 2, 16, EPI, T, 2>(g, ta, tb, grid, s); break;
   }
 }
 

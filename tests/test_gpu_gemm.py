@@ -85,7 +85,7 @@ def test_zgemm_direct_to_lds_tile(M, N, K):
             B = _rand((N, K) if opB in "TC" else (K, N), rng)
             C0 = _rand((M, N), rng)
             ref = alpha * (_op(A, opA) @ _op(B, opB)) + beta * C0
-            out, raw = {}, {}
+            out, raw, raw32 = {}, {}, {}
             dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
             for cfg in (2, 8, 9, 10):
                 ctx.set_gemm_config(cfg)
@@ -93,6 +93,11 @@ def test_zgemm_direct_to_lds_tile(M, N, K):
                 fnscc.zgemm(ctx, opA, opB, dA, dB, alpha, beta, C)
                 out[cfg] = C.cpu().numpy()
                 raw[cfg] = fnscc.zgemm(ctx, opA, opB, dA, dB).cpu().numpy()
+                raw32[cfg] = fnscc.zgemm(ctx, opA, opB, dA, dB, fp32=True).cpu().numpy()
+            # FP32 arithmetic: every tile rounds the operands to FP32 the same way and sums the
+            # same three products in the same order (same split-K counts at these shapes)
+            for cfg in (8, 9, 10):
+                assert np.array_equal(raw32[cfg], raw32[2]), (cfg, opA, opB, np.abs(raw32[cfg] - raw32[2]).max())
             for cfg in (8, 9, 10):
                 err = np.abs(out[cfg] - ref).max() / np.abs(ref).max()
                 assert err < 1e-13, (cfg, opA, opB, err)
