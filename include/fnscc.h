@@ -171,8 +171,11 @@ int fc_ladder_packed(fc_ctx ctx, fc_ints ints, const void* taup, const void* dre
  * Eq. 12-18 and 23 reduces to it): C = alpha op(A) op(B) + beta C, row-major, device pointers to
  * interleaved complex128. opA: 'N' A[m*lda+k], 'T' A[k*lda+m], 'C' conj(A[k*lda+m]),
  * 'R' conj(A[m*lda+k]); opB: 'N' B[k*ldb+n], 'T' B[n*ldb+k], 'C' conj(B[n*ldb+k]),
- * 'R' conj(B[k*ldb+n]). alpha, beta: host (re, im). precision: FC_FP64 or FC_FP32 (FP32 products
- * and sums). Stream-ordered; returns before completion. */
+ * 'R' conj(B[k*ldb+n]). alpha, beta: host (re, im). precision: FC_FP64, FC_FP32 (FP32 products
+ * and sums), or FC_SPLIT_BF16 / FC_SPLIT_FP16 (hi/lo split products with FP32 sums, as in the
+ * ladder; opA 'N' or 'R' with opB 'T' or 'C' only, other layouts FC_EUNSUPPORTED; an FP16 operand
+ * takes one power-of-two scale per 128 columns of K). Stream-ordered; returns before completion
+ * (the split precisions synchronise the context stream while choosing their FP16 scales). */
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
              long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision);
 /* fc_zgemm_noalloc - fc_zgemm for callers that cannot allocate device memory (code under HIP

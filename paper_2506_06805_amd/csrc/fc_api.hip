@@ -552,10 +552,17 @@ int fc_learned_step(fc_ctx ctx, fc_ints I, fc_mlp mlp, const void* t1, const voi
 int fc_zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, const double* alpha, const void* A,
              long lda, const void* B, long ldb, const double* beta, void* C, long ldc, int precision) {
   if (!ctx || !alpha || !beta || M < 0 || N < 0 || K < 0) return FC_EARG;
-  if (precision != FC_FP64 && precision != FC_FP32) return FC_EARG;
+  const bool split = precision == FC_SPLIT_BF16 || precision == FC_SPLIT_FP16;
+  if (precision != FC_FP64 && precision != FC_FP32 && !split) return FC_EARG;
   if (M == 0 || N == 0) return FC_OK;
   if (!C || (K > 0 && (!A || !B))) return FC_EARG;
   FC_TRY(ctx, {
+    if (split) {
+      // contraction-contiguous layouts only (FC_EUNSUPPORTED otherwise, before any launch)
+      zgemm_split(ctx, precision, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B,
+                  ldb, make_double2(beta[0], beta[1]), (z*)C, ldc);
+      return FC_OK;
+    }
     Fp32Gemms fp32(ctx, precision == FC_FP32);
     zgemm(ctx, opA, opB, M, N, K, make_double2(alpha[0], alpha[1]), (const z*)A, lda, (const z*)B, ldb,
           make_double2(beta[0], beta[1]), (z*)C, ldc);

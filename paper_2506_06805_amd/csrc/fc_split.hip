@@ -34,6 +34,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
 constexpr int TM = 128, TK = 32;   // row padding unit of split operands (the largest tile), K slice
+constexpr long SKB = 128;          // K batch of the per-batch power-of-two scales of FP16 operands
 constexpr int LDK = TK;   // LDS row length (16-bit elements): 64 bytes, four 16-byte chunks
 // Chunk c of LDS row r is stored at chunk c ^ swz(r).  Fragment reads (16 consecutive rows, one
 // chunk) and staging stores (4 consecutive rows, all chunks) then touch distinct banks whether
@@ -50,14 +51,16 @@ template <> __device__ inline double from16<FC_SPLIT_BF16>(u16 x) { return (doub
 template <> __device__ inline double from16<FC_SPLIT_FP16>(u16 x) { return (double)(float)__builtin_bit_cast(_Float16, x); }
 
 // X[r * ldx + k] (complex FP64, r < rows, k < K) -> planes [4][rows_pad][kp]
+// The scale is 2^bexp[k / kb] when bexp is given (one power of two per K batch), else `scale`.
 template <int PREC>
 __global__ void k_split(const z* __restrict__ X, long rows, long K, long ldx, long rows_pad, long kp, double scale,
-                        int conj, u16* __restrict__ out) {
+                        const int* __restrict__ bexp, long kb, int conj, u16* __restrict__ out) {
   const long total = rows_pad * kp, plane = rows_pad * kp;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     long r = t / kp, k = t % kp;
     z x = (r < rows && k < K) ? X[r * ldx + k] : make_double2(0.0, 0.0);
-    double re = x.x * scale, im = (conj ? -x.y : x.y) * scale;
+    const double sc = bexp ? ldexp(1.0, bexp[k / kb]) : scale;
+    double re = x.x * sc, im = (conj ? -x.y : x.y) * sc;
     u16 rh = to16<PREC>((float)re);
     u16 rl = to16<PREC>((float)(re - from16<PREC>(rh)));
     u16 ih = to16<PREC>((float)im);
@@ -105,7 +108,8 @@ __device__ inline void put_split(u16* out, long plane, long off, double re, doub
 template <int PREC, class T>
 __global__ __launch_bounds__(256) void k_split_dressed(const T* __restrict__ L, const z* __restrict__ Lov,
                                                        const z* __restrict__ t1, long o, long v, long N, long kp,
-                                                       long rows_pad, double scale, u16* __restrict__ out) {
+                                                       long rows_pad, double scale0, const int* __restrict__ bexp,
+                                                       long kb, u16* __restrict__ out) {
   extern __shared__ z sl[];   // [o][64]
   const long e = blockIdx.y, P = (long)blockIdx.x * 64 + (threadIdx.x & 63);
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -118,6 +122,7 @@ __global__ __launch_bounds__(256) void k_split_dressed(const T* __restrict__ L, 
     __syncthreads();
   }
   if (P >= kp) return;
+  const double scale = bexp ? ldexp(1.0, bexp[P / kb]) : scale0;   // 2^bexp per K batch of P
   for (long a0 = 4 * w; a0 < v; a0 += 16) {
     double re[4] = {0, 0, 0, 0}, im[4] = {0, 0, 0, 0};
     if (P < N) {
@@ -161,6 +166,22 @@ __global__ void k_maxabs_t(const T* __restrict__ X, long n, unsigned* out) {
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(s[0]));   // non-negative floats order as uints
 }
 
+// out[k / kb] = max |component| of X[r * ldx + k] over r < rows (one K batch per entry); the
+// workgroups of blockIdx.y take rows_per rows each
+template <class T>
+__global__ void k_maxabs_kbatch(const T* __restrict__ X, long rows, long K, long ldx, long kb, long rows_per,
+                                unsigned* __restrict__ out) {
+  const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const long r0 = (long)blockIdx.y * rows_per, r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+  float m = 0.f;
+  for (long r = r0; r < r1; ++r) {
+    const T x = X[r * ldx + k];
+    m = fmaxf(m, fmaxf((float)fabs((double)x.x), (float)fabs((double)x.y)));
+  }
+  atomicMax(out + k / kb, __float_as_uint(m));   // non-negative floats order as uints
+}
+
 // planes[p][r][k] = 0 for k0 <= k < kp, every row r < rows_pad of the four planes
 __global__ void k_zero_kpad(u16* __restrict__ planes, long rows_pad, long kp, long k0) {
   const long w = kp - k0, total = 4 * rows_pad * w;
@@ -170,22 +191,6 @@ __global__ void k_zero_kpad(u16* __restrict__ planes, long rows_pad, long kp, lo
   }
 }
 
-__global__ void k_maxabs(const z* __restrict__ X, long rows, long K, long ldx, unsigned* out) {
-  __shared__ float s[256];
-  float m = 0.f;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < rows * K; t += (long)gridDim.x * blockDim.x) {
-    z x = X[(t / K) * ldx + t % K];
-    m = fmaxf(m, fmaxf((float)fabs(x.x), (float)fabs(x.y)));
-  }
-  s[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(s[0]));   // non-negative floats order as uints
-}
-
 struct SArgs {
   const u16* A; long a_plane; long a_row0;   // planes of A, first row of this product
   const u16* B; long b_plane; long b_row0;
@@ -193,6 +198,11 @@ struct SArgs {
   z* C; long ldc;
   z alpha, beta;
   double inv_scale;
+  // per-K-batch scales (FP16 operands): the products of batch b carry 2^(eA_b + eB_b), eA_b from
+  // a_bexp (or the constant a_e when a_bexp is null), likewise for B; kb = 0: constant scales only
+  const int* a_bexp; const int* b_bexp;
+  long kb;
+  int a_e, b_e;
   long kchunk;
   z* part;
   long tiles;
@@ -344,9 +354,26 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
     FC_SSTORE(0);
   }
   __syncthreads();
+  // per-K-batch scales: the sums are kept in units of the current batch's factor 2^ecur and
+  // rescaled by a power of two (exact in FP32) where a new batch starts
+  int ecur = 0;
+  if (g.kb > 0)
+    ecur = (g.a_bexp ? g.a_bexp[klo / g.kb] : g.a_e) + (g.b_bexp ? g.b_bexp[klo / g.kb] : g.b_e);
   int buf = 0;
   for (long k0 = klo; k0 < khi; k0 += TK, buf ^= 1) {
     const bool more = k0 + TK < khi;
+    if (g.kb > 0 && k0 > klo && k0 % g.kb == 0) {
+      const long b = k0 / g.kb;
+      const int enew = (g.a_bexp ? g.a_bexp[b] : g.a_e) + (g.b_bexp ? g.b_bexp[b] : g.b_e);
+      if (enew != ecur) {
+        const float f = ldexpf(1.0f, enew - ecur);
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j) { rr[i][j] *= f; ii[i][j] *= f; im[i][j] *= f; }
+        ecur = enew;
+      }
+    }
     if (more) FC_SGLOAD(k0 + TK);
     if constexpr (TL::NT == 512) {
       // two waves per SIMD: fragments read per block pair, the other wave covers the latency
@@ -407,6 +434,7 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
 
   const int orow = 4 * (lane >> 4), ocol = lane & 15;
   const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
+  const double inv_scale = g.kb > 0 ? ldexp(1.0, -ecur) : g.inv_scale;
   // ladder layout ((a nB + b) v + e) v + f as a row part plus a column part, one 32-bit division
   // per row or column of the lane
   long coff[BJ];
@@ -433,7 +461,7 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
       for (int j = 0; j < BJ; ++j) {
         const long n = n0 + wn + 16 * j + ocol;
         if (m >= g.M || n >= g.N) continue;
-        double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * g.inv_scale, imv = (double)im[i][j][r] * g.inv_scale;
+        double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * inv_scale, imv = (double)im[i][j][r] * inv_scale;
         if (EPI == 1) {
           g.W[roff + coff[j]] = make_float2((float)re, (float)imv);
           continue;
@@ -504,6 +532,58 @@ void launch_split(int cfg, int prec, dim3 grid, const SArgs& g, hipStream_t st) 
   else launch_split_t<EPI, TileW8>(prec, grid, g, st);
 }
 
+// Per-K-batch maxima of |X[r * ldx + k]| (r < rows, k < K), batches of SKB, copied to the host.
+template <class T>
+static std::vector<double> kbatch_maxabs(fc_ctx ctx, const T* X, long rows, long K, long ldx, long nbatch) {
+  std::vector<double> out((size_t)nbatch, 0.0);
+  if (rows <= 0 || K <= 0) return out;
+  DBuf mx(ctx, sizeof(unsigned) * (size_t)nbatch);
+  FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned) * (size_t)nbatch, ctx->stream));
+  const long rows_per = std::max(1L, (rows + 255) / 256);   // at most 256 row groups
+  const dim3 grid((unsigned)((K + 255) / 256), (unsigned)((rows + rows_per - 1) / rows_per));
+  k_maxabs_kbatch<T><<<grid, 256, 0, ctx->stream>>>(X, rows, K, ldx, SKB, rows_per, mx.as<unsigned>());
+  FC_HIP(hipGetLastError());
+  std::vector<unsigned> h((size_t)nbatch);
+  FC_HIP(hipMemcpyAsync(h.data(), mx.p, sizeof(unsigned) * (size_t)nbatch, hipMemcpyDeviceToHost, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  for (long b = 0; b < nbatch; ++b) {
+    float m;
+    std::memcpy(&m, &h[(size_t)b], sizeof(m));
+    out[(size_t)b] = m;
+  }
+  return out;
+}
+
+// One power-of-two scale per K batch of an FP16 operand: e_b = 13 - ilogb(bound_b), so that the
+// batch's largest |x| maps into [2^13, 2^14) -- hi parts far below the FP16 maximum, lo parts
+// (~2^-11 of hi) normal down to ~1e-4 of that batch's largest entry, whatever the batch's size
+// relative to the others (Cholesky vectors decay over P).  A batch with no nonzero entry takes its
+// neighbour's exponent, so no rescale happens there.  Exponents stay within 40 of the smallest, so
+// that a product's FP32 sums, rescaled by 2^(eA + eB) differences at batch boundaries, stay far
+// from overflow (entries more than 2^40 below their operand's largest keep fewer bits).
+static void set_batch_scales(fc_ctx ctx, SplitOp& s, const std::vector<double>& bound) {
+  const long nb = (long)bound.size();
+  std::vector<int> e((size_t)nb, 0);
+  long first = -1;
+  int emin = 0;
+  for (long b = 0; b < nb; ++b)
+    if (bound[(size_t)b] > 0) {
+      e[(size_t)b] = std::max(-200, std::min(200, 13 - std::ilogb(bound[(size_t)b])));
+      emin = first < 0 ? e[(size_t)b] : std::min(emin, e[(size_t)b]);
+      if (first < 0) first = b;
+    }
+  for (long b = 0; b < nb; ++b) {
+    if (bound[(size_t)b] > 0) e[(size_t)b] = std::min(e[(size_t)b], emin + 40);
+    else if (b > 0) e[(size_t)b] = e[(size_t)b - 1];
+  }
+  for (long b = 0; b < first; ++b) e[(size_t)b] = e[(size_t)first];
+  s.bexp = DBuf(ctx, sizeof(int) * (size_t)nb);
+  FC_HIP(hipMemcpyAsync(s.bexp.p, e.data(), sizeof(int) * (size_t)nb, hipMemcpyHostToDevice, ctx->stream));
+  FC_HIP(hipStreamSynchronize(ctx->stream));
+  s.kb = SKB;
+  s.scale = 1.0;
+}
+
 SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, bool conj) {
   FC_REQUIRE(prec == FC_SPLIT_BF16 || prec == FC_SPLIT_FP16, FC_EARG, "split_operand: bad precision");
   SplitOp s;
@@ -512,28 +592,19 @@ SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long 
   s.rows_pad = (rows + TM - 1) / TM * TM + TM;   // one spare zero tile for row-offset products
   s.kp = std::max<long>(TK, (K + TK - 1) / TK * TK);
   s.scale = 1.0;
-  if (prec == FC_SPLIT_FP16 && rows > 0 && K > 0) {
-    DBuf mx(ctx, sizeof(unsigned));
-    FC_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned), ctx->stream));
-    unsigned nb = (unsigned)std::max(1L, std::min(2048L, (rows * K + 255) / 256));
-    k_maxabs<<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, mx.as<unsigned>());
-    FC_HIP(hipGetLastError());
-    unsigned h = 0;
-    FC_HIP(hipMemcpyAsync(&h, mx.p, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
-    FC_HIP(hipStreamSynchronize(ctx->stream));
-    float m;
-    std::memcpy(&m, &h, sizeof(m));
-    // largest |x| maps into [2^13, 2^14): hi parts stay below the FP16 maximum with margin and
-    // lo parts (~2^-11 of hi) stay normal for entries down to ~1e-4 of the maximum
-    if (m > 0) s.scale = std::ldexp(1.0, 13 - std::ilogb((double)m));
-  }
+  // FP16 (5 exponent bits): one power-of-two scale per K batch; BF16 keeps FP32's exponent range
+  if (prec == FC_SPLIT_FP16 && rows > 0 && K > 0)
+    set_batch_scales(ctx, s, kbatch_maxabs(ctx, X, rows, K, ldx, (s.kp + SKB - 1) / SKB));
   s.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)s.rows_pad * s.kp);
   const long total = s.rows_pad * s.kp;
   unsigned nb = (unsigned)std::max(1L, std::min(1048576L, (total + 1023) / 1024));
+  const int* be = s.kb > 0 ? s.bexp.as<int>() : nullptr;
   if (prec == FC_SPLIT_BF16)
-    k_split<FC_SPLIT_BF16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, s.rows_pad, s.kp, s.scale, (int)conj, s.buf.as<u16>());
+    k_split<FC_SPLIT_BF16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, s.rows_pad, s.kp, s.scale, be, s.kb, (int)conj,
+                                                        s.buf.as<u16>());
   else
-    k_split<FC_SPLIT_FP16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, s.rows_pad, s.kp, s.scale, (int)conj, s.buf.as<u16>());
+    k_split<FC_SPLIT_FP16><<<nb, 256, 0, ctx->stream>>>(X, rows, K, ldx, s.rows_pad, s.kp, s.scale, be, s.kb, (int)conj,
+                                                        s.buf.as<u16>());
   FC_HIP(hipGetLastError());
   return s;
 }
@@ -589,8 +660,10 @@ SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const
   s.kp = std::max<long>(TK, (N + TK - 1) / TK * TK);
   s.scale = 1.0;
   if (prec == FC_SPLIT_FP16) {
-    // |L_ae - sum_m t_m^a L_me| <= max|L_vv| + max_a sum_m |t_m^a| max|L_ov|
-    double bound = l_c64 ? device_maxabs(ctx, (const float2*)L, v * v * N) : device_maxabs(ctx, (const z*)L, v * v * N);
+    // per K batch of P: |L_ae - sum_m t_m^a L_me| <= max|L_vv| + max_a sum_m |t_m^a| max|L_ov|
+    const long nb = (s.kp + SKB - 1) / SKB;
+    std::vector<double> bound = l_c64 ? kbatch_maxabs(ctx, (const float2*)L, v * v, N, N, nb)
+                                      : kbatch_maxabs(ctx, (const z*)L, v * v, N, N, nb);
     if (t1) {
       std::vector<z> th((size_t)o * v);
       FC_HIP(hipMemcpyAsync(th.data(), t1, sizeof(z) * o * v, hipMemcpyDeviceToHost, ctx->stream));
@@ -601,9 +674,10 @@ SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const
         for (long m = 0; m < o; ++m) sa += std::hypot(th[m * v + a].x, th[m * v + a].y);
         tmax = std::max(tmax, sa);
       }
-      bound += tmax * (double)device_maxabs(ctx, Lov, o * v * N) * std::sqrt(2.0);
+      const std::vector<double> mo = kbatch_maxabs(ctx, Lov, o * v, N, N, nb);
+      for (long b = 0; b < nb; ++b) bound[(size_t)b] += tmax * mo[(size_t)b] * std::sqrt(2.0);
     }
-    if (bound > 0) s.scale = std::ldexp(1.0, 13 - std::ilogb(bound));
+    set_batch_scales(ctx, s, bound);
   }
   s.buf = DBuf(ctx, sizeof(u16) * 4 * (size_t)s.rows_pad * s.kp);
   // rows past v^2 are padding: zero them (the columns past N are zeroed by the kernel)
@@ -613,20 +687,21 @@ SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const
                           sizeof(u16) * (size_t)(s.rows_pad - s.rows) * s.kp, ctx->stream));
   const dim3 grid((unsigned)((s.kp + 63) / 64), (unsigned)v);
   const size_t shm = t1 ? sizeof(z) * 64 * (size_t)o : 0;
+  const int* be = s.kb > 0 ? s.bexp.as<int>() : nullptr;
   if (prec == FC_SPLIT_BF16) {
     if (l_c64)
-      k_split_dressed<FC_SPLIT_BF16, float2><<<grid, 256, shm, ctx->stream>>>((const float2*)L, Lov, t1, o, v, N, s.kp,
-                                                                              s.rows_pad, s.scale, s.buf.as<u16>());
+      k_split_dressed<FC_SPLIT_BF16, float2><<<grid, 256, shm, ctx->stream>>>(
+          (const float2*)L, Lov, t1, o, v, N, s.kp, s.rows_pad, s.scale, be, s.kb, s.buf.as<u16>());
     else
-      k_split_dressed<FC_SPLIT_BF16, double2><<<grid, 256, shm, ctx->stream>>>((const double2*)L, Lov, t1, o, v, N, s.kp,
-                                                                               s.rows_pad, s.scale, s.buf.as<u16>());
+      k_split_dressed<FC_SPLIT_BF16, double2><<<grid, 256, shm, ctx->stream>>>(
+          (const double2*)L, Lov, t1, o, v, N, s.kp, s.rows_pad, s.scale, be, s.kb, s.buf.as<u16>());
   } else {
     if (l_c64)
-      k_split_dressed<FC_SPLIT_FP16, float2><<<grid, 256, shm, ctx->stream>>>((const float2*)L, Lov, t1, o, v, N, s.kp,
-                                                                              s.rows_pad, s.scale, s.buf.as<u16>());
+      k_split_dressed<FC_SPLIT_FP16, float2><<<grid, 256, shm, ctx->stream>>>(
+          (const float2*)L, Lov, t1, o, v, N, s.kp, s.rows_pad, s.scale, be, s.kb, s.buf.as<u16>());
     else
-      k_split_dressed<FC_SPLIT_FP16, double2><<<grid, 256, shm, ctx->stream>>>((const double2*)L, Lov, t1, o, v, N, s.kp,
-                                                                               s.rows_pad, s.scale, s.buf.as<u16>());
+      k_split_dressed<FC_SPLIT_FP16, double2><<<grid, 256, shm, ctx->stream>>>(
+          (const double2*)L, Lov, t1, o, v, N, s.kp, s.rows_pad, s.scale, be, s.kb, s.buf.as<u16>());
   }
   FC_HIP(hipGetLastError());
   return s;
@@ -639,6 +714,18 @@ void split_zero_kpad(fc_ctx ctx, SplitOp& S, long k0) {
   unsigned nb = (unsigned)std::max(1L, std::min(65536L, (total + 255) / 256));
   k_zero_kpad<<<nb, 256, 0, ctx->stream>>>(S.buf.as<u16>(), S.rows_pad, S.kp, k0);
   FC_HIP(hipGetLastError());
+}
+
+// Scale fields of a split product: per-K-batch exponents of either operand, else the operands'
+// constant power-of-two scales folded into inv_scale.
+static void set_scales(SArgs& g, const SplitOp& A, const SplitOp& B) {
+  FC_REQUIRE(A.kb == 0 || B.kb == 0 || A.kb == B.kb, FC_EARG, "split product: operands batch K differently");
+  g.kb = A.kb > 0 ? A.kb : B.kb;
+  g.a_bexp = A.kb > 0 ? A.bexp.as<int>() : nullptr;
+  g.b_bexp = B.kb > 0 ? B.bexp.as<int>() : nullptr;
+  g.a_e = std::ilogb(A.scale);   // constant scales are powers of two
+  g.b_e = std::ilogb(B.scale);
+  g.inv_scale = 1.0 / (A.scale * B.scale);
 }
 
 void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const SplitOp& B, long b_row0, long N, z alpha,
@@ -654,7 +741,7 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
   g.B = B.buf.as<u16>(); g.b_plane = B.rows_pad * B.kp; g.b_row0 = b_row0;
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = C; g.ldc = ldc; g.alpha = alpha; g.beta = beta;
-  g.inv_scale = 1.0 / (A.scale * B.scale);
+  set_scales(g, A, B);
   const int tcfg = split_tile_cfg(N);
   const long tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.tiles = tiles;
@@ -704,7 +791,7 @@ void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const 
   g.B = B.buf.as<u16>(); g.b_plane = B.rows_pad * B.kp; g.b_row0 = b_row0;
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = nullptr; g.ldc = 0; g.alpha = make_double2(1, 0); g.beta = make_double2(0, 0);
-  g.inv_scale = 1.0 / (A.scale * B.scale);
+  set_scales(g, A, B);
   const int tcfg = split_tile_cfg(0);
   g.tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.kchunk = A.kp;

@@ -8,7 +8,11 @@ namespace fc {
 struct SplitOp {
   DBuf buf;            // planes re_hi, re_lo, im_hi, im_lo, each [rows_pad][kp] (16-bit)
   long rows = 0, rows_pad = 0, kp = 0;
-  double scale = 1.0;  // values stored as scale * x
+  double scale = 1.0;  // values stored as scale * x (a power of two; 1 when kb > 0)
+  // kb > 0: column k stored as 2^bexp[k / kb] x instead (int per K batch, device) -- FP16 operands
+  // whose contraction index is the Cholesky index, over which the vectors decay
+  DBuf bexp;
+  long kb = 0;
   int prec = FC_SPLIT_BF16;
 };
 
@@ -18,7 +22,8 @@ SplitOp split_operand(fc_ctx ctx, int prec, const z* X, long rows, long K, long 
 SplitOp split_operand_cols(fc_ctx ctx, int prec, const z* X, long rows, long K, long ldx, const int* colmap);
 // The ladder's assembly operand: rows a v + e, columns P of s (L_ae^P - sum_m t_m^a L_me^P), from L_vv
 // [a][e][P] in complex64 (l_c64) or complex128 and L_ov [m][e][P]; t1 (o x v) may be NULL (no
-// dressing; with dressing o <= 64).  FP16 takes one power-of-two scale from a bound on the dressed entries.
+// dressing; with dressing o <= 64).  FP16 takes one power-of-two scale per batch of P from a bound on
+// the dressed entries of that batch.
 SplitOp split_lvv_dressed(fc_ctx ctx, int prec, const void* L, bool l_c64, const z* Lov, const z* t1, long o, long v,
                           long N);
 // Zero the contraction columns [k0, kp) of every (padded) row of the four planes.

@@ -449,12 +449,21 @@ def ladder_packed(ctx: Context, ints: Ints, taup, t1=None, precision=-1, out=Non
     return R
 
 
-def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False, noalloc=False):
+def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False, noalloc=False, precision=None):
     """C = alpha op(A) op(B) + beta C on the library's complex GEMM (2-D contiguous tensors);
-    FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True.  noalloc=True calls
-    fc_zgemm_noalloc (no device allocation inside the library; C must then be given)."""
+    FP64 arithmetic, or FP32 arithmetic on the FP64 data with fp32=True, or the hi/lo split
+    products with precision="split-bf16" / "split-fp16" (opA N or R, opB T or C).  noalloc=True
+    calls fc_zgemm_noalloc (no device allocation inside the library; C must then be given)."""
     if opA not in "NTCR" or opB not in "NTCR" or len(opA) != 1 or len(opB) != 1:
         raise ValueError("zgemm: op must be one of N, T, C, R")
+    if precision is None:
+        prec = FC_FP32 if fp32 else FC_FP64
+    else:
+        prec = {"fp32": FC_FP32, **PRECISION}.get(precision, precision)
+        if prec not in (FC_FP64, FC_FP32, FC_SPLIT_BF16, FC_SPLIT_FP16):
+            raise ValueError(f"zgemm: unknown precision {precision!r}")
+        if noalloc and prec in (FC_SPLIT_BF16, FC_SPLIT_FP16):
+            raise ValueError("zgemm: the allocation-free product has no split precisions")
     _require(A, "zgemm: A", _C128)
     _require(B, "zgemm: B", _C128)
     if A.dim() != 2 or B.dim() != 2:
@@ -474,7 +483,7 @@ def zgemm(ctx: Context, opA, opB, A, B, alpha=1.0, beta=0.0, C=None, fp32=False,
     be = np.array([complex(beta).real, complex(beta).imag])
     fn, name = (lib.fc_zgemm_noalloc, "fc_zgemm_noalloc") if noalloc else (lib.fc_zgemm, "fc_zgemm")
     ctx.check(fn(ctx.h, opA.encode(), opB.encode(), M, N, K, al.ctypes.data, _ptr(A), A.shape[1],
-                 _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1], FC_FP32 if fp32 else FC_FP64), name)
+                 _ptr(B), B.shape[1], be.ctypes.data, _ptr(C), C.shape[1], prec), name)
     return C
 
 

@@ -125,3 +125,46 @@ def test_gemm_config_override_is_validated(gpu_ctx):
     with pytest.raises(RuntimeError):
         gpu_ctx.set_gemm_config(-2)
     gpu_ctx.set_gemm_config(-1)
+
+
+@pytest.mark.parametrize("prec,unit", [("split-bf16", 2.0 ** -16), ("split-fp16", 2.0 ** -22)])
+def test_zgemm_split_precisions(gpu_ctx, prec, unit):
+    # hi/lo split products: error within a few units of the split's precision of sum |a||b|
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(11)
+    M, N, K = 150, 140, 300
+    for opA, opB in (("N", "T"), ("R", "C"), ("N", "C")):
+        A, B = _rand((M, K), rng), _rand((N, K), rng)
+        ref = _op(A, opA) @ _op(B, opB)
+        scale = np.abs(A) @ np.abs(B).T
+        C = fnscc.zgemm(gpu_ctx, opA, opB, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), precision=prec)
+        err = (np.abs(C.cpu().numpy() - ref) / scale).max()
+        assert err < 8 * unit, (opA, opB, err)
+    # A stored K x M ('T'): not contraction-contiguous, refused by the library
+    with pytest.raises(fnscc.FcError) as e:
+        fnscc.zgemm(gpu_ctx, "T", "T", torch.from_numpy(A.T.copy()).cuda(), torch.from_numpy(B).cuda(), precision=prec)
+    assert e.value.code == fnscc.FC_EUNSUPPORTED
+
+
+def test_fp16_split_scales_each_k_batch(gpu_ctx):
+    # Columns k < 256 carry O(1) entries on the first half of the rows, columns k >= 256 entries of
+    # 2^-30 on the second half (Cholesky vectors decay over their index).  With one scale per
+    # operand the small entries would fall into FP16's subnormal range (2^-30 x 2^13 = 2^-17) and keep
+    # a few bits; with one power-of-two scale per 128 columns they keep the split's full precision.
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(12)
+    M, N, K, h = 96, 80, 512, 256
+    A, B = np.zeros((M, K), complex), np.zeros((N, K), complex)
+    A[:M // 2, :h], B[:N // 2, :h] = _rand((M // 2, h), rng), _rand((N // 2, h), rng)
+    A[M // 2:, h:], B[N // 2:, h:] = _rand((M - M // 2, K - h), rng) * 2.0 ** -30, _rand((N - N // 2, K - h), rng) * 2.0 ** -30
+    ref = A @ B.T
+    scale = np.abs(A) @ np.abs(B).T
+    C = fnscc.zgemm(gpu_ctx, "N", "T", torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
+                    precision="split-fp16").cpu().numpy()
+    for rows, cols in ((slice(0, M // 2), slice(0, N // 2)), (slice(M // 2, M), slice(N // 2, N))):
+        err = (np.abs(C[rows, cols] - ref[rows, cols]) / scale[rows, cols]).max()
+        assert err < 8 * 2.0 ** -22, err
+    # the blocks that share no nonzero column are exactly zero
+    assert not C[:M // 2, N // 2:].any() and not C[M // 2:, :N // 2].any()
