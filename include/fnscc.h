@@ -141,6 +141,10 @@ typedef struct {
   int stall_window; /* iterations without residual decrease before falling back (learned) */
   void (*on_iter)(int iter, const void* t1, const void* t2, void* user);
   void* user;
+  int diis_start;   /* first iteration whose iterate enters the DIIS history (earlier: plain steps) */
+  int precond;      /* 1 (default): Jacobi denominators dressed by the diagonals of the residual's
+                       one-particle intermediates (a diagonal Newton step); 0: bare orbital-energy
+                       denominators */
 } fc_ccsd_opts;
 void fc_ccsd_default_opts(fc_ccsd_opts* opts);
 

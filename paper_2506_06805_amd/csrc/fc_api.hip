@@ -12,7 +12,8 @@
 
 namespace fc {
 void stage_cholesky(fc_ctx ctx, fc_ints I, const void* Ldev, int l_dtype);
-void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2);
+void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2,
+                 const z* fd = nullptr);
 int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
                    const fc_eom_opts& op, z* omega, z* Rout, int* iters, bool left = false);
 int left_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps, const int* nroots,
@@ -138,7 +139,8 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
       FC_HIP(hipStreamSynchronize(ctx->stream));
       op.on_iter(it, t.p(), t.p() + n1, op.user);
     }
-    ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec, learned ? fd.as<z>() : nullptr);
+    ccsd_residual_dev(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, prec,
+                      (learned || op.precond == 1) ? fd.as<z>() : nullptr);
     z a = dotc(ctx, n1, r.p(), r.p()), b = dotc(ctx, n2, r.p() + n1, r.p() + n1);
     double rms = std::sqrt(std::max(0.0, (a.x + 0.25 * b.x) / std::max(1.0, nuniq)));
     if (!std::isfinite(a.x + b.x) && learned && have_good) {
@@ -171,9 +173,10 @@ static int solve_one(fc_ctx ctx, fc_ints I, const fc_ccsd_opts& op, fc_amps* tou
       FC_HIP(hipMemcpyAsync(rprev.p(), r.p() + n1, sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
       have_prev = true;
     } else {
-      jacobi_step(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1);
+      jacobi_step(ctx, I, t.p(), t.p() + n1, r.p(), r.p() + n1, tn.p(), tn.p() + n1,
+                  op.precond == 1 ? fd.as<z>() : nullptr);
     }
-    if (op.diis_dim > 1) {
+    if (op.diis_dim > 1 && it >= op.diis_start) {
       diis_push_extrapolate(ctx, D, tn.p(), t.p(), tx.p());
       std::swap(t, tx);
     } else {
@@ -487,6 +490,8 @@ void fc_ccsd_default_opts(fc_ccsd_opts* op) {
   op->learned = 0;
   op->precision = -1;  // inherit from the integral handle
   op->stall_window = 3;
+  op->diis_start = 1;
+  op->precond = 1;
 }
 
 int ccsd_solve(fc_ctx ctx, int nb, const fc_ints* ints, const fc_ccsd_opts* opts, fc_amps* t, double* e_corr, int* iters) {
@@ -496,6 +501,8 @@ int ccsd_solve(fc_ctx ctx, int nb, const fc_ints* ints, const fc_ccsd_opts* opts
     if (opts) op = *opts; else fc_ccsd_default_opts(&op);
     FC_REQUIRE(op.max_iter >= 1, FC_EARG, "ccsd_solve: max_iter must be >= 1");
     FC_REQUIRE(op.diis_dim <= 16, FC_EARG, "ccsd_solve: diis_dim must be <= 16");
+    FC_REQUIRE(op.diis_start >= 1, FC_EARG, "ccsd_solve: diis_start must be >= 1");
+    FC_REQUIRE(op.precond == 0 || op.precond == 1, FC_EARG, "ccsd_solve: precond must be 0 or 1");
     int status = FC_OK;
     for (int b = 0; b < nb; ++b) {
       FC_REQUIRE(ints[b], FC_EARG, "ccsd_solve: NULL integral handle");

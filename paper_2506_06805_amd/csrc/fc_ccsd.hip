@@ -72,6 +72,36 @@ __global__ void k_jacobi2(const z* t, const z* r, z* out, const double* eps, lon
     out[x] = make_double2(t[x].x + r[x].x / d, t[x].y + r[x].y / d);
   }
 }
+// The same step with the dressed diagonal of the T2 (T1) equation's one-particle operators,
+// d - (F_aa + F_bb - F_ii - F_jj) with F = fd (complex; fd[0..o) occupied, fd[o..o+v) virtual):
+// the diagonal of the residual's Jacobian, so the step is a diagonal Newton step.  Where the
+// dressing would bring the denominator below half the bare one's size, the bare one is used.
+__device__ inline z dressed_div(z r, double d, z df) {
+  const double dr = d - df.x, di = -df.y;
+  const double n2 = dr * dr + di * di;
+  if (!(n2 >= 0.25 * d * d)) return make_double2(r.x / d, r.y / d);
+  return make_double2((r.x * dr + r.y * di) / n2, (r.y * dr - r.x * di) / n2);
+}
+__global__ void k_jacobi1_dressed(const z* t, const z* r, z* out, const double* eps, const z* fd, long o, long v) {
+  GRID_STRIDE(x, o * v) {
+    long a = x % v, i = x / v;
+    const double d = eps[i] - eps[o + a];
+    const z df = make_double2(fd[o + a].x - fd[i].x, fd[o + a].y - fd[i].y);
+    const z q = dressed_div(r[x], d, df);
+    out[x] = make_double2(t[x].x + q.x, t[x].y + q.y);
+  }
+}
+__global__ void k_jacobi2_dressed(const z* t, const z* r, z* out, const double* eps, const z* fd, long o, long v) {
+  GRID_STRIDE(x, o * o * v * v) {
+    long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
+    if (i == j || a == b) { out[x] = make_double2(0, 0); continue; }
+    const double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
+    const z df = make_double2(fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x,
+                              fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y);
+    const z q = dressed_div(r[x], d, df);
+    out[x] = make_double2(t[x].x + q.x, t[x].y + q.y);
+  }
+}
 // X[m,n,i,j] -> X - X^(i<->j) added into W (o^4)
 // out[k] = F[k * n + k]
 __global__ void k_diag_copy(const z* F, long n, z* out) {
@@ -211,11 +241,21 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   FC_HIP(hipGetLastError());
 }
 
-// Jacobi step out = t + Omega/D (exported for the solver)
-void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2) {
+// Jacobi step out = t + Omega/D (exported for the solver); with fd (the dressed one-particle
+// diagonals from the residual) the denominators are dressed
+void jacobi_step(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, const z* r1, const z* r2, z* o1, z* o2,
+                 const z* fd) {
   const long o = I->o, v = I->v;
-  hipLaunchKernelGGL(k_jacobi1, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, t1, r1, o1, I->eps_d.as<double>(), o, v);
-  hipLaunchKernelGGL(k_jacobi2, dim3(nblk(o * o * v * v)), dim3(TPB), 0, ctx->stream, t2, r2, o2, I->eps_d.as<double>(), o, v);
+  if (fd) {
+    hipLaunchKernelGGL(k_jacobi1_dressed, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, t1, r1, o1,
+                       I->eps_d.as<double>(), fd, o, v);
+    hipLaunchKernelGGL(k_jacobi2_dressed, dim3(nblk(o * o * v * v)), dim3(TPB), 0, ctx->stream, t2, r2, o2,
+                       I->eps_d.as<double>(), fd, o, v);
+  } else {
+    hipLaunchKernelGGL(k_jacobi1, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, t1, r1, o1, I->eps_d.as<double>(), o, v);
+    hipLaunchKernelGGL(k_jacobi2, dim3(nblk(o * o * v * v)), dim3(TPB), 0, ctx->stream, t2, r2, o2,
+                       I->eps_d.as<double>(), o, v);
+  }
   FC_HIP(hipGetLastError());
 }
 

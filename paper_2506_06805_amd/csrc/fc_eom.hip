@@ -18,7 +18,7 @@
 #include "fc_sigma.hpp"
 
 namespace fc {
-void jacobi_step(fc_ctx, fc_ints, const z*, const z*, const z*, const z*, z*, z*);
+void jacobi_step(fc_ctx, fc_ints, const z*, const z*, const z*, const z*, z*, z*, const z* = nullptr);
 namespace {
 constexpr int TPB = 256;
 inline unsigned nblk(long n) { return (unsigned)std::max(1L, std::min(1048576L, (n + TPB * 4 - 1) / (TPB * 4))); }

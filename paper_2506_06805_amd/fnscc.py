@@ -33,7 +33,8 @@ ON_ITER_FN = C.CFUNCTYPE(None, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p)
 class CcsdOpts(C.Structure):
     _fields_ = [("e_tol", C.c_double), ("r_tol", C.c_double), ("max_iter", C.c_int), ("diis_dim", C.c_int),
                 ("learned", C.c_int), ("precision", C.c_int), ("t1_init", C.c_void_p), ("t2_init", C.c_void_p),
-                ("mlp", C.c_void_p), ("stall_window", C.c_int), ("on_iter", ON_ITER_FN), ("user", C.c_void_p)]
+                ("mlp", C.c_void_p), ("stall_window", C.c_int), ("on_iter", ON_ITER_FN), ("user", C.c_void_p),
+                ("diis_start", C.c_int), ("precond", C.c_int)]
 
 
 class EomOpts(C.Structure):
