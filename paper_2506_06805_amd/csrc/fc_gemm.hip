@@ -696,7 +696,10 @@ int heuristic_cfg(long M, long N, long K, int batch, bool fp32) {
   if (M <= 32 && N <= 32) return 7;
   if (!fp32) {
     const long tm = (M + 127) / 128, tn = (N + 63) / 64;
-    if (M >= 256 && N >= 64 && tm * tn * batch >= 256 && 4 * (tm * 128) * (tn * 64) <= 5 * M * N) return 10;
+    // enough tiles to fill the chip, or outputs of a few hundred squared with K long enough for
+    // split K to fill it (576 x 576 x 25600: 47 -> 58 TFLOP/s; 3840 x 500 x 3840: 56 -> 71)
+    const bool fills = tm * tn * batch >= 256 || (M >= 256 && N >= 256 && K >= 2048 && batch == 1);
+    if (M >= 256 && N >= 64 && fills && 4 * (tm * 128) * (tn * 64) <= 5 * M * N) return 10;
   }
   const long t128 = ((M + 127) / 128) * ((N + 127) / 128), t64 = ((M + 63) / 64) * ((N + 63) / 64);
   // 128 x 128 unless its padding costs a quarter more work than 64 x 64 tiles (e.g. 300 x 300)

@@ -35,6 +35,7 @@ typedef unsigned short u16;
 
 constexpr int TM = 128, TK = 32;   // row padding unit of split operands (the largest tile), K slice
 constexpr long SKB = 128;          // K batch of the per-batch power-of-two scales of FP16 operands
+static_assert(SKB % 64 == 0, "a wave's columns must lie in one scale batch");
 constexpr int LDK = TK;   // LDS row length (16-bit elements): 64 bytes, four 16-byte chunks
 // Chunk c of LDS row r is stored at chunk c ^ swz(r).  Fragment reads (16 consecutive rows, one
 // chunk) and staging stores (4 consecutive rows, all chunks) then touch distinct banks whether
@@ -167,19 +168,23 @@ __global__ void k_maxabs_t(const T* __restrict__ X, long n, unsigned* out) {
 }
 
 // out[k / kb] = max |component| of X[r * ldx + k] over r < rows (one K batch per entry); the
-// workgroups of blockIdx.y take rows_per rows each
+// workgroups of blockIdx.y take rows_per rows each.  kb is a multiple of 64, so the 64 columns of
+// a wave lie in one batch: the wave reduces its maximum first and one lane updates the batch
+// (per-lane atomics on the few batch words serialise in L2).
 template <class T>
 __global__ void k_maxabs_kbatch(const T* __restrict__ X, long rows, long K, long ldx, long kb, long rows_per,
                                 unsigned* __restrict__ out) {
   const long k = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  if (k >= K) return;
   const long r0 = (long)blockIdx.y * rows_per, r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
   float m = 0.f;
-  for (long r = r0; r < r1; ++r) {
-    const T x = X[r * ldx + k];
-    m = fmaxf(m, fmaxf((float)fabs((double)x.x), (float)fabs((double)x.y)));
-  }
-  atomicMax(out + k / kb, __float_as_uint(m));   // non-negative floats order as uints
+  if (k < K)
+    for (long r = r0; r < r1; ++r) {
+      const T x = X[r * ldx + k];
+      m = fmaxf(m, fmaxf((float)fabs((double)x.x), (float)fabs((double)x.y)));
+    }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  const long k0 = k - (threadIdx.x & 63);   // the wave's first column
+  if ((threadIdx.x & 63) == 0 && k0 < K) atomicMax(out + k0 / kb, __float_as_uint(m));   // non-negative floats order as uints
 }
 
 // planes[p][r][k] = 0 for k0 <= k < kp, every row r < rows_pad of the four planes
