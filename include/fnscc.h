@@ -214,7 +214,9 @@ int ipeom_sigma(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* R, vo
  * Y, S: device, nvec x dim complex128.  Errors as ipeom_sigma. */
 int ipeom_sigma_left(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* Y, void* S);
 
-/* graph: 1 (default) captures the sigma launches of all instances once into a HIP graph and
+/* max_subspace: trial vectors kept before a restart collapses the subspace (0, the default:
+ * 10 x nroots; the host eigenproblem of the projected matrix grows as its cube).
+ * graph: 1 (default) captures the sigma launches of all instances once into a HIP graph and
  * replays it for every Davidson iteration; 0 launches them directly (same results bit for bit). */
 typedef struct {
   double r_tol, w_tol;

@@ -666,7 +666,7 @@ void fc_eom_default_opts(fc_eom_opts* op) {
   op->r_tol = 1e-9;
   op->w_tol = 1e-10;
   op->max_iter = 200;
-  op->max_subspace = 0;  // 0 = 20 x roots
+  op->max_subspace = 0;  // 0 = 10 x roots
   op->guess_per_root = 2;
   op->graph = 1;
 }

@@ -336,7 +336,9 @@ int davidson_batch(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* amps,
     s.k = nroots[b];
     FC_REQUIRE(s.k >= 1 && s.k <= s.dim, FC_EARG, "ipeom_davidson: nroots out of range");
     s.nguess = (int)std::min<long>(s.dim, std::max(s.k, op.guess_per_root * s.k));
-    const long msub = op.max_subspace > 0 ? op.max_subspace : 20L * s.k;
+    // 10 x roots by default: at o=24 v=160 with 8 roots, 18 iterations in 46 ms against 15 in
+    // 68 ms with 20 x roots (the host eigenproblem of the projected matrix grows as its cube)
+    const long msub = op.max_subspace > 0 ? op.max_subspace : 10L * s.k;
     s.maxsub = (int)std::min<long>(s.dim, std::max<long>(msub, s.nguess + s.k));
     s.V = DBuf(ctx, sizeof(z) * (size_t)s.maxsub * s.dim);
     s.S = DBuf(ctx, sizeof(z) * (size_t)s.maxsub * s.dim);
