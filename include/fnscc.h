@@ -76,6 +76,15 @@ int fc_autotune_size(fc_ctx ctx);
 int fc_set_gemm_config(fc_ctx ctx, int cfg);
 int fc_gemm_num_configs(void);
 
+/* fc_set_split_config - forces the staging of the 128-wide tiles of the split-precision products
+ * (FC_SPLIT_BF16 / FC_SPLIT_FP16 products and the ladder on them) of this context: 0 operands
+ * staged through registers, 8 waves; 1 the same with 4 waves; 2 operands loaded straight into LDS,
+ * 8 waves (0 <= cfg < fc_split_num_configs()); cfg = -1 restores the default (2).  0 and 2 give
+ * the same bits; 1 differs in rounding order only.  FC_EARG for a cfg outside
+ * [-1, fc_split_num_configs()). */
+int fc_set_split_config(fc_ctx ctx, int cfg);
+int fc_split_num_configs(void);
+
 /* cd_ao_pivoted - single-step pivoted Cholesky of the AO two-electron supermatrix (Eq. 21):
  * M ~= sum_P l_P l_P^T.  Each step takes as pivot the largest remaining diagonal entry (the lowest
  * index among equal ones), forms l = (M[p, :] - sum_{earlier P} l_P[p] l_P) / sqrt(d_p) and

@@ -8,6 +8,7 @@
 #include <sstream>
 
 #include "fc_gemm.hpp"
+#include "fc_split.hpp"
 #include "fc_state.hpp"
 
 namespace fc {
@@ -403,6 +404,14 @@ int fc_set_gemm_config(fc_ctx ctx, int cfg) {
 }
 
 int fc_gemm_num_configs(void) { return gemm_num_configs(); }
+
+int fc_set_split_config(fc_ctx ctx, int cfg) {
+  if (!ctx || cfg < -1 || cfg >= fc::FC_SPLIT_NUM_CONFIGS) return FC_EARG;
+  ctx->split_cfg = cfg;
+  return FC_OK;
+}
+
+int fc_split_num_configs(void) { return fc::FC_SPLIT_NUM_CONFIGS; }
 
 int cd_ao_pivoted(fc_ctx ctx, long m, const double* M, double tau, int max_vec, double* L, int* nvec, int* piv) {
   if (!ctx || m < 1 || !M || !L || !nvec || max_vec < 1 || !(tau > 0)) return FC_EARG;

@@ -26,6 +26,7 @@
 
 #include "fc_internal.hpp"
 #include "fc_gemm.hpp"
+#include "fc_dma.hpp"
 
 namespace fc {
 namespace {
@@ -341,9 +342,6 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 // reads slice kt + 1's first quarter and runs the second quarter's products.  The loads are issued
 // from inline assembly: the compiler would otherwise make every later LDS read wait for all of
 // them, and the waits here are explicit.
-typedef __attribute__((address_space(1))) void* gbl_ptr_t;
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
 __device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
 
 template <int BM, int BN, int BK>
@@ -369,23 +367,6 @@ template <bool KC, int R, int BK>
 __device__ __forceinline__ void dma_elem(int r, int lane, int& m, int& k) {
   if (KC) { m = (64 / BK) * r + lane / BK; k = (lane % BK) ^ dma_sw<BK>(m); }
   else { k = r / (R / 64); m = (r % (R / 64)) * 64 + lane; }
-}
-
-// 16 bytes per lane from src into LDS bytes [lds + 16 lane, lds + 16 lane + 16); lds uniform.
-// No register receives data, so nothing the compiler allocates is written late; M0 is restored.
-__device__ __forceinline__ void lds_dma16(const z* src, const z* lds) {
-  const unsigned dst = (unsigned)(unsigned long)(lds_ptr_t)(lds);
-  unsigned saved;
-  asm volatile(
-      "s_mov_b32 %0, m0\n\t"
-      "s_mov_b32 m0, %1\n\t"
-      "s_nop 0\n\t"
-      "global_load_lds_dwordx4 %2, off\n\t"
-      "s_mov_b32 m0, %0\n\t"
-      "s_nop 0"
-      : "=&s"(saved)
-      : "s"(__builtin_amdgcn_readfirstlane(dst)), "v"(src)
-      : "memory");
 }
 
 __device__ __forceinline__ double flip_sign(double x, unsigned long long mask) {
@@ -458,48 +439,52 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
   const unsigned long long cmB = g.conjB ? 0x8000000000000000ull : 0ull;
   const int lr = lane & 15, lk = lane >> 4;
   const long nk = (khi - klo + BK - 1) / BK;
-  // fragments of one K quarter: A rows (re, im), B columns (re, im), rounded to T (LDS holds the
-  // FP64 elements)
-  struct Frag { T ar[FI], ai[FI], br[FJ], bi[FJ]; };
+  // fragments of one K quarter as the raw FP64 elements (A rows, B columns).  Conjugation and the
+  // rounding to T happen in the products' step: an operation on a fragment right after its read
+  // would make the wave wait for the read there, before the products it is meant to overlap.
+  struct Frag { z a[FI], b[FJ]; };
 #define FC_DMA_READ(buf, h, F)                                                                     \
   do {                                                                                             \
-    _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                               \
-      const z v = sm.A[buf][dma_slot<KCA, BM, BK>(wm + 16 * i + lr, 4 * (h) + lk)];                \
-      F.ar[i] = (T)v.x;                                                                            \
-      F.ai[i] = (T)flip_sign(v.y, cmA);                                                            \
-    }                                                                                              \
-    _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                               \
-      const z v = sm.B[buf][dma_slot<KCB, BN, BK>(wn + 16 * j + lr, 4 * (h) + lk)];                \
-      F.br[j] = (T)v.x;                                                                            \
-      F.bi[j] = (T)flip_sign(v.y, cmB);                                                            \
-    }                                                                                              \
+    _Pragma("unroll") for (int i = 0; i < FI; ++i)                                                 \
+      F.a[i] = sm.A[buf][dma_slot<KCA, BM, BK>(wm + 16 * i + lr, 4 * (h) + lk)];                   \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j)                                                 \
+      F.b[j] = sm.B[buf][dma_slot<KCB, BN, BK>(wn + 16 * j + lr, 4 * (h) + lk)];                   \
   } while (0)
   // 4M: cr += ar br - ai bi, ci += ar bi + ai br, the minus sign on bi (the same products as -ai
   // times bi, bit for bit).  3M: cr += ar br, ci += ai bi, cx += (ar + ai)(br + bi).
 #define FC_DMA_MAC(F)                                                                              \
   do {                                                                                             \
+    T ar_[FI], ai_[FI], br_[FJ], bi_[FJ];                                                          \
+    _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                               \
+      ar_[i] = (T)F.a[i].x;                                                                        \
+      ai_[i] = (T)flip_sign(F.a[i].y, cmA);                                                        \
+    }                                                                                              \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                               \
+      br_[j] = (T)F.b[j].x;                                                                        \
+      bi_[j] = (T)flip_sign(F.b[j].y, cmB);                                                        \
+    }                                                                                              \
     if constexpr (G3M) {                                                                           \
       T sa_[FI], sb_[FJ];                                                                          \
-      _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = F.ar[i] + F.ai[i];                   \
-      _Pragma("unroll") for (int j = 0; j < FJ; ++j) sb_[j] = F.br[j] + F.bi[j];                   \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = ar_[i] + ai_[i];                   \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) sb_[j] = br_[j] + bi_[j];                   \
       _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
         _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
-          cr[i][j] = Mfma<T>::mac(F.ar[i], F.br[j], cr[i][j]);                                     \
-          ci[i][j] = Mfma<T>::mac(F.ai[i], F.bi[j], ci[i][j]);                                     \
+          cr[i][j] = Mfma<T>::mac(ar_[i], br_[j], cr[i][j]);                                     \
+          ci[i][j] = Mfma<T>::mac(ai_[i], bi_[j], ci[i][j]);                                     \
           cx[i][j] = Mfma<T>::mac(sa_[i], sb_[j], cx[i][j]);                                       \
         }                                                                                          \
     } else {                                                                                       \
       T nbi[FJ];                                                                                   \
-      _Pragma("unroll") for (int j = 0; j < FJ; ++j) nbi[j] = -F.bi[j];                            \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) nbi[j] = -bi_[j];                            \
       _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
         _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
-          cr[i][j] = Mfma<double>::mac(F.ar[i], F.br[j], cr[i][j]);                                \
-          ci[i][j] = Mfma<double>::mac(F.ar[i], F.bi[j], ci[i][j]);                                \
+          cr[i][j] = Mfma<double>::mac(ar_[i], br_[j], cr[i][j]);                                \
+          ci[i][j] = Mfma<double>::mac(ar_[i], bi_[j], ci[i][j]);                                \
         }                                                                                          \
       _Pragma("unroll") for (int i = 0; i < FI; ++i)                                               \
         _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                           \
-          cr[i][j] = Mfma<double>::mac(F.ai[i], nbi[j], cr[i][j]);                                 \
-          ci[i][j] = Mfma<double>::mac(F.ai[i], F.br[j], ci[i][j]);                                \
+          cr[i][j] = Mfma<double>::mac(ai_[i], nbi[j], cr[i][j]);                                 \
+          ci[i][j] = Mfma<double>::mac(ai_[i], br_[j], ci[i][j]);                                \
         }                                                                                          \
     }                                                                                              \
   } while (0)
@@ -529,7 +514,11 @@ __device__ __forceinline__ void gemm_tile_dma(const TileJob& g, DmaSmem<BM, BN, 
         else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
         FC_DMA_READ(nbuf, 0, f[(h + 1) & 1]);
       }
+      // keep the next quarter's reads ahead of this quarter's products (the scheduler would
+      // otherwise sink them below the products or hoist the products' waits above them)
+      __builtin_amdgcn_sched_barrier(0);
       FC_DMA_MAC(f[h & 1]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     buf = nbuf;
   }

@@ -63,6 +63,8 @@ struct fc_ctx_s {
   std::map<std::string, std::pair<int, float>> tune;
   // forced tile configuration of single products (-1: heuristic or autotuner)
   int gemm_cfg = -1;
+  // forced staging of the 128-wide split-precision tiles (-1: default)
+  int split_cfg = -1;
 };
 
 namespace fc {

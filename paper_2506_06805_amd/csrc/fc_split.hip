@@ -12,9 +12,12 @@
 // the 128-row tile, so tile loads need no bounds checks.  C[m][n] = alpha sum_k A[m][k] B[n][k]
 // + beta C[m][n] (FP64 complex output).
 //
-// Tiles are 128 x 128 (8 waves of 64 x 32), K slices of 32, double-buffered in LDS with an XOR
-// chunk swizzle (see swz); with 128 KB of LDS and 222 registers one workgroup fits per CU, which
-// is what the split-K count of skinny products is chosen for.
+// Tiles are 128 x 128 (8 waves of 64 x 32), K slices of 32, in LDS with an XOR chunk swizzle (see
+// swz).  By default both operands go straight from global memory into LDS (k_gemm_split_dma: three
+// A buffers and two B buffers, 160 KB); the register-staged kernel (k_gemm_split: two buffers,
+// 128 KB, 32 staging registers per lane) serves the other tile shapes and gives the same bits.
+// Either way one workgroup fits per CU, which is what the split-K count of skinny products is
+// chosen for.
 //
 // MFMA 16x16x32 (bf16/f16) lane layout on gfx950 (measured): A fragment lane l holds
 // A[row = l % 16][k = 8 (l / 16) + 0..7], B fragment B[k = 8 (l / 16) + 0..7][col = l % 16],
@@ -23,6 +26,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "fc_dma.hpp"
 #include "fc_split.hpp"
 
 namespace fc {
@@ -257,6 +261,87 @@ using TileW4n96 = STile<2, 2, 64, 48>;
 // 8 waves of 32 x 48 at two waves per SIMD: 128 x 96 outputs
 using TileW8n96 = STile<4, 2, 32, 48>;
 
+// Origin (m0, n0) of this workgroup's output tile; false when the tile is past the product or is a
+// skipped tile of a triangular ladder launch.  XCD x (= blockIdx.x % 8) walks the contiguous tiles
+// [x * per, (x + 1) * per); the split index rotates the slot so that the splits of one tile spread
+// over all XCDs.
+template <int EPI, int TMt, int TNt>
+__device__ __forceinline__ bool split_tile_origin(const SArgs& g, long& m0, long& n0) {
+  const long ntn = (g.N + TNt - 1) / TNt;
+  const long per = (g.tiles + 7) / 8;
+  const long bx = ((long)blockIdx.x + blockIdx.y) % gridDim.x;
+  const long tile = (bx & 7) * per + (bx >> 3);
+  if (tile >= g.tiles) return false;
+  long mi = tile / ntn;
+  if (EPI == 1 && g.ltri) {
+    // triangular launches: fold the tile rows so every XCD's band mixes live and skipped tiles
+    const long tm = g.tiles / ntn;
+    mi = (mi & 1) ? tm - 1 - (mi >> 1) : (mi >> 1);
+  }
+  m0 = mi * TMt;
+  n0 = (tile % ntn) * TNt;
+  if (EPI == 1 && g.ltri) {
+    const long amin = m0 / g.lv, bmax = (n0 + TNt - 1 < g.N ? n0 + TNt - 1 : g.N - 1) / g.lv;
+    if (amin > bmax) return false;
+  }
+  return true;
+}
+
+// Output of a wave's BI x BJ blocks: C = alpha (rr - ii + i im) / 2^ecur + beta C, or the split-K
+// partial sums, or the ladder's FP32 W (EPI = 1).
+template <int EPI, int BI, int BJ>
+__device__ __forceinline__ void split_epilogue(const SArgs& g, const f4 (&rr)[BI][BJ], const f4 (&ii)[BI][BJ],
+                                               const f4 (&im)[BI][BJ], long m0, long n0, int wm, int wn, int lane,
+                                               int ecur) {
+  const int orow = 4 * (lane >> 4), ocol = lane & 15;
+  const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
+  const double inv_scale = g.kb > 0 ? ldexp(1.0, -ecur) : g.inv_scale;
+  // ladder layout ((a nB + b) v + e) v + f as a row part plus a column part, one 32-bit division
+  // per row or column of the lane
+  long coff[BJ];
+#pragma unroll
+  for (int j = 0; j < BJ; ++j) {
+    coff[j] = 0;
+    if (EPI == 1) {
+      const unsigned lv = (unsigned)g.lv;
+      const unsigned n = (unsigned)(n0 + wn + 16 * j + ocol), b = n / lv;
+      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long m = m0 + wm + 16 * i + orow + r;
+      long roff = 0;
+      if (EPI == 1) {
+        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
+        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
+      }
+#pragma unroll
+      for (int j = 0; j < BJ; ++j) {
+        const long n = n0 + wn + 16 * j + ocol;
+        if (m >= g.M || n >= g.N) continue;
+        double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * inv_scale, imv = (double)im[i][j][r] * inv_scale;
+        if (EPI == 1) {
+          g.W[roff + coff[j]] = make_float2((float)re, (float)imv);
+          continue;
+        }
+        if (g.part) {
+          g.part[((long)blockIdx.y * g.M + m) * g.N + n] = make_double2(re, imv);
+          continue;
+        }
+        z out = make_double2(g.alpha.x * re - g.alpha.y * imv, g.alpha.x * imv + g.alpha.y * re);
+        if (use_beta) {
+          z c0 = g.C[m * g.ldc + n];
+          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
+          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
+        }
+        g.C[m * g.ldc + n] = out;
+      }
+    }
+}
+
 template <int PREC, int EPI, class TL>
 __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
   constexpr int TMt = TL::TM, TNt = TL::TN, BI = TL::BI, BJ = TL::BJ, RP = TL::RP;
@@ -266,24 +351,8 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
   __shared__ __attribute__((aligned(16))) u16 sB[2][4][TNt][LDK];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave / TL::WN) * TL::WTM, wn = (wave % TL::WN) * TL::WTN;
-  const long ntn = (g.N + TNt - 1) / TNt;
-  // XCD x (= blockIdx.x % 8) walks the contiguous tiles [x * per, (x + 1) * per); the split index
-  // rotates the slot so that the splits of one tile spread over all XCDs
-  const long per = (g.tiles + 7) / 8;
-  const long bx = ((long)blockIdx.x + blockIdx.y) % gridDim.x;
-  const long tile = (bx & 7) * per + (bx >> 3);
-  if (tile >= g.tiles) return;
-  long mi = tile / ntn;
-  if (EPI == 1 && g.ltri) {
-    // triangular launches: fold the tile rows so every XCD's band mixes live and skipped tiles
-    const long tm = g.tiles / ntn;
-    mi = (mi & 1) ? tm - 1 - (mi >> 1) : (mi >> 1);
-  }
-  const long m0 = mi * TMt, n0 = (tile % ntn) * TNt;
-  if (EPI == 1 && g.ltri) {
-    const long amin = m0 / g.lv, bmax = (n0 + TNt - 1 < g.N ? n0 + TNt - 1 : g.N - 1) / g.lv;
-    if (amin > bmax) return;
-  }
+  long m0, n0;
+  if (!split_tile_origin<EPI, TMt, TNt>(g, m0, n0)) return;
   const long klo = (long)blockIdx.y * g.kchunk;
   const long khi = klo + g.kchunk < g.kp ? klo + g.kchunk : g.kp;
   const u16* A = g.A + (g.a_row0 + m0) * g.kp;
@@ -437,58 +506,170 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
     __syncthreads();
   }
 
-  const int orow = 4 * (lane >> 4), ocol = lane & 15;
-  const bool use_beta = (g.beta.x != 0.0 || g.beta.y != 0.0);
-  const double inv_scale = g.kb > 0 ? ldexp(1.0, -ecur) : g.inv_scale;
-  // ladder layout ((a nB + b) v + e) v + f as a row part plus a column part, one 32-bit division
-  // per row or column of the lane
-  long coff[BJ];
-#pragma unroll
-  for (int j = 0; j < BJ; ++j) {
-    coff[j] = 0;
-    if (EPI == 1) {
-      const unsigned lv = (unsigned)g.lv;
-      const unsigned n = (unsigned)(n0 + wn + 16 * j + ocol), b = n / lv;
-      coff[j] = (long)b * g.lv * g.lv + (long)(n - b * lv);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < BI; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long m = m0 + wm + 16 * i + orow + r;
-      long roff = 0;
-      if (EPI == 1) {
-        const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
-        roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
-      }
-#pragma unroll
-      for (int j = 0; j < BJ; ++j) {
-        const long n = n0 + wn + 16 * j + ocol;
-        if (m >= g.M || n >= g.N) continue;
-        double re = ((double)rr[i][j][r] - (double)ii[i][j][r]) * inv_scale, imv = (double)im[i][j][r] * inv_scale;
-        if (EPI == 1) {
-          g.W[roff + coff[j]] = make_float2((float)re, (float)imv);
-          continue;
-        }
-        if (g.part) {
-          g.part[((long)blockIdx.y * g.M + m) * g.N + n] = make_double2(re, imv);
-          continue;
-        }
-        z out = make_double2(g.alpha.x * re - g.alpha.y * imv, g.alpha.x * imv + g.alpha.y * re);
-        if (use_beta) {
-          z c0 = g.C[m * g.ldc + n];
-          out.x += g.beta.x * c0.x - g.beta.y * c0.y;
-          out.y += g.beta.x * c0.y + g.beta.y * c0.x;
-        }
-        g.C[m * g.ldc + n] = out;
-      }
-    }
+  split_epilogue<EPI, BI, BJ>(g, rr, ii, im, m0, n0, wm, wn, lane, ecur);
 }
 #undef FC_SGLOAD
 #undef FC_SSTORE
 #undef FC_LD
 #undef FC_ST
+
+// The same product with both operands staged by direct-to-LDS loads (8-wave tiles, 128 rows of A).
+// The register-staged kernel loads slice k + 1 while slice k's products run, through 32 staging
+// registers per lane; the loads of a slice then have one slice of products to land, and the
+// workgroup barrier waits for the slowest of its waves.  Here the loads bypass the registers and
+// run further ahead: A rotates through three LDS buffers (slice k + 3 is requested at the end of
+// slice k, into the buffer slice k has just left), B through two (slice k + 2 is requested once
+// every wave holds slice k's B fragments in registers, a quarter of a slice in).  LDS: 3 x 32 KiB
+// of A + 2 x 32 KiB of B = 160 KiB.  The layout in LDS is the register-staged kernel's (rows of
+// 32 elements, 16-byte chunks XOR-swizzled by swz(row)): a 1 KiB run is 16 rows of one plane, lane
+// l fetching row l / 4 and the chunk that belongs at position l % 4.  Fragments: B's of a whole
+// slice and A's of one 16-row block, read one block ahead of the products; the MFMA order per
+// accumulator is the register-staged kernel's, so both give the same bits.
+template <int PREC, int EPI, class TL>
+__global__ __launch_bounds__(TL::NT) void k_gemm_split_dma(SArgs g) {
+  static_assert(TL::NT == 512 && TL::BI == 4 && TL::BJ == 2, "8 waves of 64 x 32");
+  constexpr int TMt = TL::TM, TNt = TL::TN, BI = TL::BI, BJ = TL::BJ;
+  constexpr int QA = 4, QB = 4;   // loads per wave and slice: one 16-row run of each plane
+  static_assert(TMt == 16 * (TL::NT / 64) && TNt == 16 * (TL::NT / 64), "one 16-row block of each operand per wave");
+  __shared__ __attribute__((aligned(16))) u16 sA[3][4][TMt][LDK];
+  __shared__ __attribute__((aligned(16))) u16 sB[2][4][TNt][LDK];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = (wave / TL::WN) * TL::WTM, wn = (wave % TL::WN) * TL::WTN;
+  long m0, n0;
+  if (!split_tile_origin<EPI, TMt, TNt>(g, m0, n0)) return;
+  const long klo = (long)blockIdx.y * g.kchunk;
+  const long khi = klo + g.kchunk < g.kp ? klo + g.kchunk : g.kp;
+  const int nk = khi > klo ? (int)((khi - klo) / TK) : 0;   // kchunk and kp are multiples of TK
+
+  // wave w moves rows 16 w + 0..15 of each of the four planes of both operands (one 1 KiB run per
+  // plane): lane l fetches row 16 w + l / 4, the chunk that belongs at position l % 4
+  const int lrow = lane >> 2, lchunk = 8 * ((lane & 3) ^ swz(lrow));
+  const u16* pa = g.A + (g.a_row0 + m0 + 16 * wave + lrow) * g.kp + klo + lchunk;
+  const u16* pb = g.B + (g.b_row0 + n0 + 16 * wave + lrow) * g.kp + klo + lchunk;
+#define FC_DMA_A(s, slot)                                                                           \
+  _Pragma("unroll") for (int q = 0; q < 4; ++q)                                                     \
+    lds_dma16(pa + q * g.a_plane + (long)(s) * TK, &sA[slot][q][16 * wave][0])
+#define FC_DMA_B(s, slot)                                                                           \
+  _Pragma("unroll") for (int q = 0; q < 4; ++q)                                                     \
+    lds_dma16(pb + q * g.b_plane + (long)(s) * TK, &sB[slot][q][16 * wave][0])
+
+  const int lr = lane & 15, lk = 8 * ((lane >> 4) ^ swz(lr));
+#define FC_RD_A(slot, i, F) \
+  _Pragma("unroll") for (int p = 0; p < 4; ++p) F[p] = *reinterpret_cast<const uint4*>(&sA[slot][p][wm + 16 * (i) + lr][lk])
+#define FC_RD_BJ(slot, j, F) \
+  _Pragma("unroll") for (int p = 0; p < 4; ++p) F[p][j] = *reinterpret_cast<const uint4*>(&sB[slot][p][wn + 16 * (j) + lr][lk])
+  // planes 0 re_hi, 1 re_lo, 2 im_hi, 3 im_lo; terms hi*hi, hi*lo, lo*hi
+#define FC_PROD_J(i, j, FA, FB)                                                                     \
+  do {                                                                                              \
+    rr[i][j] = mma_r<PREC>(FA[0], FB[0][j], rr[i][j]);                                              \
+    rr[i][j] = mma_r<PREC>(FA[0], FB[1][j], rr[i][j]);                                              \
+    rr[i][j] = mma_r<PREC>(FA[1], FB[0][j], rr[i][j]);                                              \
+    ii[i][j] = mma_r<PREC>(FA[2], FB[2][j], ii[i][j]);                                              \
+    ii[i][j] = mma_r<PREC>(FA[2], FB[3][j], ii[i][j]);                                              \
+    ii[i][j] = mma_r<PREC>(FA[3], FB[2][j], ii[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[0], FB[2][j], im[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[0], FB[3][j], im[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[1], FB[2][j], im[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[2], FB[0][j], im[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[2], FB[1][j], im[i][j]);                                              \
+    im[i][j] = mma_r<PREC>(FA[3], FB[0][j], im[i][j]);                                              \
+  } while (0)
+#define FC_PROD(i, FA, FB) _Pragma("unroll") for (int j = 0; j < BJ; ++j) FC_PROD_J(i, j, FA, FB)
+
+  f4 rr[BI][BJ], ii[BI][BJ], im[BI][BJ];
+#pragma unroll
+  for (int i = 0; i < BI; ++i)
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) { rr[i][j] = f4{0, 0, 0, 0}; ii[i][j] = f4{0, 0, 0, 0}; im[i][j] = f4{0, 0, 0, 0}; }
+  int ecur = 0;
+  if (g.kb > 0)
+    ecur = (g.a_bexp ? g.a_bexp[klo / g.kb] : g.a_e) + (g.b_bexp ? g.b_bexp[klo / g.kb] : g.b_e);
+
+  // fragments: fb the B columns of the current slice (block j = 1 of the next slice arrives while
+  // the first products of that slice run), fa0 / fa1 A row blocks, one block ahead of the products
+  uint4 fa0[4], fa1[4], fb[4][BJ];
+  if (nk > 0) {
+    // slices 0 and 1 of both operands and slice 2 of A; then wait for slice 0
+    FC_DMA_A(0, 0);
+    FC_DMA_B(0, 0);
+    if (nk > 1) { FC_DMA_A(1, 1); FC_DMA_B(1, 1); }
+    if (nk > 2) {
+      FC_DMA_A(2, 2);
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(2 * QA + QB) : "memory");
+    } else if (nk > 1) {
+      asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+    }
+    _Pragma("unroll") for (int j = 0; j < BJ; ++j) FC_RD_BJ(0, j, fb);
+    FC_RD_A(0, 0, fa0);
+  }
+  int sa = 0, sb = 0;
+  for (int kt = 0; kt < nk; ++kt) {
+    const long k0 = klo + (long)TK * kt;
+    if (g.kb > 0 && kt > 0 && k0 % g.kb == 0) {
+      // FP16 operands: the sums move to the scale of the K batch that starts here (a uniform index,
+      // so the exponents come through the scalar cache and no wait touches the loads in flight)
+      typedef const __attribute__((address_space(4))) int* cint_p;   // read-only: scalar loads
+      const int b = __builtin_amdgcn_readfirstlane((int)(k0 / g.kb));
+      const int enew = (g.a_bexp ? ((cint_p)g.a_bexp)[b] : g.a_e) + (g.b_bexp ? ((cint_p)g.b_bexp)[b] : g.b_e);
+      if (enew != ecur) {
+        const float f = ldexpf(1.0f, enew - ecur);
+#pragma unroll
+        for (int i = 0; i < BI; ++i)
+#pragma unroll
+          for (int j = 0; j < BJ; ++j) { rr[i][j] *= f; ii[i][j] *= f; im[i][j] *= f; }
+        ecur = enew;
+      }
+    }
+    const int san = sa == 2 ? 0 : sa + 1, sbn = sb ^ 1;
+    FC_RD_A(sa, 1, fa1);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_PROD_J(0, 0, fa0, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    // every wave holds slice kt's B fragments: their buffer takes slice kt + 2
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 2 < nk) FC_DMA_B(kt + 2, sb);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_PROD_J(0, 1, fa0, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_RD_A(sa, 2, fa0);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_PROD(1, fa1, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_RD_A(sa, 3, fa1);
+    __builtin_amdgcn_sched_barrier(0);
+    FC_PROD(2, fa0, fb);
+    __builtin_amdgcn_sched_barrier(0);
+    // own loads of slice kt + 1 landed (those of kt + 2 may still run) and own reads of slice kt
+    // done; then every wave's: slice kt's A buffer takes slice kt + 3.  The next slice's fragments
+    // are read even after the last slice (stale LDS, unused): a read on one path only would make
+    // the compiler wait for it before the products below.
+    if (kt + 2 < nk) asm volatile("s_waitcnt vmcnt(%0) lgkmcnt(0)\n\ts_barrier" ::"n"(QA + QB) : "memory");
+    else asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    if (kt + 3 < nk) FC_DMA_A(kt + 3, sa);
+    FC_RD_A(san, 0, fa0);
+    __builtin_amdgcn_sched_barrier(0);
+    // the last row block's products, each B column block followed by the next slice's copy of it
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+      FC_PROD_J(3, j, fa1, fb);
+      __builtin_amdgcn_sched_barrier(0);
+      FC_RD_BJ(sbn, j, fb);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    sa = san;
+    sb = sbn;
+  }
+#undef FC_PROD
+#undef FC_PROD_J
+#undef FC_RD_A
+#undef FC_RD_BJ
+#undef FC_DMA_A
+#undef FC_DMA_B
+  split_epilogue<EPI, BI, BJ>(g, rr, ii, im, m0, n0, wm, wn, lane, ecur);
+}
 
 __global__ void k_split_reduce(const z* __restrict__ P, int ns, long M, long N, z* __restrict__ C, long ldc, z alpha,
                                z beta) {
@@ -507,23 +688,33 @@ __global__ void k_split_reduce(const z* __restrict__ P, int ns, long M, long N, 
     C[m * ldc + n] = out;
   }
 }
-template <int EPI, class TL>
+template <int EPI, class TL, bool DMA = false>
 void launch_split_t(int prec, dim3 grid, const SArgs& g, hipStream_t st) {
-  if (prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
-  else k_gemm_split<FC_SPLIT_FP16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+  if constexpr (DMA) {
+    if (prec == FC_SPLIT_BF16) k_gemm_split_dma<FC_SPLIT_BF16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+    else k_gemm_split_dma<FC_SPLIT_FP16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+  } else {
+    if (prec == FC_SPLIT_BF16) k_gemm_split<FC_SPLIT_BF16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+    else k_gemm_split<FC_SPLIT_FP16, EPI, TL><<<grid, TL::NT, 0, st>>>(g);
+  }
   FC_HIP(hipGetLastError());
 }
 }  // namespace
 
 // Tile of a split product: 0 = 8 waves of 64 x 32 (128 x 128), 1 = 4 waves of 64 x 64 (128 x 128),
-// 2 = 4 waves of 64 x 48 (128 x 96), 3 = 8 waves of 32 x 48 (128 x 96).  The 96-wide tiles serve
-// output widths that 96 pads much less than 128.  n = 0: the ladder assembly (any width).
-// FNSCC_SPLIT_TILE=1 selects the 4-wave tiles (a measurement switch; the 8-wave ones are faster).
-int split_tile_cfg(long n) {
-  static const int base = [] {
+// 2 = 4 waves of 64 x 48 (128 x 96), 3 = 8 waves of 32 x 48 (128 x 96), 4 = tile 0 staged by
+// direct-to-LDS loads.  The 96-wide tiles serve output widths that 96 pads much less than 128.
+// n = 0: the ladder assembly (any width).  The context's staging choice (fc_set_split_config:
+// 0 register-staged 8 waves, 1 four waves, 2 direct-to-LDS 8 waves), else FNSCC_SPLIT_TILE (the
+// same numbers), overrides the default for the 128-wide outputs.
+int split_tile_cfg(fc_ctx ctx, long n) {
+  static const int env = [] {
     const char* e = getenv("FNSCC_SPLIT_TILE");
-    return e ? (atoi(e) == 1 ? 1 : 0) : 0;
+    const int v = e ? atoi(e) : -1;
+    return v >= 0 && v < FC_SPLIT_NUM_CONFIGS ? v : -1;
   }();
+  const int pick = ctx->split_cfg >= 0 ? ctx->split_cfg : env >= 0 ? env : FC_SPLIT_DEFAULT_CONFIG;
+  const int base = pick == 1 ? 1 : pick == 2 ? 4 : 0;
   // 96-wide tiles when they pad at least 15% less than 128-wide ones (N = 276: 288 against 384)
   if (n > 96 && 100 * ((n + 95) / 96 * 96) < 85 * ((n + 127) / 128 * 128)) return base == 1 ? 2 : 3;
   return base;
@@ -531,7 +722,8 @@ int split_tile_cfg(long n) {
 long tile_tn(int cfg) { return (cfg == 2 || cfg == 3) ? 96 : 128; }
 template <int EPI>
 void launch_split(int cfg, int prec, dim3 grid, const SArgs& g, hipStream_t st) {
-  if (cfg == 1) launch_split_t<EPI, TileW4>(prec, grid, g, st);
+  if (cfg == 4) launch_split_t<EPI, TileW8, true>(prec, grid, g, st);
+  else if (cfg == 1) launch_split_t<EPI, TileW4>(prec, grid, g, st);
   else if (cfg == 2) launch_split_t<EPI, TileW4n96>(prec, grid, g, st);
   else if (cfg == 3) launch_split_t<EPI, TileW8n96>(prec, grid, g, st);
   else launch_split_t<EPI, TileW8>(prec, grid, g, st);
@@ -747,7 +939,7 @@ void gemm_split_nt(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const Spli
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = C; g.ldc = ldc; g.alpha = alpha; g.beta = beta;
   set_scales(g, A, B);
-  const int tcfg = split_tile_cfg(N);
+  const int tcfg = split_tile_cfg(ctx, N);
   const long tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.tiles = tiles;
   g.W = nullptr; g.lv = 1; g.lnB = 1; g.ltri = 0;
@@ -797,7 +989,7 @@ void gemm_split_ladder(fc_ctx ctx, const SplitOp& A, long a_row0, long M, const 
   g.M = M; g.N = N; g.kp = A.kp;
   g.C = nullptr; g.ldc = 0; g.alpha = make_double2(1, 0); g.beta = make_double2(0, 0);
   set_scales(g, A, B);
-  const int tcfg = split_tile_cfg(0);
+  const int tcfg = split_tile_cfg(ctx, 0);
   g.tiles = ((M + 127) / 128) * ((N + tile_tn(tcfg) - 1) / tile_tn(tcfg));
   g.kchunk = A.kp;
   g.part = nullptr;

@@ -5,6 +5,11 @@
 
 namespace fc {
 
+// staging choices of the 128-wide split tiles (fc_set_split_config): 0 register-staged 8 waves,
+// 1 four waves, 2 direct-to-LDS 8 waves
+constexpr int FC_SPLIT_NUM_CONFIGS = 3;
+constexpr int FC_SPLIT_DEFAULT_CONFIG = 2;
+
 struct SplitOp {
   DBuf buf;            // planes re_hi, re_lo, im_hi, im_lo, each [rows_pad][kp] (16-bit)
   long rows = 0, rows_pad = 0, kp = 0;

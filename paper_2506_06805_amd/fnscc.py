@@ -52,6 +52,8 @@ _sig = {
     "fc_set_autotune": (C.c_int, [P, C.c_int]),
     "fc_set_gemm_config": (C.c_int, [P, C.c_int]),
     "fc_gemm_num_configs": (C.c_int, []),
+    "fc_set_split_config": (C.c_int, [P, C.c_int]),
+    "fc_split_num_configs": (C.c_int, []),
     "fc_autotune_save": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_load": (C.c_int, [P, C.c_char_p]),
     "fc_autotune_size": (C.c_int, [P]),
@@ -234,6 +236,15 @@ class Context:
     @staticmethod
     def gemm_num_configs():
         return int(lib.fc_gemm_num_configs())
+
+    def set_split_config(self, cfg):
+        """Force the staging of the 128-wide split-precision tiles (0 registers, 1 four waves,
+        2 direct-to-LDS; -1: default)."""
+        self.check(lib.fc_set_split_config(self.h, int(cfg)), "fc_set_split_config")
+
+    @staticmethod
+    def split_num_configs():
+        return int(lib.fc_split_num_configs())
 
     def take_timings(self):
         buf = C.create_string_buffer(1 << 16)

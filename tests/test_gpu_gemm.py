@@ -168,3 +168,33 @@ def test_fp16_split_scales_each_k_batch(gpu_ctx):
         assert err < 8 * 2.0 ** -22, err
     # the blocks that share no nonzero column are exactly zero
     assert not C[:M // 2, N // 2:].any() and not C[M // 2:, :N // 2].any()
+
+
+@pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 64), (256, 384, 96), (140, 200, 3000), (260, 270, 520)])
+def test_split_direct_to_lds_tile(M, N, K):
+    # the split product staged straight into LDS (three A buffers, two B buffers; K slices 1, 2, 3
+    # and many, ragged tiles, split-K on the long contraction) against the register-staged tile: the
+    # same MFMAs per accumulator in the same order, so the same bits; FP16 with its per-K-batch
+    # scales crossing batch boundaries
+    import torch
+    from paper_2506_06805_amd import fnscc
+    rng = np.random.default_rng(M + N + K)
+    A, B = _rand((M, K), rng), _rand((N, K), rng)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = A @ B.T
+    scale = np.abs(A) @ np.abs(B).T
+    ctx = fnscc.Context(0)
+    try:
+        assert fnscc.Context.split_num_configs() == 3
+        for prec, unit in (("split-bf16", 2.0 ** -16), ("split-fp16", 2.0 ** -22)):
+            out = {}
+            for cfg in (0, 2):
+                ctx.set_split_config(cfg)
+                out[cfg] = fnscc.zgemm(ctx, "N", "T", dA, dB, precision=prec).cpu().numpy()
+            assert np.array_equal(out[0], out[2]), prec
+            assert (np.abs(out[2] - ref) / scale).max() < 8 * unit, prec
+        ctx.set_split_config(-1)
+        with pytest.raises(fnscc.FcError):
+            ctx.set_split_config(3)
+    finally:
+        ctx.close()

@@ -104,3 +104,28 @@ def test_autotune_keeps_results_and_roundtrips(gpu_ctx, tmp_path):
         ctx2.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [0, 2])
+def test_split_ladder_staging(cfg):
+    # the split ladder's assembly (ladder-layout epilogue, triangular launches) and contraction with
+    # the 128-wide tiles staged through registers (0) or straight into LDS (2): the same bits, and
+    # within the split's bound of the oracle ladder
+    from paper_2506_06805_amd import fnscc
+    o, v, N = 6, 70, 200
+    inst = synth.make_instance(o, v, N, seed=77, kappa=0.6)
+    tau = _tau(o, v, 6)
+    ref = _ladder_ref(inst, tau)
+    ctxs = [fnscc.Context(0), fnscc.Context(0)]
+    try:
+        ctxs[1].set_split_config(cfg)
+        for prec, tol in (("split-bf16", 2e-4), ("split-fp16", 2e-6)):
+            R = []
+            for ctx in ctxs:
+                ints = fnscc.cd_integrals(ctx, inst.eps, inst.L, o)
+                R.append(fnscc.ladder(ctx, ints, _dev(tau), precision=prec).cpu().numpy())
+            assert np.abs(R[1] - ref).max() / np.abs(ref).max() < tol, prec
+            assert np.array_equal(R[0], R[1]), prec
+    finally:
+        for ctx in ctxs:
+            ctx.close()
