@@ -31,7 +31,7 @@ PEAK = {"fp64": 78.6, "split-bf16": 2516.6, "split-fp16": 2516.6}   # TFLOP/s, M
 # (from its first fill on) and scaled by what each counter reads for a 1 GiB device copy (FETCH
 # x2.0, WRITE x1.0): FP64 33.13 GB fetched + 9.09 GB written; split-BF16 16.70 + 5.00 GB.  Only
 # for the kernels and workload they were measured on.
-LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.89e9, ("o24v160n500", "split-bf16"): 21.57e9}
+LADDER_TRAFFIC_BYTES = {("o24v160n500", "fp64"): 41.90e9, ("o24v160n500", "split-bf16"): 21.59e9}
 TRAFFIC_SOURCE = ("profile constant, not counted in this run: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
                   "summed over the ladder kernels of the same kernel version and workload "
                   "(profiles/ladder_o24v160n500.md), each scaled by its reading for a 1 GiB copy")

@@ -7,6 +7,9 @@ bytes (a copy of S bytes must read S and write S bytes).
 `python -m paper_2506_06805_amd.profiling gemm` times the library's complex GEMM on the shapes the
 hot path uses, next to torch's complex128 matmul.
 
+`python -m paper_2506_06805_amd.profiling split-gemm` times the hi/lo split products (BF16 and FP16)
+with the 128-wide tiles staged through registers and straight into LDS.
+
 `python -m paper_2506_06805_amd.profiling fns-presets` runs the paper's frozen-natural-spinor presets
 against the untruncated solve on the FNS-structured generator.
 
@@ -47,10 +50,13 @@ GEMM_SHAPES = [("square4096", 4096, 4096, 4096, "N", "N"), ("assembly_T64", 1024
                ("fae_o24v160", 160, 160, 92160, "N", "N")]
 
 
-def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1) -> None:
+def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1, shapes: str = "",
+               fp64_only: bool = False) -> None:
     """TFLOP/s of the library's complex GEMM (FP64 and FP32 arithmetic) on the listed shapes, next
     to torch's complex128 matmul on the same operands (a vendor-library reference point).  With
-    `tune` the library's autotuner times every tile configuration first and keeps the fastest."""
+    `tune` the library's autotuner times every tile configuration first and keeps the fastest.
+    `shapes` (comma-separated names) restricts the shapes; `fp64_only` times the FP64 products
+    alone (a clean program for counter runs)."""
     import torch
 
     from . import fnscc
@@ -72,7 +78,10 @@ def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1) -> 
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    keep = set(shapes.split(",")) if shapes else None
     for name, M, N, K, oa, ob in GEMM_SHAPES:
+        if keep is not None and name not in keep:
+            continue
         A = torch.randn(M, K, dtype=torch.complex128, device="cuda")
         B = torch.randn(K, N, dtype=torch.complex128, device="cuda") if ob == "N" else \
             torch.randn(N, K, dtype=torch.complex128, device="cuda")
@@ -81,8 +90,9 @@ def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1) -> 
         fl = 8.0 * M * N * K
         res = {"shape": name, "M": M, "N": N, "K": K}
         res["fp64_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C)) / 1e9
-        res["fp32_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C, fp32=True)) / 1e9
-        res["torch_complex128_tflops"] = fl / timed(lambda: torch.matmul(A, Bn, out=C)) / 1e9
+        if not fp64_only:
+            res["fp32_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C, fp32=True)) / 1e9
+            res["torch_complex128_tflops"] = fl / timed(lambda: torch.matmul(A, Bn, out=C)) / 1e9
         print(json.dumps({k: (round(x, 1) if isinstance(x, float) else x) for k, x in res.items()}), flush=True)
         del A, B, C, Bn
     if tune and save:
@@ -91,6 +101,41 @@ def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1) -> 
 
 # The paper's thresholds (Sec. 4.1): natural-spinor occupation and Cholesky threshold per preset.
 FNS_PRESETS = [("LOOSE", 1e-4, 1e-3), ("NORMAL", 10 ** -4.5, 1e-4), ("TIGHT", 1e-5, 1e-5)]
+
+
+def split_gemm_probe(reps: int) -> None:
+    """C = A B^T on complex128 operands through the split precisions: the whole call (splitting
+    both operands into hi/lo planes, the product, the FP64 output), timed with hipEvents on the
+    current stream, for each staging of the 128-wide tiles (0 registers, 2 direct-to-LDS)."""
+    import torch
+
+    from . import fnscc
+    ctx = fnscc.Context(0)
+    shapes = [("assembly_T64", 10240, 10240, 512), ("square4096", 4096, 4096, 4096),
+              ("contraction_o40", 8000, 780, 20000), ("contraction_o24", 12720, 276, 12720)]
+    for name, m, n, k in shapes:
+        A = torch.randn(m, k, dtype=torch.complex128, device="cuda")
+        B = torch.randn(n, k, dtype=torch.complex128, device="cuda")
+        C = torch.empty(m, n, dtype=torch.complex128, device="cuda")
+        row = {"shape": name, "M": m, "N": n, "K": k}
+        for prec in ("split-bf16", "split-fp16"):
+            for cfg in (0, 2):
+                ctx.set_split_config(cfg)
+                fnscc.zgemm(ctx, "N", "T", A, B, C=C, precision=prec)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fnscc.zgemm(ctx, "N", "T", A, B, C=C, precision=prec)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                row[f"{prec}_cfg{cfg}_ms"] = round(ms, 3)
+                row[f"{prec}_cfg{cfg}_tflops"] = round(8.0 * m * n * k / (ms * 1e-3) / 1e12, 1)
+        print(json.dumps(row), flush=True)
+        del A, B, C
+    ctx.set_split_config(-1)
+    ctx.close()
 
 
 def fns_presets(o: int, v: int, ncd: int, gamma: float, roots: int, seed: int) -> None:
@@ -309,6 +354,10 @@ def main() -> None:
     g.add_argument("--tune", action="store_true")
     g.add_argument("--save", type=str, default="", help="with --tune: write the tuned table to this file")
     g.add_argument("--cfg", type=int, default=-1, help="force this tile configuration where it fits")
+    g.add_argument("--shapes", type=str, default="", help="comma-separated shape names (default: all)")
+    g.add_argument("--fp64-only", action="store_true", help="time the FP64 products alone")
+    sg = sub.add_parser("split-gemm")
+    sg.add_argument("--reps", type=int, default=5)
     f = sub.add_parser("fns-presets")
     f.add_argument("--o", type=int, default=24)
     f.add_argument("--v", type=int, default=300)
@@ -340,7 +389,9 @@ def main() -> None:
     if args.cmd == "copy":
         copy_probe(args.mib)
     elif args.cmd == "gemm":
-        gemm_probe(args.reps, args.tune, args.save, args.cfg)
+        gemm_probe(args.reps, args.tune, args.save, args.cfg, args.shapes, args.fp64_only)
+    elif args.cmd == "split-gemm":
+        split_gemm_probe(args.reps)
     elif args.cmd == "fns-presets":
         fns_presets(args.o, args.v, args.ncd, args.gamma, args.roots, args.seed)
     elif args.cmd == "sigma":
