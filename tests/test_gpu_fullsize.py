@@ -132,3 +132,34 @@ def test_left_vectors_full_size(gpu_ctx, c2, hbar):
     P = rng.standard_normal((3, Rh.shape[1])) + 1j * rng.standard_normal((3, Rh.shape[1]))
     proj = Lh @ eom.sigma(hbar, P).T - w_l[:, None] * (Lh @ P.T)
     assert (np.abs(proj) / np.linalg.norm(Lh, axis=1)[:, None]).max() < 1e-6
+
+
+
+@pytest.mark.parametrize("prec,tol", [("split-bf16", 2e-4), ("split-fp16", 2e-6)])
+def test_split_ladder_staging_full_size(c2, prec, tol):
+    # the benchmark's split ladder (converged amplitudes, T1 dressing) with its 128-wide tiles
+    # staged through registers (0) and straight into LDS (2, the default): the same bits at full
+    # size, and the oracle's sampled rows within the split's bound
+    import torch
+    from paper_2506_06805_amd import fnscc
+    t1, t2 = c2["t1"], c2["t2"]
+    _, tau = ccsd.taus(t1, t2)
+    tau_d, t1_d = torch.from_numpy(tau).cuda(), torch.from_numpy(t1).cuda()
+    R = {}
+    for cfg in (0, 2):
+        ctx = fnscc.Context(0)
+        try:
+            ctx.set_split_config(cfg)
+            ints = fnscc.cd_integrals(ctx, c2["inst"].eps, c2["L"], c2["inst"].o)
+            R[cfg] = fnscc.ladder(ctx, ints, tau_d, t1_d, precision=prec).cpu().numpy()
+        finally:
+            ctx.close()
+    assert np.array_equal(R[0], R[2])
+    g = c2["g"]
+    o = t1.shape[0]
+    Lv = g.L[:, o:, o:] - np.einsum("ma,Pme->Pae", t1, g.L[:, :o, o:], optimize=True)
+    for a in ROWS:
+        x = np.einsum("Pe,Pbf->bef", Lv[:, a, :], Lv, optimize=True)
+        ref = 0.5 * np.einsum("ijef,bef->ijb", tau, x - x.transpose(0, 2, 1), optimize=True)
+        err = np.abs(R[2][:, :, a, :] - ref).max() / np.abs(ref).max()
+        assert err < tol, (a, err)
