@@ -519,7 +519,8 @@ __global__ __launch_bounds__(TL::NT) void k_gemm_split(SArgs g) {
 // workgroup barrier waits for the slowest of its waves.  Here the loads bypass the registers and
 // run further ahead: A rotates through three LDS buffers (slice k + 3 is requested at the end of
 // slice k, into the buffer slice k has just left), B through two (slice k + 2 is requested once
-// every wave holds slice k's B fragments in registers, a quarter of a slice in).  LDS: 3 x 32 KiB
+// every wave holds slice k's B fragments in registers, after the slice's first twelve of its 96
+// products per wave).  LDS: 3 x 32 KiB
 // of A + 2 x 32 KiB of B = 160 KiB.  The layout in LDS is the register-staged kernel's (rows of
 // 32 elements, 16-byte chunks XOR-swizzled by swz(row)): a 1 KiB run is 16 rows of one plane, lane
 // l fetching row l / 4 and the chunk that belongs at position l % 4.  Fragments: B's of a whole
