@@ -913,6 +913,48 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm(const char* __res
   }
 }
 
+// The same persistent walk over the plan's tiles on the 128 x 64 direct-to-LDS tile with Gauss's
+// three real products (8 waves, one workgroup per CU).  The tile ends without a barrier after its
+// last LDS reads, so one is taken before the next tile's loads reuse the buffers.
+template <int BM, int BN, int WGM, int WGN, int BK>
+__global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm_dma(const char* __restrict__ plan) {
+  __shared__ DmaSmem<BM, BN, BK> sm;
+  const GroupHeader* h = reinterpret_cast<const GroupHeader*>(plan);
+  const GroupDesc* d = reinterpret_cast<const GroupDesc*>(plan + PLAN_HDR);
+  const long total = h->total_tiles, np = h->nprob;
+  const long span = (total + 7) / 8 * 8;
+  bool first = true;
+  for (long vt = blockIdx.x; vt < span; vt += gridDim.x) {
+    const long t = xcd_tile(vt, total);
+    if (t >= total) continue;
+    const GroupDesc g = d[group_find<&GroupDesc::tile0>(d, np, t)];
+    const long loc = t - g.tile0;
+    const long tt = loc % g.tiles, r = loc / g.tiles;
+    const long b = r % g.batch, s = r / g.batch;
+    TileJob j;
+    j.M = g.M; j.N = g.N;
+    j.A = g.A + b * g.sA; j.lda = g.lda;
+    j.B = g.B + b * g.sB; j.ldb = g.ldb;
+    j.C = g.C + b * g.sC; j.ldc = g.ldc;
+    j.alpha = g.alpha; j.beta = g.beta;
+    j.conjA = g.conjA; j.conjB = g.conjB;
+    j.m0 = (tt / g.tn) * BM; j.n0 = (tt % g.tn) * BN;
+    j.klo = s * g.kchunk;
+    j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
+    j.part = g.ksplit > 1 ? g.part + (s * g.batch + b) * g.M * g.N : nullptr;
+    j.lv = 1; j.lnB = 1;
+    if (!first) __syncthreads();   // every wave has left the previous tile's buffers
+    first = false;
+    if (g.ta) {
+      if (g.tb) gemm_tile_dma<BM, BN, WGM, WGN, BK, true, true, 0, true, double>(j, sm);
+      else gemm_tile_dma<BM, BN, WGM, WGN, BK, true, false, 0, true, double>(j, sm);
+    } else {
+      if (g.tb) gemm_tile_dma<BM, BN, WGM, WGN, BK, false, true, 0, true, double>(j, sm);
+      else gemm_tile_dma<BM, BN, WGM, WGN, BK, false, false, 0, true, double>(j, sm);
+    }
+  }
+}
+
 // C = alpha * sum_s part[s] + beta * C for every split product of the plan, in split order.
 __global__ void k_group_reduce(const char* __restrict__ plan) {
   const GroupHeader* h = reinterpret_cast<const GroupHeader*>(plan);
@@ -939,8 +981,10 @@ __global__ void k_group_reduce(const char* __restrict__ plan) {
 }
 }  // namespace
 
-constexpr int GROUP_NCFG = 2;
-constexpr long GROUP_BM[GROUP_NCFG] = {64, 128}, GROUP_BN[GROUP_NCFG] = {64, 64};
+// grouped tiles: 0 = 64 x 64 and 1 = 128 x 64 register-staged (four products), 2 = 128 x 64
+// direct-to-LDS with three products
+constexpr int GROUP_NCFG = 3;
+constexpr long GROUP_BM[GROUP_NCFG] = {64, 128, 128}, GROUP_BN[GROUP_NCFG] = {64, 64, 64};
 
 GroupCounts group_encode(const std::vector<GroupGemm>& probs, const GroupTiling& tl, void* host_plan,
                          size_t plan_cap, z* work, size_t work_cap) {
@@ -1009,8 +1053,15 @@ void group_launch(fc_ctx ctx, int cfg, const void* dplan, long max_tiles, long m
   const char* p = static_cast<const char*>(dplan);
   // persistent grid: at most 4 workgroups per CU of 256 CUs, a multiple of 8
   const long g1 = std::max(8L, std::min(1024L, (max_tiles + 7) / 8 * 8));
-  if (cfg == 1) k_group_gemm<128, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
-  else k_group_gemm<64, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  if (cfg == 2) {
+    // 144 KB of LDS: one workgroup per CU
+    const long gd = std::max(8L, std::min(256L, (max_tiles + 7) / 8 * 8));
+    k_group_gemm_dma<128, 64, 4, 2, 16><<<(unsigned)gd, 512, 0, ctx->stream>>>(p);
+  } else if (cfg == 1) {
+    k_group_gemm<128, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  } else {
+    k_group_gemm<64, 64, 2, 2, 8><<<(unsigned)g1, 256, 0, ctx->stream>>>(p);
+  }
   FC_HIP(hipGetLastError());
   if (max_elems > 0) {
     const long g2 = std::max(1L, std::min(2048L, (max_elems + 255) / 256));

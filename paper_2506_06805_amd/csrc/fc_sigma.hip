@@ -432,7 +432,7 @@ void SigmaBatch::tune(const z* const* R, z* const* S, const long* nvec) {
   FC_HIP(hipEventCreate(&e1));
   float best = 1e30f;
   int bestc = (0 << 5) | 9;
-  for (int cfg = 0; cfg < 2; ++cfg)
+  for (int cfg = 0; cfg < 3; ++cfg)
     for (int lg = 8; lg <= 11; ++lg) {
       configure(GroupTiling{cfg, 1L << lg}, GroupTiling{cfg, 512});
       float ms = 0.f;
@@ -455,8 +455,24 @@ void SigmaBatch::tune(const z* const* R, z* const* S, const long* nvec) {
 void SigmaBatch::run(const z* const* R, z* const* S, const long* nvec) {
   StageTimer st(ctx_, "sigma");
   if (!configured_) {
-    if (ctx_->autotune) tune(R, S, nvec);
-    else configure(GroupTiling{0, 512}, GroupTiling{0, 512});
+    if (ctx_->autotune) {
+      tune(R, S, nvec);
+    } else {
+      // grouped tile configuration of both launches: FNSCC_SIGMA_CFG (0, 1, 2; a measurement
+      // switch), else by size
+      static const int env = [] {
+        const char* e = getenv("FNSCC_SIGMA_CFG");
+        const int c = e ? atoi(e) : -1;
+        return c >= 0 && c <= 2 ? c : -1;
+      }();
+      // default: the direct-to-LDS three-product tile once the ring product k o x o v x o v has at
+      // least three 128-row tiles (measured at o = 24, v = 160: k = 16 1.37 -> 1.31 ms, k = 32
+      // 2.37 -> 2.07 ms per sigma; k = 8 0.83 -> 0.93 ms, so smaller blocks keep the 64 x 64 tile)
+      long rows = 0;
+      for (int b = 0; b < nb_; ++b) rows = std::max(rows, kmax_[b] * I_[b]->o);
+      const int cfg = env >= 0 ? env : rows >= 384 ? 2 : 0;
+      configure(GroupTiling{cfg, 512}, GroupTiling{cfg, 512});
+    }
   }
   upload(R, S, nvec);
   if (!graph_) {

@@ -83,6 +83,23 @@ def test_sigma_parity_random_t(gpu_ctx, o, v, N):
     assert _rel(S, ref) < TOL_TERM
 
 
+def test_sigma_parity_large_block(gpu_ctx):
+    # 40 trial vectors at o = 12: the ring product has k o = 480 rows, so both grouped launches run
+    # on the direct-to-LDS three-product tile; right and left products against the oracle
+    from paper_2506_06805_amd import fnscc
+    o, v, N, k = 12, 24, 60, 40
+    inst = synth.make_instance(o, v, N, seed=83, kappa=0.6)
+    ints = fnscc.cd_integrals(gpu_ctx, inst.eps, inst.L, o)
+    t1, t2 = _rand_amps(o, v, 8)
+    amps = fnscc.amps_create(gpu_ctx, ints, _dev(t1), _dev(t2))
+    h = eom.Hbar(integrals.Blocks(inst.L, o), inst.eps, t1, t2)
+    rng = np.random.default_rng(10)
+    dim = eom.dim(o, v)
+    R = rng.standard_normal((k, dim)) + 1j * rng.standard_normal((k, dim))
+    assert _rel(_host(fnscc.ipeom_sigma(gpu_ctx, ints, amps, _dev(R))), eom.sigma(h, R)) < TOL_TERM
+    assert _rel(_host(fnscc.ipeom_sigma_left(gpu_ctx, ints, amps, _dev(R))), eom.sigma_left(h, R)) < TOL_TERM
+
+
 def test_solve_parity_small(gpu_ctx):
     from paper_2506_06805_amd import fnscc
     o, v, N, k = 6, 20, 60, 4
