@@ -170,7 +170,8 @@ def test_fp16_split_scales_each_k_batch(gpu_ctx):
     assert not C[:M // 2, N // 2:].any() and not C[M // 2:, :N // 2].any()
 
 
-@pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 64), (256, 384, 96), (140, 200, 3000), (260, 270, 520)])
+@pytest.mark.parametrize("M,N,K", [(96, 100, 20), (300, 257, 37), (129, 130, 64), (256, 384, 96), (140, 200, 3000),
+                                   (260, 270, 520)])
 def test_split_direct_to_lds_tile(M, N, K):
     # the split product staged straight into LDS (three A buffers, two B buffers; K slices 1, 2, 3
     # and many, ragged tiles, split-K on the long contraction) against the register-staged tile: the
