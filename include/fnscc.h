@@ -127,12 +127,15 @@ int fns_truncate(fc_ctx ctx, fc_ints in, double occ_thresh, fc_ints* out, int* v
                  void* U);
 
 /* Learned T2 update network (4 -> 64 -> 64 -> 2, tanh). Not part of the paper's method: a
- * per-amplitude gain g with t_ij^ab += (Omega_ij^ab / D_ij^ab)(1 + g), features built from the
- * dressed diagonal u = (F_aa + F_bb - F_ii - F_jj) / D and the residual ratio
+ * per-amplitude gain g with t_ij^ab += q_ij^ab (1 + g), q the dressed Jacobi step
+ * Omega / (D - (F_aa + F_bb - F_ii - F_jj)) (Omega / D where the dressing would bring the
+ * denominator below half of D; the learned step keeps this base whatever precond says), features
+ * built from the dressed diagonal u = (F_aa + F_bb - F_ii - F_jj) / D and the residual ratio
  * rho = Omega_k / Omega_{k-1} of the amplitude; Omega = 0 gives a zero step. */
 typedef struct fc_mlp_s* fc_mlp;
 
-/* Options of ccsd_solve. Jacobi update t += Omega/D with complex DIIS (FP64) over the last
+/* Options of ccsd_solve. Jacobi update t += Omega/D (D dressed or bare, see precond) with complex
+ * DIIS (FP64) over the last
  * diis_dim iterates (default 10, at most 16; <= 1 turns DIIS off). Converged when
  * |dE| < e_tol and RMS(Omega over unique amplitudes) < r_tol; e_tol, r_tol <= 0 (the defaults)
  * select 1e-10 and 1e-9 for FC_FP64 and 1e-8 and 1e-7 for the split precisions, whose product
@@ -261,7 +264,7 @@ int ipeom_left(fc_ctx ctx, int nb, const fc_ints* ints, const fc_amps* t, const 
 /* Learned update network. Parameters: one FP32 vector W1 (64x4), b1, W2 (64x64), b2, W3 (2x64),
  * b3 (fc_mlp_num_params() entries). fc_mlp_create: params_host (host) or NULL for a seeded
  * initialisation. Training minimises sum_s |r_s - q_s g_s|^2 / sum_s |q_s|^2 over a minibatch of
- * B samples: X (device, B x 4 FP32 features), q (device, B complex64: Jacobi step Omega/D),
+ * B samples: X (device, B x 4 FP32 features), q (device, B complex64: the dressed Jacobi step),
  * r (device, B complex64: (t* - t) - q); fc_mlp_train_step does one Adam step (lr > 0) on FP32
  * master weights and refreshes the BF16 copy used by the solver; fc_mlp_grad returns the
  * gradient (host, FP32) without updating; fc_mlp_forward evaluates Y (device, B x 2) with the FP32
@@ -274,10 +277,11 @@ int fc_mlp_grad(fc_mlp mlp, const float* X, const float* q, const float* r, long
 int fc_mlp_train_step(fc_mlp mlp, const float* X, const float* q, const float* r, long B, float lr, float* loss);
 int fc_mlp_forward(fc_mlp mlp, const float* X, long B, float* Y, int bf16_weights);
 /* fc_learned_step - one learned amplitude update as the solver applies it (test and measurement
- * helper): t1_out = t1 + r1 / D1 (Jacobi); for every i < j, a < b, with the features above built
- * from fdiag and the residual ratio r2 / r2prev (r2prev NULL: ratio 0) and g the network output
- * with BF16-rounded weights, t2_out_ij^ab = t2_ij^ab + (r2_ij^ab / D_ij^ab)(1 + g), written to all
- * four antisymmetric images, and zero where i == j or a == b.  t1, r1, t1_out: device o x v;
+ * helper): t1_out = t1 + q1 (the dressed Jacobi step of the singles); for every i < j, a < b, with
+ * the features above built from fdiag and the residual ratio r2 / r2prev (r2prev NULL: ratio 0)
+ * and g the network output with BF16-rounded weights, t2_out_ij^ab = t2_ij^ab + q (1 + g) with q
+ * the dressed Jacobi step of the amplitude, written to all four antisymmetric images, and zero
+ * where i == j or a == b.  t1, r1, t1_out: device o x v;
  * t2, r2, r2prev, t2_out: device o x o x v x v; fdiag: device o + v complex128 (F_mi then F_ae
  * diagonals).  All complex128. */
 int fc_learned_step(fc_ctx ctx, fc_ints ints, fc_mlp mlp, const void* t1, const void* t2, const void* r1,

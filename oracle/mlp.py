@@ -2,8 +2,8 @@
 
 The paper has no learned component; this is the reference for the library's own network:
 inputs x (n_in features per amplitude) -> h1 = tanh(W1 x + b1) -> h2 = tanh(W2 h1 + b2) ->
-y = W3 h2 + b3, y = (Re g, Im g).  For a sample with Jacobi step q = Omega/D and target
-correction r = (t* - t) - q, the loss of a minibatch is
+y = W3 h2 + b3, y = (Re g, Im g).  For a sample with Jacobi step q (the step the gain
+multiplies) and target correction r = (t* - t) - q, the loss of a minibatch is
     loss = sum_s |r_s - q_s g_s|^2 / sum_s |q_s|^2 .
 Parameters are one flat vector in the order W1 (n_h x n_in, row-major), b1, W2 (n_h x n_h), b2,
 W3 (n_out x n_h), b3.  Gradients here come from central finite differences of `loss`, so they

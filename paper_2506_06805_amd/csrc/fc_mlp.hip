@@ -172,6 +172,16 @@ __device__ inline unsigned long long mix64(unsigned long long x) {  // splitmix6
   return x ^ (x >> 31);
 }
 
+// r / (d - df), the solver's dressed Jacobi step (the residual's one-particle diagonals df taken
+// off the orbital-energy difference d; the bare r / d where the dressing would bring the
+// denominator below half the bare one's size)
+__device__ inline z dressed_step(z r, double d, z df) {
+  const double dr = d - df.x, di = -df.y;
+  const double n2 = dr * dr + di * di;
+  if (!(n2 >= 0.25 * d * d)) return make_double2(r.x / d, r.y / d);
+  return make_double2((r.x * dr + r.y * di) / n2, (r.y * dr - r.x * di) / n2);
+}
+
 // samples: unique amplitude (i<j, a<b) chosen by a counter-based hash of (seed, k)
 __global__ void k_samples(const z* __restrict__ t2, const z* __restrict__ r2, const z* __restrict__ r2prev,
                           const z* __restrict__ t2s,
@@ -189,7 +199,8 @@ __global__ void k_samples(const z* __restrict__ t2, const z* __restrict__ r2, co
     const double fr = fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x;
     const double fi = fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y;
     features(D, fr, fi, r2, r2prev, idx, X + k * NIN);
-    const double qr = r2[idx].x / D, qi = r2[idx].y / D;
+    const z qd = dressed_step(r2[idx], D, make_double2(fr, fi));
+    const double qr = qd.x, qi = qd.y;
     q[2 * k] = (float)qr;
     q[2 * k + 1] = (float)qi;
     r[2 * k] = (float)(t2s[idx].x - t2[idx].x - qr);
@@ -210,9 +221,10 @@ __device__ inline void pair_of_index(long p, long n, long& i, long& j) {
   j = i + 1 + (p - (i * n - i * (i + 1) / 2));
 }
 
-// t2_new = t2 + (r2 / D)(1 + g(x)) for every unique amplitude (i < j, a < b), written to its four
-// antisymmetric images, with the BF16-rounded weights; the 64 x 64 hidden layer runs on the BF16
-// matrix cores with FP32 accumulation (h1 rounded to BF16), the rest in FP32.  Each wave takes 64
+// t2_new = t2 + q (1 + g(x)), q the dressed Jacobi step, for every unique amplitude (i < j, a < b),
+// written to its four antisymmetric images, with the BF16-rounded weights; the 64 x 64 hidden
+// layer runs on the BF16 matrix cores with FP32 accumulation (h1 rounded to BF16), the rest in
+// FP32.  Each wave takes 64
 // unique amplitudes (one per lane), forms the features and the first hidden layer per lane,
 // stages h1 as a 64 x 64 block in LDS, and multiplies it by W2^T with v_mfma_f32_16x16x32_bf16
 // (4 x 4 output blocks, K = 64 in 2 steps; W2 fragments stay in registers for the whole kernel).
@@ -256,6 +268,7 @@ __global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __rest
     const bool valid = u < nu;
     long i = 0, j = 1, a = 0, b = 1, x = 0;
     double D = 1.0;
+    z df = make_double2(0.0, 0.0);
     float xin[NIN] = {0.f, 0.f, 0.f, 0.f};
     if (valid) {
       pair_of_index(u / nv, o, i, j);
@@ -264,6 +277,7 @@ __global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __rest
       D = eps[i] + eps[j] - eps[o + a] - eps[o + b];
       const double fr = fd[o + a].x + fd[o + b].x - fd[i].x - fd[j].x;
       const double fi = fd[o + a].y + fd[o + b].y - fd[i].y - fd[j].y;
+      df = make_double2(fr, fi);
       features(D, fr, fi, r2, r2prev, x, xin);
     }
 #pragma unroll
@@ -332,7 +346,8 @@ __global__ __launch_bounds__(64 * LW) void k_learned_t2_mfma(const float* __rest
     __syncthreads();
     if (valid) {
       const float g0 = H[2 * lane] + b30, g1 = H[2 * lane + 1] + b31;
-      const double qr = r2[x].x / D, qi = r2[x].y / D;
+      const z qd = dressed_step(r2[x], D, df);
+      const double qr = qd.x, qi = qd.y;
       const double gr = 1.0 + (double)g0, gi = (double)g1;
       const z n = make_double2(t2[x].x + qr * gr - qi * gi, t2[x].y + qr * gi + qi * gr);
       const z mneg = make_double2(-n.x, -n.y);
@@ -359,11 +374,11 @@ __global__ void k_zero_diagonals(z* out, long o, long v) {
     out[x] = make_double2(0.0, 0.0);
   }
 }
-__global__ void k_jacobi_t1(const z* t, const z* r, z* out, const double* eps, long o, long v) {
+__global__ void k_jacobi_t1(const z* t, const z* r, z* out, const double* eps, const z* fd, long o, long v) {
   GRID_STRIDE(x, o * v) {
     const long a = x % v, i = x / v;
-    const double d = eps[i] - eps[o + a];
-    out[x] = make_double2(t[x].x + r[x].x / d, t[x].y + r[x].y / d);
+    const z q = dressed_step(r[x], eps[i] - eps[o + a], make_double2(fd[o + a].x - fd[i].x, fd[o + a].y - fd[i].y));
+    out[x] = make_double2(t[x].x + q.x, t[x].y + q.y);
   }
 }
 inline unsigned nblk(long n) { return (unsigned)std::max(1L, std::min(1048576L, (n + TPB - 1) / TPB)); }
@@ -378,7 +393,7 @@ int learned_step(fc_ctx ctx, fc_ints I, const void* mlpv, const z* t1, const z* 
   fc_mlp m = (fc_mlp)mlpv;
   check_mlp(m);
   const long o = I->o, v = I->v;
-  k_jacobi_t1<<<nblk(o * v), TPB, 0, ctx->stream>>>(t1, r1, o1, I->eps_d.as<double>(), o, v);
+  k_jacobi_t1<<<nblk(o * v), TPB, 0, ctx->stream>>>(t1, r1, o1, I->eps_d.as<double>(), fd, o, v);
   k_zero_diagonals<<<nblk(o * v * v + o * o * v), TPB, 0, ctx->stream>>>(o2, o, v);
   const long nu = (o * (o - 1) / 2) * (v * (v - 1) / 2);
   if (nu > 0) {

@@ -3,9 +3,9 @@ sampling, forward, backward and Adam all run in the HIP library).
 
 collect(): for each instance, a plain Jacobi + DIIS solve gives the converged doubles t*; the same
 deterministic solve is repeated and, at every iterate t_k, `per_iter` amplitudes are sampled with
-their features (which use the previous iterate's residual), Jacobi step q = Omega/D and target
-correction r = (t* - t_k) - q.  Samples that are not finite or whose step exceeds `qmax` are
-dropped.
+their features (which use the previous iterate's residual), the dressed Jacobi step
+q = Omega / (D - (F_aa + F_bb - F_ii - F_jj)) and target correction r = (t* - t_k) - q.  Samples
+that are not finite or whose step exceeds `qmax` are dropped.
 train(): Adam on minibatches of those samples.
 """
 from __future__ import annotations
