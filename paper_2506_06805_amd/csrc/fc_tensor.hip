@@ -205,16 +205,84 @@ __global__ void __launch_bounds__(TT * TR) k_permute_tiled(const z* __restrict__
   }
 }
 
-// r[i,j,a,b] += alpha * P(..) x
-__global__ void k_antisym_add(z* __restrict__ r, const z* __restrict__ x, long o, long v, int mode, z alpha) {
-  const long n = o * o * v * v;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    long b = t % v, a = (t / v) % v, j = (t / (v * v)) % o, i = t / (v * v * o);
-    z val = x[t];
-    if (mode & 1) val = csub(val, x[((i * o + j) * v + b) * v + a]);
-    if (mode & 2) val = csub(val, x[((j * o + i) * v + a) * v + b]);
-    if (mode == 3) val = cadd(val, x[((j * o + i) * v + b) * v + a]);
-    r[t] = cadd(r[t], cmul(alpha, val));
+// r[i,j,a,b] += alpha * P(..) x over 16 x 16 (a, b) tiles, each element of x read once: val (the antisymmetrised
+// x of the mode) is antisymmetric in the swapped index pairs, so one workgroup forms it for a tile
+// and adds it, with the sign of each image, to every image of the tile -- the (a, b)-transposed
+// images through LDS, so that reads and writes stay coalesced.  Images are negations of the same
+// floating-point value, so the update is exactly antisymmetric.  Grid: x = (A, B) tile pair (A <= B
+// for modes 1 and 3, every pair for mode 2), y = (i, j) (every plane for mode 1, i < j otherwise:
+// val vanishes at i = j).
+constexpr int AT = 16;
+__device__ inline z cneg(z a) { return make_double2(-a.x, -a.y); }
+__global__ __launch_bounds__(AT * AT) void k_antisym_tiles(z* __restrict__ r, const z* __restrict__ x, long o, long v,
+                                                           int mode, z alpha) {
+  __shared__ z T[4][AT][AT + 1];
+  const int tx = threadIdx.x % AT, ty = threadIdx.x / AT;
+  const long nb = (v + AT - 1) / AT;
+  long A, B;
+  if (mode == 2) {
+    A = blockIdx.x / nb;
+    B = blockIdx.x % nb;
+  } else {
+    long q = blockIdx.x;
+    A = 0;
+    while (q >= nb - A) { q -= nb - A; ++A; }
+    B = A + q;
+  }
+  long i, j;
+  if (mode == 1) {
+    i = blockIdx.y / o;
+    j = blockIdx.y % o;
+  } else {
+    long q = blockIdx.y;
+    i = 0;
+    while (q >= o - 1 - i) { q -= o - 1 - i; ++i; }
+    j = i + 1 + q;
+  }
+  const long pij = (i * o + j) * v * v, pji = (j * o + i) * v * v;
+  const long A0 = A * AT, B0 = B * AT;
+  auto load = [&](int k, long plane, long R0, long C0) {
+    const long e = R0 + ty, f = C0 + tx;
+    T[k][ty][tx] = (e < v && f < v) ? x[plane + e * v + f] : make_double2(0.0, 0.0);
+  };
+  auto add = [&](long plane, long R0, long C0, z val) {
+    const long e = R0 + ty, f = C0 + tx;
+    if (e < v && f < v) {
+      z* p = r + plane + e * v + f;
+      *p = cadd(*p, cmul(alpha, val));
+    }
+  };
+  if (mode == 2) {
+    // val = x_ijab - x_jiab: no transpose; r_ij += val, r_ji -= val
+    const long e = A0 + ty, f = B0 + tx;
+    if (e < v && f < v) {
+      const z val = csub(x[pij + e * v + f], x[pji + e * v + f]);
+      add(pij, A0, B0, val);
+      add(pji, A0, B0, cneg(val));
+    }
+    return;
+  }
+  load(0, pij, A0, B0);
+  if (A != B) load(1, pij, B0, A0);
+  if (mode == 3) {
+    load(2, pji, A0, B0);
+    if (A != B) load(3, pji, B0, A0);
+  }
+  __syncthreads();
+  const int kBA = A != B ? 1 : 0, kJBA = A != B ? 3 : 2;   // tiles holding x_ijba, x_jiba
+  // val of element (a, b) = (A0 + ra, B0 + cb) from the tiles, in the order x_ijab - x_ijba - x_jiab + x_jiba
+  auto val_at = [&](int ra, int cb) {
+    z w = csub(T[0][ra][cb], T[kBA][cb][ra]);
+    if (mode == 3) w = cadd(csub(w, T[2][ra][cb]), T[kJBA][cb][ra]);
+    return w;
+  };
+  const z vab = val_at(ty, tx);          // this thread's element of the (A, B) tile
+  add(pij, A0, B0, vab);
+  if (mode == 3) add(pji, A0, B0, cneg(vab));
+  if (A != B) {
+    const z vba = val_at(tx, ty);        // the element whose (B, A) image this thread writes
+    add(pij, B0, A0, cneg(vba));
+    if (mode == 3) add(pji, B0, A0, vba);
   }
 }
 
@@ -460,7 +528,12 @@ void permute(fc_ctx ctx, const ZT& in, const std::vector<int>& perm, z alpha, z 
 void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha) {
   long n = o * o * v * v;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_antisym_add, dim3(nblocks(n, 4)), dim3(TPB), 0, ctx->stream, r, x, o, v, mode, alpha);
+  const long nb = (v + AT - 1) / AT;
+  const long gx = mode == 2 ? nb * nb : nb * (nb + 1) / 2, gy = mode == 1 ? o * o : o * (o - 1) / 2;
+  if (gy <= 0) return;
+  FC_REQUIRE(gx < (1L << 31) && gy <= 65535, FC_EARG, "antisym_add: too many tiles");
+  hipLaunchKernelGGL(k_antisym_tiles, dim3((unsigned)gx, (unsigned)gy), dim3(AT * AT), 0, ctx->stream, r, x, o, v,
+                     mode, alpha);
   FC_HIP(hipGetLastError());
 }
 
