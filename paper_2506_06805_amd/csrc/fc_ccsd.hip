@@ -209,7 +209,9 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     ZTensor Fp(ctx, {o, o});
     FC_HIP(hipMemcpyAsync(Fp.p(), Fmi.p(), sizeof(z) * Fp.size(), hipMemcpyDeviceToDevice, ctx->stream));
     zein(ctx, "je,me->mj", half, T1, Fme, one, Fp);
-    zein(ctx, "imab,mj->ijab", one, T2, Fp, zero, x);
+    // one product per i: x[i] (j x ab) = Fp^T t2[i] (m x ab), no operand reordering
+    zgemm(ctx, 'T', 'N', o, v * v, o, one, Fp.p(), o, t2p, v * v, zero, x.p(), v * v, (int)o, 0, o * v * v,
+          o * v * v);
     antisym_add(ctx, r2p, x.p(), o, v, 2, mone);
     if (fdiag) hipLaunchKernelGGL(k_diag_copy, dim3(1), dim3(TPB), 0, ctx->stream, Fp.p(), o, fdiag);
   }
@@ -222,7 +224,13 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   {  // P(ij)P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
     zein(ctx, "imae,mbej->ijab", one, T2, Wmbej, zero, x);
     ZTensor U(ctx, {o, o, v, o});
-    zein(ctx, "ie,mbej->imbj", one, T1, I->ovvo, zero, U);
+    // U[i,m,b,j] = sum_e t_i^e <mb||ej>: one product (i x j) = t1 (i x e) <mb||ej>[m,b] (e x j) per (m, b),
+    // batch index m v + b (C stride o, B stride v o), launched in chunks of at most 65535
+    for (long s0 = 0; s0 < o * v; s0 += 65535) {
+      const long nb = std::min(65535L, o * v - s0);
+      zgemm(ctx, 'N', 'N', o, o, v, one, t1p, v, I->ovvo.p() + s0 * v * o, o, zero, U.p() + s0 * o, o * v * o, (int)nb,
+            0, v * o, o);
+    }
     zein(ctx, "ma,imbj->ijab", mone, T1, U, one, x);
     antisym_add(ctx, r2p, x.p(), o, v, 3, one);
   }

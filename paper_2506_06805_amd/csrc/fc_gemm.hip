@@ -71,6 +71,8 @@ struct GemmArgs {
   // C[((m / v) nB + n / v) v^2 + (m % v) v + n % v]; tiles with every a > every b are skipped
   long lv, lnB;
   int ltri;
+  int omap;           // EPI 0: C laid out by `om` instead of row-major with ldc
+  OutMap om;
 };
 
 // blockIdx -> tile so that XCD x (= bid % 8) owns the contiguous tiles [x * per, (x + 1) * per)
@@ -118,6 +120,9 @@ struct TileSmem<BM, BN, BK, double> {
   }
 };
 
+// Source of the elements outside a product for loads that must issue on every path.
+__device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
+
 // One output tile [m0, m0 + BM) x [n0, n0 + BN) of one product over the K range [klo, khi).
 struct TileJob {
   long M, N;
@@ -129,6 +134,8 @@ struct TileJob {
   long m0, n0, klo, khi;
   z* part;        // split-K: raw sums over this K range as [M][N] (nullptr: write C)
   long lv, lnB;   // ladder epilogue (EPI == 1)
+  int omap;       // EPI 0: C laid out by om
+  OutMap om;
 };
 
 // Writes a finished tile: alpha, beta and the output layout (row-major C, the ladder layout, or
@@ -144,6 +151,9 @@ __device__ __forceinline__ void tile_epilogue(const TileJob& g, const Acc (&cr)[
   // Ladder layout: off = ((a nB + b) v + e) v + f = (a nB v + e) v + (b v^2 + f) splits into a row
   // part and a column part, each formed once per row or column of the lane with 32-bit division
   // (a per-element 64-bit division cost more than a tenth of the assembly's time).
+  // A general output map (EPI 0 with omap) splits the same way: (m / rd) rs1 + (m % rd) rs2 per row,
+  // (n / cd) cs1 + (n % cd) cs2 per element (M, N < 2^31, checked by the host).
+  const bool om = EPI == 0 && g.omap;
   long coff[FJ];
   if (EPI == 1) {
     const unsigned lv = (unsigned)g.lv;
@@ -162,6 +172,9 @@ __device__ __forceinline__ void tile_epilogue(const TileJob& g, const Acc (&cr)[
       if (EPI == 1) {
         const unsigned mu = (unsigned)m, lv = (unsigned)g.lv, a = mu / lv;
         roff = ((long)a * g.lnB * g.lv + (long)(mu - a * lv)) * g.lv;
+      } else if (om) {
+        const unsigned mu = (unsigned)m, rd = (unsigned)g.om.rd, q = mu / rd;
+        roff = (long)q * g.om.rs1 + (long)(mu - q * rd) * g.om.rs2;
       }
 #pragma unroll
       for (int j = 0; j < FJ; ++j) {
@@ -177,7 +190,11 @@ __device__ __forceinline__ void tile_epilogue(const TileJob& g, const Acc (&cr)[
           g.part[m * g.N + n] = make_double2(re, im);
           continue;
         }
-        const long off = EPI == 1 ? roff + coff[j] : m * g.ldc + n;
+        long off = EPI == 1 ? roff + coff[j] : m * g.ldc + n;
+        if (om) {  // column part formed here: a per-column array costs registers in every EPI 0 kernel
+          const unsigned nu = (unsigned)n, cd = (unsigned)g.om.cd, q = nu / cd;
+          off = roff + (long)q * g.om.cs1 + (long)(nu - q * cd) * g.om.cs2;
+        }
         z out = make_double2(g.alpha.x * re - g.alpha.y * im, g.alpha.x * im + g.alpha.y * re);
         if (use_beta) {
           z c0 = C[off];
@@ -206,7 +223,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
   const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
 
   z ra[LA], rb[LB];
-#define FC_LOAD_TILE(k0)                                                                 \
+#define FC_LOAD_TILE(k0, ra, rb)                                                                 \
   do {                                                                                   \
     _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
       int e = tid + NT * r, mm, kk;                                                      \
@@ -225,7 +242,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       rb[r] = val;                                                                       \
     }                                                                                    \
   } while (0)
-#define FC_STORE_TILE(buf)                                                               \
+#define FC_STORE_TILE(buf, ra, rb)                                                               \
   do {                                                                                   \
     _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
       int e = tid + NT * r, mm, kk;                                                      \
@@ -236,6 +253,26 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       int e = tid + NT * r, nn, kk;                                                      \
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }           \
       sm.putB(buf, kk, nn, make_double2(rb[r].x, sb * rb[r].y));                         \
+    }                                                                                    \
+  } while (0)
+// The same loads with no branch: an element outside the product is read from a zero in global
+// memory, so every load instruction issues on every path (no select after it either) and the
+// compiler's count of loads in flight stays exact across the two-slice pipeline below.
+#define FC_LOAD_TILE_U(k0, ra, rb)                                                       \
+  do {                                                                                   \
+    _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
+      int e = tid + NT * r, mm, kk;                                                      \
+      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }           \
+      const long gm = m0 + mm, gk = (k0) + kk;                                           \
+      const z* src = (gm < g.M && gk < khi) ? A + (TA ? gk * g.lda + gm : gm * g.lda + gk) : g_dma_zero; \
+      ra[r] = *src;                                                                      \
+    }                                                                                    \
+    _Pragma("unroll") for (int r = 0; r < LB; ++r) {                                     \
+      int e = tid + NT * r, nn, kk;                                                      \
+      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }           \
+      const long gn = n0 + nn, gk = (k0) + kk;                                           \
+      const z* src = (gn < g.N && gk < khi) ? B + (TB ? gn * g.ldb + gk : gk * g.ldb + gn) : g_dma_zero; \
+      rb[r] = *src;                                                                      \
     }                                                                                    \
   } while (0)
 
@@ -260,64 +297,84 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 
   constexpr bool kEarlyStore = sizeof(T) == sizeof(double);
   const long nk = (khi - klo + BK - 1) / BK;
-  FC_LOAD_TILE(klo);
-  FC_STORE_TILE(0);
-  __syncthreads();
   const int lr = lane & 15, lk = lane >> 4;
-  for (long kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) FC_LOAD_TILE(klo + (kt + 1) * BK);
-#pragma unroll
-    for (int ks = 0; ks < BK; ks += 4) {
-      T ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];
-#pragma unroll
-      for (int i = 0; i < FI; ++i) {
-        sm.getA(buf, ks + lk, wm + 16 * i + lr, ar[i], ai[i]);
-        nai[i] = -ai[i];
+  // the products of one K slice from LDS buffer `buf` (FP64: the next slice is stored to the other
+  // buffer before the last quarter's products)
+#define FC_SLICE_PRODUCTS(buf, kt)                                                                \
+  _Pragma("unroll") for (int ks = 0; ks < BK; ks += 4) {                                          \
+    T ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];                                                    \
+    _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                              \
+      sm.getA(buf, ks + lk, wm + 16 * i + lr, ar[i], ai[i]);                                      \
+      nai[i] = -ai[i];                                                                            \
+    }                                                                                             \
+    _Pragma("unroll") for (int j = 0; j < FJ; ++j) sm.getB(buf, ks + lk, wn + 16 * j + lr, br[j], bi[j]); \
+    if (kEarlyStore && ks == BK - 4 && (kt) + 1 < nk) FC_STORE_TILE((buf) ^ 1, ra, rb);           \
+    if constexpr (k3M) {                                                                          \
+      T sa_[FI], sb_[FJ];                                                                         \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = ar[i] + ai[i];                      \
+      _Pragma("unroll") for (int j = 0; j < FJ; ++j) sb_[j] = br[j] + bi[j];                      \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                              \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                          \
+          cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);                                        \
+          ci[i][j] = Mfma<T>::mac(ai[i], bi[j], ci[i][j]);                                        \
+          cx[i][j] = Mfma<T>::mac(sa_[i], sb_[j], cx[i][j]);                                      \
+        }                                                                                         \
+    } else {                                                                                      \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                              \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                          \
+          cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);                                        \
+          ci[i][j] = Mfma<T>::mac(ar[i], bi[j], ci[i][j]);                                        \
+        }                                                                                         \
+      _Pragma("unroll") for (int i = 0; i < FI; ++i)                                              \
+        _Pragma("unroll") for (int j = 0; j < FJ; ++j) {                                          \
+          cr[i][j] = Mfma<T>::mac(nai[i], bi[j], cr[i][j]);                                       \
+          ci[i][j] = Mfma<T>::mac(ai[i], br[j], ci[i][j]);                                        \
+        }                                                                                         \
+    }                                                                                             \
+  }
+
+  // FP32 128 x 128: global loads two K slices ahead into two register sets (even slices in ra/rb,
+  // odd ones in ra2/rb2), the loop unrolled by two so that each half names its sets statically: a
+  // slice's FP32 products are too short to cover the load latency on their own, and this tile (one
+  // workgroup per CU) has registers to spare below the next occupancy step.  The smaller FP32 tiles
+  // would lose a wave per SIMD and keep loads one slice ahead, as do the FP64 tiles.
+  constexpr bool kDepth2 = sizeof(T) == sizeof(float) && BM == 128 && BN == 128;
+  if constexpr (kDepth2) {
+    z ra2[LA], rb2[LB];
+    FC_LOAD_TILE_U(klo, ra, rb);
+    FC_STORE_TILE(0, ra, rb);
+    FC_LOAD_TILE_U(klo + BK, ra2, rb2);
+    __syncthreads();
+    for (long kt = 0; kt < nk; kt += 2) {
+      FC_LOAD_TILE_U(klo + (kt + 2) * BK, ra, rb);
+      FC_SLICE_PRODUCTS(0, kt);
+      if (kt + 1 < nk) FC_STORE_TILE(1, ra2, rb2);
+      __syncthreads();
+      if (kt + 1 < nk) {
+        FC_LOAD_TILE_U(klo + (kt + 3) * BK, ra2, rb2);
+        FC_SLICE_PRODUCTS(1, kt + 1);
+        if (kt + 2 < nk) FC_STORE_TILE(0, ra, rb);
+        __syncthreads();
       }
-#pragma unroll
-      for (int j = 0; j < FJ; ++j) {
-        sm.getB(buf, ks + lk, wn + 16 * j + lr, br[j], bi[j]);
-      }
+    }
+  } else {
+    FC_LOAD_TILE(klo, ra, rb);
+    FC_STORE_TILE(0, ra, rb);
+    __syncthreads();
+    for (long kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) FC_LOAD_TILE(klo + (kt + 1) * BK, ra, rb);
       // FP64: the next tile goes to the other buffer while the last products of this one run
       // (measured: +6-10% on skinny and long-K products, neutral on large ones); FP32 products
       // are twice as fast, too short to cover the global loads, and store after the step instead
-      if (kEarlyStore && ks == BK - 4 && kt + 1 < nk) FC_STORE_TILE(buf ^ 1);
-      if constexpr (k3M) {
-        T sa_[FI], sb_[FJ];
-#pragma unroll
-        for (int i = 0; i < FI; ++i) sa_[i] = ar[i] + ai[i];
-#pragma unroll
-        for (int j = 0; j < FJ; ++j) sb_[j] = br[j] + bi[j];
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
-#pragma unroll
-          for (int j = 0; j < FJ; ++j) {
-            cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::mac(ai[i], bi[j], ci[i][j]);
-            cx[i][j] = Mfma<T>::mac(sa_[i], sb_[j], cx[i][j]);
-          }
-      } else {
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
-#pragma unroll
-          for (int j = 0; j < FJ; ++j) {
-            cr[i][j] = Mfma<T>::mac(ar[i], br[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::mac(ar[i], bi[j], ci[i][j]);
-          }
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
-#pragma unroll
-          for (int j = 0; j < FJ; ++j) {
-            cr[i][j] = Mfma<T>::mac(nai[i], bi[j], cr[i][j]);
-            ci[i][j] = Mfma<T>::mac(ai[i], br[j], ci[i][j]);
-          }
-      }
+      FC_SLICE_PRODUCTS(buf, kt);
+      if (!kEarlyStore && kt + 1 < nk) FC_STORE_TILE(buf ^ 1, ra, rb);
+      __syncthreads();
     }
-    if (!kEarlyStore && kt + 1 < nk) FC_STORE_TILE(buf ^ 1);
-    __syncthreads();
   }
+#undef FC_SLICE_PRODUCTS
 #undef FC_LOAD_TILE
+#undef FC_LOAD_TILE_U
 #undef FC_STORE_TILE
 
   tile_epilogue<BM, BN, WGM, WGN, EPI, T, k3M>(g, cr, ci, cx, wm, wn, lr, lk);
@@ -342,7 +399,6 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
 // reads slice kt + 1's first quarter and runs the second quarter's products.  The loads are issued
 // from inline assembly: the compiler would otherwise make every later LDS read wait for all of
 // them, and the waits here are explicit.
-__device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
 
 template <int BM, int BN, int BK>
 struct DmaSmem {
@@ -562,6 +618,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
   j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
   j.part = g.part ? g.part + (long)blockIdx.y * g.M * g.N : nullptr;
   j.lv = g.lv; j.lnB = g.lnB;
+  j.omap = g.omap; j.om = g.om;
   if constexpr (DMA) {
     __shared__ DmaSmem<BM, BN, BK> sm;
     gemm_tile_dma<BM, BN, WGM, WGN, BK, TA, TB, EPI, DMA == 2, T>(j, sm);
@@ -575,9 +632,11 @@ __global__ __launch_bounds__(WGM * WGN * 64) void zgemm_f64_kernel(GemmArgs g) {
 // take the splits s = w, w + W, ... in ascending order (two running sums each) and wave 0 adds
 // the W results in wave order.  The order depends only on (ns, W), so results repeat bit for bit,
 // and many splits of a small output are summed by W waves at once instead of one serial loop.
+// With omap, C is laid out by om (the product's output map) instead of row-major with ldc.
 template <int W>
 __global__ void __launch_bounds__(64 * W) k_splitk_reduce(const z* __restrict__ P, int ns, long M, long N,
-                                                          z* __restrict__ C, long ldc, z alpha, z beta) {
+                                                          z* __restrict__ C, long ldc, z alpha, z beta, int omap,
+                                                          OutMap om) {
   __shared__ z acc[W][64];
   const long MN = M * N;
   const bool use_beta = (beta.x != 0.0 || beta.y != 0.0);
@@ -600,24 +659,29 @@ __global__ void __launch_bounds__(64 * W) k_splitk_reduce(const z* __restrict__ 
       double re = 0, im = 0;
       for (int q = 0; q < W; ++q) { re += acc[q][lane].x; im += acc[q][lane].y; }
       const long m = t / N, n = t % N;
+      const long off = omap ? (m / om.rd) * om.rs1 + (m % om.rd) * om.rs2 + (n / om.cd) * om.cs1 + (n % om.cd) * om.cs2
+                            : m * ldc + n;
       z out = make_double2(alpha.x * re - alpha.y * im, alpha.x * im + alpha.y * re);
       if (use_beta) {
-        const z c0 = C[m * ldc + n];
+        const z c0 = C[off];
         out.x += beta.x * c0.x - beta.y * c0.y;
         out.y += beta.x * c0.y + beta.y * c0.x;
       }
-      C[m * ldc + n] = out;
+      C[off] = out;
     }
     __syncthreads();
   }
 }
 
-void splitk_reduce(hipStream_t st, const z* part, long ns, long M, long N, z* C, long ldc, z alpha, z beta) {
+void splitk_reduce(hipStream_t st, const z* part, long ns, long M, long N, z* C, long ldc, z alpha, z beta,
+                   const OutMap* om) {
   const long MN = M * N;
   const unsigned nb = (unsigned)std::max(1L, std::min(65536L, (MN + 63) / 64));
-  if (ns >= 64) k_splitk_reduce<16><<<nb, 64 * 16, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
-  else if (ns >= 8) k_splitk_reduce<4><<<nb, 64 * 4, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
-  else k_splitk_reduce<1><<<nb, 64, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta);
+  const int f = om ? 1 : 0;
+  const OutMap m = om ? *om : OutMap{};
+  if (ns >= 64) k_splitk_reduce<16><<<nb, 64 * 16, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta, f, m);
+  else if (ns >= 8) k_splitk_reduce<4><<<nb, 64 * 4, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta, f, m);
+  else k_splitk_reduce<1><<<nb, 64, 0, st>>>(part, (int)ns, M, N, C, ldc, alpha, beta, f, m);
 }
 
 template <int BM, int BN, int WGM, int WGN, int BK, int EPI, typename T, int DMA = 0>
@@ -661,9 +725,10 @@ void launch_cfg(int cfg, const GemmArgs& g, bool ta, bool tb, dim3 grid, hipStre
 // Launch one configuration (split-K decided inside for configurations whose grid cannot fill the chip).
 // fixed_part: when given, split-K partial sums go there (at most NOALLOC_SCRATCH_BYTES) instead
 // of into a buffer from the context's allocator.
+// om: when given, C is laid out by the output map (batch 1, no ladder epilogue).
 void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
-               const LadderEpilogue* lep, z* fixed_part = nullptr);
+               const LadderEpilogue* lep, z* fixed_part = nullptr, const OutMap* om = nullptr);
 
 // Shape bucket: operand layouts, sizes rounded to powers of two, batching and epilogue kind.
 std::string bucket(char opA, char opB, long M, long N, long K, int batch, const LadderEpilogue* lep, int fp32) {
@@ -714,7 +779,8 @@ int forced_cfg(fc_ctx ctx, long M, long N) {
 }
 
 void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B,
-                long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC, const LadderEpilogue* lep) {
+                long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC, const LadderEpilogue* lep,
+                const OutMap* om = nullptr) {
   if (M <= 0 || N <= 0 || batch <= 0) return;
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
   int cfg = heuristic_cfg(M, N, K, batch, !lep && ctx->gemm_fp32);
@@ -728,8 +794,9 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
       cfg = it->second.first;
     } else {
       // time every configuration once (after one warm-up launch) on a scratch copy of C, keep the fastest
-      const long csz = lep ? (M / lep->v) * lep->nB * lep->v * lep->v
-                           : ((long)(batch - 1) * sC + (M - 1) * ldc + N);
+      const long csz = lep  ? (M / lep->v) * lep->nB * lep->v * lep->v
+                       : om ? (long)(batch - 1) * sC + om->span(M, N)
+                            : ((long)(batch - 1) * sC + (M - 1) * ldc + N);
       DBuf trial(ctx, sizeof(z) * (size_t)std::max(1L, csz));
       hipEvent_t e0, e1;
       FC_HIP(hipEventCreate(&e0));
@@ -743,7 +810,8 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
           if (!lep && (beta.x != 0.0 || beta.y != 0.0))
             FC_HIP(hipMemcpyAsync(trial.p, C, sizeof(z) * csz, hipMemcpyDeviceToDevice, ctx->stream));
           FC_HIP(hipEventRecord(e0, ctx->stream));
-          zgemm_run(ctx, c, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, trial.as<z>(), ldc, batch, sA, sB, sC, lep);
+          zgemm_run(ctx, c, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, trial.as<z>(), ldc, batch, sA, sB, sC, lep,
+                    nullptr, om);
           FC_HIP(hipEventRecord(e1, ctx->stream));
           FC_HIP(hipEventSynchronize(e1));
           FC_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -756,15 +824,18 @@ void zgemm_impl(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha,
       cfg = bestc;
     }
   }
-  zgemm_run(ctx, cfg, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, lep);
+  zgemm_run(ctx, cfg, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, lep, nullptr, om);
 }
 
 void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                const z* B, long ldb, z beta, z* C, long ldc, int batch, long sA, long sB, long sC,
-               const LadderEpilogue* lep, z* fixed_part) {
+               const LadderEpilogue* lep, z* fixed_part, const OutMap* om) {
   FC_REQUIRE(strchr("NTCR", opA) && strchr("NTCR", opB), FC_EARG, "zgemm: bad op");
+  FC_REQUIRE(!om || (!lep && om->rd >= 1 && om->cd >= 1 && M % om->rd == 0 && N % om->cd == 0 &&
+                     M < (1L << 31) && N < (1L << 31)),
+             FC_EARG, "zgemm: bad output map");
   if (K <= 0) {  // C = beta C
-    FC_REQUIRE(!lep, FC_EARG, "zgemm: empty ladder product");
+    FC_REQUIRE(!lep && !om, FC_EARG, "zgemm: empty ladder or mapped product");
     for (int b = 0; b < batch; ++b)
       for (long m = 0; m < M; ++m) scale(ctx, C + b * sC + m * ldc, N, beta);
     return;
@@ -780,6 +851,8 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   g.lv = lep ? lep->v : 1;
   g.lnB = lep ? lep->nB : 1;
   g.ltri = lep ? lep->triangular : 0;
+  g.omap = om ? 1 : 0;
+  g.om = om ? *om : OutMap{};
   const bool ta = (opA == 'T' || opA == 'C');
   const bool tb = (opB == 'T' || opB == 'C');
   FC_REQUIRE(batch <= 65535, FC_EARG, "zgemm: batch too large");
@@ -827,7 +900,7 @@ void zgemm_run(fc_ctx ctx, int cfg, char opA, char opB, long M, long N, long K, 
   else launch_cfg<0, double>(cfg, g, ta, tb, grid, ctx->stream);
   FC_HIP(hipGetLastError());
   if (ksplit > 1) {
-    splitk_reduce(ctx->stream, g.part, ksplit, M, N, C, ldc, alpha, beta);
+    splitk_reduce(ctx->stream, g.part, ksplit, M, N, C, ldc, alpha, beta, om);
     FC_HIP(hipGetLastError());
   }
   if (e0) {
@@ -902,7 +975,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm(const char* __res
     j.klo = s * g.kchunk;
     j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
     j.part = g.ksplit > 1 ? g.part + (s * g.batch + b) * g.M * g.N : nullptr;
-    j.lv = 1; j.lnB = 1;
+    j.lv = 1; j.lnB = 1; j.omap = 0;
     if (g.ta) {
       if (g.tb) gemm_tile<BM, BN, WGM, WGN, BK, true, true, 0>(j, sm);
       else gemm_tile<BM, BN, WGM, WGN, BK, true, false, 0>(j, sm);
@@ -942,7 +1015,7 @@ __global__ __launch_bounds__(WGM * WGN * 64) void k_group_gemm_dma(const char* _
     j.klo = s * g.kchunk;
     j.khi = j.klo + g.kchunk < g.K ? j.klo + g.kchunk : g.K;
     j.part = g.ksplit > 1 ? g.part + (s * g.batch + b) * g.M * g.N : nullptr;
-    j.lv = 1; j.lnB = 1;
+    j.lv = 1; j.lnB = 1; j.omap = 0;
     if (!first) __syncthreads();   // every wave has left the previous tile's buffers
     first = false;
     if (g.ta) {
@@ -1155,6 +1228,11 @@ void zgemm_noalloc(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alp
 void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, const z* B, long ldb,
            z beta, z* C, long ldc, int batch, long sA, long sB, long sC) {
   zgemm_impl(ctx, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, nullptr);
+}
+
+void zgemm_mapped(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+                  const z* B, long ldb, z beta, z* C, const OutMap& om, int batch, long sA, long sB, long sC) {
+  zgemm_impl(ctx, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, 0, batch, sA, sB, sC, nullptr, &om);
 }
 
 void zgemm_ladder(fc_ctx ctx, long M, long N, long K, const z* A, long lda, const z* B, long ldb, z* W,

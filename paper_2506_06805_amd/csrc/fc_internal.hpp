@@ -123,6 +123,20 @@ struct ZTensor {
 void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
            const z* B, long ldb, z beta, z* C, long ldc, int batch = 1, long sA = 0, long sB = 0,
            long sC = 0);
+// Output layout of a product whose row and column indices each split into two sub-indices with
+// strides of their own (a contraction whose free indices interleave in the output tensor):
+// element (m, n) is C[(m / rd) rs1 + (m % rd) rs2 + (n / cd) cs1 + (n % cd) cs2].  rd divides M
+// and cd divides N, so the map is known to reach exactly its largest offset (span()).
+struct OutMap {
+  long rd = 1, rs1 = 0, rs2 = 0, cd = 1, cs1 = 0, cs2 = 0;
+  long span(long M, long N) const {
+    return (M / rd - 1) * rs1 + (rd - 1) * rs2 + (N / cd - 1) * cs1 + (cd - 1) * cs2 + 1;
+  }
+};
+// C_b = alpha op(A_b) op(B_b) + beta C_b with each C_b (at C + b sC) laid out by `om`.
+void zgemm_mapped(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
+                  const z* B, long ldb, z beta, z* C, const OutMap& om, int batch = 1, long sA = 0, long sB = 0,
+                  long sC = 0);
 
 // Split-precision variant (hi/lo BF16 or FP16 parts, FP32 accumulation, three products).
 void zgemm_split(fc_ctx ctx, int precision, char opA, char opB, long M, long N, long K, z alpha,

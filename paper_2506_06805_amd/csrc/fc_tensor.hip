@@ -577,6 +577,30 @@ std::vector<int> perm_to(const std::string& from, const std::string& to) {
   for (char ch : to) p.push_back((int)from.find(ch));
   return p;
 }
+// Output map for a product whose rows run over rowOrd and columns over colOrd (each row-major)
+// into C with index order cOrd: possible when each side's indices (those of extent > 1) form at
+// most two runs that are also consecutive and contiguous in C.
+bool out_map(const std::string& cOrd, std::map<char, long>& dim, const std::string& rowOrd,
+             const std::string& colOrd, OutMap& om) {
+  std::map<char, long> str;
+  long st = 1;
+  for (int k = (int)cOrd.size() - 1; k >= 0; --k) { str[cOrd[k]] = st; st *= dim[cOrd[k]]; }
+  auto side = [&](const std::string& ord, long& d, long& s1, long& s2) {
+    std::vector<std::string> runs;
+    for (char ch : ord) {
+      if (dim[ch] == 1) continue;
+      if (!runs.empty() && str[runs.back().back()] == dim[ch] * str[ch]) runs.back() += ch;
+      else runs.push_back(std::string(1, ch));
+    }
+    auto ext = [&](const std::string& r) { long e = 1; for (char ch : r) e *= dim[ch]; return e; };
+    if (runs.size() > 2) return false;
+    if (runs.empty()) { d = 1; s1 = 0; s2 = 0; }
+    else if (runs.size() == 1) { d = ext(runs[0]); s1 = 0; s2 = str[runs[0].back()]; }
+    else { d = ext(runs[1]); s1 = str[runs[0].back()]; s2 = str[runs[1].back()]; }
+    return true;
+  };
+  return side(rowOrd, om.rd, om.rs1, om.rs2) && side(colOrd, om.cd, om.cs1, om.cs2);
+}
 }  // namespace
 
 void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z beta, const ZT& C, bool conjA, bool conjB) {
@@ -613,26 +637,42 @@ void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z bet
   // contiguously; the plan that moves the fewest bytes through permutations wins.
   struct Plan {
     std::string kOrd, faOrd, fbOrd;
-    bool permA = false, permB = false, permC = false;
+    bool permA = false, permB = false, permC = false, mapC = false, flipC = false;
     char opA = 'N', opB = 'N';
+    OutMap om;
     double cost = 0;
   };
   std::string cFA, cFB;   // free indices in the output's order
   for (char ch : s.c) (FA.find(ch) != std::string::npos ? cFA : cFB) += ch;
-  auto plan_for = [&](const std::string& kOrd) {
+  // A mapped output is stored coalesced when consecutive columns of the product are consecutive in
+  // C (the column side's innermost run has stride 1): the matrix-core tile stores 16 consecutive
+  // columns per row.  Other maps scatter every element to its own cache line and cost more than
+  // the permutation they replace (measured), so they are not used.
+  auto coalesced = [](const OutMap& m) { return m.cs2 == 1; };
+  // forceA / forceB: reorder that operand into the output's index order even when it could be used
+  // in place (a small operand reordered can turn a large output permutation into a coalesced map)
+  auto plan_for = [&](const std::string& kOrd, bool forceA, bool forceB) {
     Plan p;
     p.kOrd = kOrd;
     const std::string pre = s.a.substr(0, FA.size()), post = s.a.substr(FA.size());
     const std::string pre2 = s.a.substr(0, K.size()), post2 = s.a.substr(K.size());
-    if (is_perm_of(pre, FA) && post == kOrd) { p.faOrd = pre; p.opA = conjA ? 'R' : 'N'; }
-    else if (pre2 == kOrd && is_perm_of(post2, FA)) { p.faOrd = post2; p.opA = conjA ? 'C' : 'T'; }
+    if (!forceA && is_perm_of(pre, FA) && post == kOrd) { p.faOrd = pre; p.opA = conjA ? 'R' : 'N'; }
+    else if (!forceA && pre2 == kOrd && is_perm_of(post2, FA)) { p.faOrd = post2; p.opA = conjA ? 'C' : 'T'; }
     else { p.faOrd = cFA; p.permA = true; p.opA = 'N'; }
     const std::string bpre = s.b.substr(0, K.size()), bpost = s.b.substr(K.size());
     const std::string bpre2 = s.b.substr(0, FB.size()), bpost2 = s.b.substr(FB.size());
-    if (bpre == kOrd && is_perm_of(bpost, FB)) { p.fbOrd = bpost; p.opB = conjB ? 'R' : 'N'; }
-    else if (bpost2 == kOrd && is_perm_of(bpre2, FB)) { p.fbOrd = bpre2; p.opB = conjB ? 'C' : 'T'; }
+    if (!forceB && bpre == kOrd && is_perm_of(bpost, FB)) { p.fbOrd = bpost; p.opB = conjB ? 'R' : 'N'; }
+    else if (!forceB && bpost2 == kOrd && is_perm_of(bpre2, FB)) { p.fbOrd = bpre2; p.opB = conjB ? 'C' : 'T'; }
     else { p.fbOrd = cFB; p.permB = true; p.opB = 'N'; }
     p.permC = !(s.c == p.faOrd + p.fbOrd || s.c == p.fbOrd + p.faOrd);
+    // an output the product can store in place, coalesced, through an output map needs no
+    // permutation; flipC: as the transposed product (rows from B, columns from A)
+    if (p.permC && KK > 0 && M < (1L << 31) && N < (1L << 31)) {
+      OutMap m;
+      if (out_map(s.c, dim, p.faOrd, p.fbOrd, m) && coalesced(m)) { p.mapC = true; p.om = m; }
+      else if (out_map(s.c, dim, p.fbOrd, p.faOrd, m) && coalesced(m)) { p.mapC = p.flipC = true; p.om = m; }
+      if (p.mapC) p.permC = false;
+    }
     p.cost = (p.permA ? 2.0 * A.size() : 0.0) + (p.permB ? 2.0 * B.size() : 0.0) + (p.permC ? 3.0 * M * N : 0.0);
     return p;
   };
@@ -647,13 +687,14 @@ void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z bet
   add(K);
   Plan best;
   best.cost = -1;
-  for (const auto& k : cands) {
-    Plan p = plan_for(k);
-    if (best.cost < 0 || p.cost < best.cost) best = p;
-  }
-  if (ctx->verbose >= 2 && best.cost > 0)
-    fprintf(stderr, "[zein] %s permutes A:%d B:%d C:%d (%.1f MB moved)\n", spec, best.permA, best.permB, best.permC,
-            best.cost * sizeof(z) / 1e6);
+  for (const auto& k : cands)
+    for (int f = 0; f < 4; ++f) {
+      Plan p = plan_for(k, f & 1, f & 2);
+      if (best.cost < 0 || p.cost < best.cost) best = p;
+    }
+  if (ctx->verbose >= 2 && (best.cost > 0 || best.mapC))
+    fprintf(stderr, "[zein] %s permutes A:%d B:%d C:%d%s (%.1f MB moved)\n", spec, best.permA, best.permB, best.permC,
+            best.mapC ? " (output mapped)" : "", best.cost * sizeof(z) / 1e6);
   const std::string& kOrd = best.kOrd;
   const std::string faOrd = best.faOrd, fbOrd = best.fbOrd;
   const z* Ap = A.p; char opA = best.opA; DBuf Atmp;
@@ -670,11 +711,15 @@ void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z bet
   }
   const long lda = (opA == 'N' || opA == 'R') ? KK : M;
   const long ldb = (opB == 'N' || opB == 'R') ? N : KK;
-  if (s.c == faOrd + fbOrd) {
+  // C^T = op(B)^T op(A)^T: swap operands and flip their transposition.
+  auto flip = [](char op) { return op == 'N' ? 'T' : op == 'T' ? 'N' : op == 'R' ? 'C' : 'R'; };
+  if (best.mapC && !best.flipC) {
+    zgemm_mapped(ctx, opA, opB, M, N, KK, alpha, Ap, lda, Bp, ldb, beta, C.p, best.om);
+  } else if (best.mapC) {
+    zgemm_mapped(ctx, flip(opB), flip(opA), N, M, KK, alpha, Bp, ldb, Ap, lda, beta, C.p, best.om);
+  } else if (s.c == faOrd + fbOrd) {
     zgemm(ctx, opA, opB, M, N, KK, alpha, Ap, lda, Bp, ldb, beta, C.p, N);
   } else if (s.c == fbOrd + faOrd) {
-    // C^T = op(B)^T op(A)^T: swap operands and flip their transposition.
-    auto flip = [](char op) { return op == 'N' ? 'T' : op == 'T' ? 'N' : op == 'R' ? 'C' : 'R'; };
     zgemm(ctx, flip(opB), flip(opA), N, M, KK, alpha, Bp, ldb, Ap, lda, beta, C.p, M);
   } else {
     DBuf Ctmp(ctx, sizeof(z) * std::max(1L, M * N));

@@ -51,12 +51,12 @@ GEMM_SHAPES = [("square4096", 4096, 4096, 4096, "N", "N"), ("assembly_T64", 1024
 
 
 def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1, shapes: str = "",
-               fp64_only: bool = False) -> None:
+               fp64_only: bool = False, fp32_only: bool = False) -> None:
     """TFLOP/s of the library's complex GEMM (FP64 and FP32 arithmetic) on the listed shapes, next
     to torch's complex128 matmul on the same operands (a vendor-library reference point).  With
     `tune` the library's autotuner times every tile configuration first and keeps the fastest.
-    `shapes` (comma-separated names) restricts the shapes; `fp64_only` times the FP64 products
-    alone (a clean program for counter runs)."""
+    `shapes` (comma-separated names) restricts the shapes; `fp64_only` / `fp32_only` time the FP64
+    or the FP32-arithmetic products alone (clean programs for counter runs)."""
     import torch
 
     from . import fnscc
@@ -89,9 +89,11 @@ def gemm_probe(reps: int, tune: bool = False, save: str = "", cfg: int = -1, sha
         Bn = B if ob == "N" else B.t().contiguous()
         fl = 8.0 * M * N * K
         res = {"shape": name, "M": M, "N": N, "K": K}
-        res["fp64_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C)) / 1e9
+        if not fp32_only:
+            res["fp64_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C)) / 1e9
         if not fp64_only:
             res["fp32_tflops"] = fl / timed(lambda: fnscc.zgemm(ctx, oa, ob, A, B, C=C, fp32=True)) / 1e9
+        if not (fp64_only or fp32_only):
             res["torch_complex128_tflops"] = fl / timed(lambda: torch.matmul(A, Bn, out=C)) / 1e9
         print(json.dumps({k: (round(x, 1) if isinstance(x, float) else x) for k, x in res.items()}), flush=True)
         del A, B, C, Bn
@@ -356,6 +358,7 @@ def main() -> None:
     g.add_argument("--cfg", type=int, default=-1, help="force this tile configuration where it fits")
     g.add_argument("--shapes", type=str, default="", help="comma-separated shape names (default: all)")
     g.add_argument("--fp64-only", action="store_true", help="time the FP64 products alone")
+    g.add_argument("--fp32-only", action="store_true", help="time the FP32-arithmetic products alone")
     sg = sub.add_parser("split-gemm")
     sg.add_argument("--reps", type=int, default=5)
     f = sub.add_parser("fns-presets")
@@ -389,7 +392,7 @@ def main() -> None:
     if args.cmd == "copy":
         copy_probe(args.mib)
     elif args.cmd == "gemm":
-        gemm_probe(args.reps, args.tune, args.save, args.cfg, args.shapes, args.fp64_only)
+        gemm_probe(args.reps, args.tune, args.save, args.cfg, args.shapes, args.fp64_only, args.fp32_only)
     elif args.cmd == "split-gemm":
         split_gemm_probe(args.reps)
     elif args.cmd == "fns-presets":
