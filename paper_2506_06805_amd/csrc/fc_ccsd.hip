@@ -153,7 +153,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
 
   // ---- intermediates
   ZTensor Fme(ctx, {o, v}), Fae(ctx, {v, v}), Fmi(ctx, {o, o});
-  zein(ctx, "nf,mnef->me", one, T1, I->oovv, zero, Fme);
+  zein(ctx, "nf,menf->me", one, T1, I->oovv_r, zero, Fme);
   // F_ae = sum_mf t_m^f <ma||fe> - 1/2 sum tau~_mn^af <mn||ef>,  <ma||fe> = (mf|ae) - (me|af)
   zein(ctx, "P,aeP->ae", one, xP, Lvv, zero, Fae);
   zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, Fae);
@@ -179,13 +179,17 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   {
     ZTensor Z(ctx, {o, o, v, v});
     hipLaunchKernelGGL(k_ring_amp, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, t1p, t2p, Z.p(), o, v, 0.5);
-    zein(ctx, "jnfb,mnef->mbej", mone, Z, I->oovv, one, Wmbej);
+    zein(ctx, "jnfb,menf->mbej", mone, Z, I->oovv_r, one, Wmbej);
   }
+
+  // t_im^ae as [i][a][m][e]: the two products that sum over (m, e) with (i, a) free read it in place
+  ZTensor T2r(ctx, {o, v, o, v});
+  permute(ctx, T2, {0, 2, 1, 3}, one, zero, T2r.p());
 
   // ---- T1 residual
   zein(ctx, "ie,ae->ia", one, T1, Fae, zero, R1);
   zein(ctx, "ma,mi->ia", mone, T1, Fmi, one, R1);
-  zein(ctx, "imae,me->ia", one, T2, Fme, one, R1);
+  zein(ctx, "iame,me->ia", one, T2r, Fme, one, R1);
   zein(ctx, "nf,naif->ia", mone, T1, I->ovov, one, R1);
   {  // -1/2 sum_mef t_im^ef <ma||ef> = - sum_fP Q[i,f,P] L^P_af,  Q[i,f,P] = sum_me t_im^ef L^P_me
     ZTensor Q(ctx, {o, v, N});
@@ -222,7 +226,7 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     axpy(ctx, n2, one, x.p(), r2p);
   }
   {  // P(ij)P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
-    zein(ctx, "imae,mbej->ijab", one, T2, Wmbej, zero, x);
+    zein(ctx, "iame,mbej->ijab", one, T2r, Wmbej, zero, x);
     ZTensor U(ctx, {o, o, v, o});
     // U[i,m,b,j] = sum_e t_i^e <mb||ej>: one product (i x j) = t1 (i x e) <mb||ej>[m,b] (e x j) per (m, b),
     // batch index m v + b (C stride o, B stride v o), launched in chunks of at most 65535

@@ -100,7 +100,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   zgemm(ctx, 'N', 'N', o, N, v, one, T->t1.p(), v, I->Lov.p(), N, zero, Cm.p(), N, (int)o, 0, v * N, o * N);
 
   H.Fme = ZTensor(ctx, {o, v});
-  zein(ctx, "nf,mnef->me", one, T1, I->oovv, zero, H.Fme);
+  zein(ctx, "nf,menf->me", one, T1, I->oovv_r, zero, H.Fme);
   H.Fmi = ZTensor(ctx, {o, o});
   zein(ctx, "ne,mnie->mi", one, T1, I->ooov, zero, H.Fmi);
   zein(ctx, "inef,mnef->mi", half, tau, I->oovv, one, H.Fmi);
@@ -132,7 +132,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   {
     ZTensor Z(ctx, {o, o, v, v});
     hipLaunchKernelGGL(k_ring_amp1, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, T->t1.p(), T->t2.p(), Z.p(), o, v);
-    zein(ctx, "jnfb,mnef->mbej", mone, Z, I->oovv, one, H.Wmbej);
+    zein(ctx, "jnfb,menf->mbej", mone, Z, I->oovv_r, one, H.Wmbej);
   }
   // W_mbij = <mb||ij> - F_me t_ij^be - t_n^b W_mnij + 1/2 <mb||ef> tau_ij^ef
   //          + P(ij) [<mn||ie> t_jn^be + t_i^e (<mb||ej> - t_nj^bf <mn||ef>)]
@@ -145,7 +145,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
     ZTensor x(ctx, {o, v, o, o}), V(ctx, {o, v, v, o});
     zein(ctx, "mnie,jnbe->mbij", one, I->ooov, T2, zero, x);
     FC_HIP(hipMemcpyAsync(V.p(), I->ovvo.p(), sizeof(z) * V.size(), hipMemcpyDeviceToDevice, ctx->stream));
-    zein(ctx, "njbf,mnef->mbej", mone, T2, I->oovv, one, V);
+    zein(ctx, "njbf,menf->mbej", mone, T2, I->oovv_r, one, V);
     zein(ctx, "ie,mbej->mbij", one, T1, V, one, x);
     hipLaunchKernelGGL(k_antisym_last2, dim3(nblk(x.size())), dim3(TPB), 0, ctx->stream, H.Wmbij.p(), x.p(), o * v, o, one);
   }

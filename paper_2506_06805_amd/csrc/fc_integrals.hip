@@ -137,6 +137,8 @@ void assemble_integrals(fc_ctx ctx, fc_ints I) {
   permute(ctx, I->ooov, {2, 3, 0, 1}, one, zero, I->ovoo.p(), true);
   I->vvoo = ZTensor(ctx, {o, o, v, v});                      // <ab||ij> stored as [i][j][a][b]
   copy_conj(ctx, I->oovv.size(), I->oovv.p(), I->vvoo.p(), true);
+  I->oovv_r = ZTensor(ctx, {o, v, o, v});                    // (m,e,n,f) <- <mn||ef>
+  permute(ctx, I->oovv, {0, 2, 1, 3}, one, zero, I->oovv_r.p());
 }
 
 }  // namespace fc
