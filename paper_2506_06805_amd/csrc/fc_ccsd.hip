@@ -190,10 +190,11 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   zein(ctx, "ie,ae->ia", one, T1, Fae, zero, R1);
   zein(ctx, "ma,mi->ia", mone, T1, Fmi, one, R1);
   zein(ctx, "iame,me->ia", one, T2r, Fme, one, R1);
-  zein(ctx, "nf,naif->ia", mone, T1, I->ovov, one, R1);
+  zein(ctx, "nf,nfai->ia", mone, T1, I->ovov, one, R1);
   {  // -1/2 sum_mef t_im^ef <ma||ef> = - sum_fP Q[i,f,P] L^P_af,  Q[i,f,P] = sum_me t_im^ef L^P_me
     ZTensor Q(ctx, {o, v, N});
-    zein(ctx, "imef,meP->ifP", one, T2, I->Lov, zero, Q);
+    // one product per i: Q[i] (f x P) = t2[i]^T ((m,e) x f, read transposed in place) L_ov ((m,e) x P)
+    zgemm(ctx, 'T', 'N', v, N, o * v, one, t2p, v, I->Lov.p(), N, zero, Q.p(), N, (int)o, o * v * v, 0, v * N);
     zein(ctx, "ifP,afP->ia", mone, Q, Lvv, one, R1);
   }
   zein(ctx, "mnae,nmei->ia", mhalf, T2, I->oovo, one, R1);

@@ -131,8 +131,8 @@ void assemble_integrals(fc_ctx ctx, fc_ints I) {
   // symmetry copies
   I->oovo = ZTensor(ctx, {o, o, v, o});                      // <mn||ej> = -<mn||je>
   permute(ctx, I->ooov, {0, 1, 3, 2}, mone, zero, I->oovo.p());
-  I->ovov = ZTensor(ctx, {o, v, o, v});                      // <ma||if> = -<ma||fi>
-  permute(ctx, I->ovvo, {0, 1, 3, 2}, mone, zero, I->ovov.p());
+  I->ovov = ZTensor(ctx, {o, v, v, o});                      // <ma||if> = -<ma||fi> as (m,f,a,i)
+  permute(ctx, I->ovvo, {0, 2, 1, 3}, mone, zero, I->ovov.p());
   I->ovoo = ZTensor(ctx, {o, v, o, o});                      // <mb||ij> = conj <ij||mb>
   permute(ctx, I->ooov, {2, 3, 0, 1}, one, zero, I->ovoo.p(), true);
   I->vvoo = ZTensor(ctx, {o, o, v, v});                      // <ab||ij> stored as [i][j][a][b]

@@ -18,7 +18,7 @@ struct fc_ints_s {
   // stored antisymmetrised integrals with <= 2 virtual indices (Sec. 3)
   fc::ZTensor oooo, ooov, oovv, ovvo;  // <mn||ij>, <mn||ie>, <mn||ef>, <mb||ej>
   // the same integrals re-indexed (symmetry copies kept for contiguous GEMM operands)
-  fc::ZTensor oovo, ovov, ovoo, vvoo;  // <mn||ej>, <ma||if>, <mb||ij>, <ab||ij> as [i][j][a][b]
+  fc::ZTensor oovo, ovov, ovoo, vvoo;  // <mn||ej>, <ma||if> as [m][f][a][i], <mb||ij>, <ab||ij> as [i][j][a][b]
   fc::ZTensor oovv_r;                  // <mn||ef> as [m][e][n][f]: (n, f) contiguous for the ring terms
 };
 
