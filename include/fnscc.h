@@ -214,7 +214,9 @@ void fc_free_amps(fc_amps t);
 
 /* ipeom_sigma - sigma = H-bar R on the 1h + 2h1p space (Eq. 17-18) for nvec vectors.
  * R, S: device, nvec x dim complex128 (layout above). The H-bar blocks with at most two virtual
- * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3).
+ * indices are built from `t` on first use and cached in the amplitude handle (Sec. 3); with a
+ * split-precision integral handle their products run in FP32 arithmetic (FP64 storage), as do
+ * the mixed-precision residual's products outside the ladder.  The sigma products are FP64.
  * nvec = 0 returns FC_OK without touching the device (R and S may be NULL); nvec < 0, or `t`
  * made from another integral handle: FC_EARG. */
 int ipeom_sigma(fc_ctx ctx, fc_ints ints, fc_amps t, int nvec, const void* R, void* S);

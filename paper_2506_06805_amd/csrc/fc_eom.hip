@@ -85,6 +85,10 @@ static void wmbij_three_virtual(fc_ctx ctx, fc_ints I, const ZTensor& tau, z* ou
 void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   StageTimer st(ctx, "hbar");
   ensure_integrals(ctx, I);
+  // with a split-precision integral handle (the mixed path) the H-bar products run in FP32
+  // arithmetic like the residual's products outside the ladder; the blocks are stored in FP64 and
+  // the Davidson sigma products that read them stay FP64
+  Fp32Gemms fp32(ctx, I->precision != FC_FP64);
   const ZTensor& Lvv = lvv(ctx, I);
   HbarBlocks& H = T->hb;
   const long o = I->o, v = I->v, N = I->ncd;
