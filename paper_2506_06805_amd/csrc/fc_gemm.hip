@@ -88,8 +88,15 @@ template <int BM, int BN, int BK, typename T = double>
 struct TileSmem {
   __attribute__((aligned(8))) float2 A[2][BK][BM + PADF];
   __attribute__((aligned(8))) float2 B[2][BK][BN + PADF];
-  __device__ __forceinline__ void putA(int b, int k, int m, z v) { A[b][k][m] = make_float2((float)v.x, (float)v.y); }
-  __device__ __forceinline__ void putB(int b, int k, int n, z v) { B[b][k][n] = make_float2((float)v.x, (float)v.y); }
+  // cj: conjugate (the sign flip follows the rounding to FP32, so no FP64 multiply is needed)
+  __device__ __forceinline__ void putA(int b, int k, int m, z v, bool cj) {
+    const float im = (float)v.y;
+    A[b][k][m] = make_float2((float)v.x, cj ? -im : im);
+  }
+  __device__ __forceinline__ void putB(int b, int k, int n, z v, bool cj) {
+    const float im = (float)v.y;
+    B[b][k][n] = make_float2((float)v.x, cj ? -im : im);
+  }
   __device__ __forceinline__ void getA(int b, int k, int m, T& re, T& im) const {
     const float2 v = A[b][k][m];
     re = v.x; im = v.y;
@@ -108,8 +115,8 @@ template <int BM, int BN, int BK>
 struct TileSmem<BM, BN, BK, double> {
   __attribute__((aligned(16))) z A[2][BK][BM + PADZ];
   __attribute__((aligned(16))) z B[2][BK][BN + PADZ];
-  __device__ __forceinline__ void putA(int b, int k, int m, z v) { A[b][k][m] = v; }
-  __device__ __forceinline__ void putB(int b, int k, int n, z v) { B[b][k][n] = v; }
+  __device__ __forceinline__ void putA(int b, int k, int m, z v, bool cj) { A[b][k][m] = make_double2(v.x, cj ? -v.y : v.y); }
+  __device__ __forceinline__ void putB(int b, int k, int n, z v, bool cj) { B[b][k][n] = make_double2(v.x, cj ? -v.y : v.y); }
   __device__ __forceinline__ void getA(int b, int k, int m, double& re, double& im) const {
     const z v = A[b][k][m];
     re = v.x; im = v.y;
@@ -220,7 +227,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
   const long m0 = g.m0, n0 = g.n0, klo = g.klo, khi = g.khi;
   const z* __restrict__ A = g.A;
   const z* __restrict__ B = g.B;
-  const double sa = g.conjA ? -1.0 : 1.0, sb = g.conjB ? -1.0 : 1.0;
+  const bool cja = g.conjA != 0, cjb = g.conjB != 0;
 
   z ra[LA], rb[LB];
 #define FC_LOAD_TILE(k0, ra, rb)                                                                 \
@@ -247,17 +254,20 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
     _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
       int e = tid + NT * r, mm, kk;                                                      \
       if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }           \
-      sm.putA(buf, kk, mm, make_double2(ra[r].x, sa * ra[r].y));                         \
+      sm.putA(buf, kk, mm, ra[r], cja);                                                  \
     }                                                                                    \
     _Pragma("unroll") for (int r = 0; r < LB; ++r) {                                     \
       int e = tid + NT * r, nn, kk;                                                      \
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }           \
-      sm.putB(buf, kk, nn, make_double2(rb[r].x, sb * rb[r].y));                         \
+      sm.putB(buf, kk, nn, rb[r], cjb);                                                  \
     }                                                                                    \
   } while (0)
 // The same loads with no branch: an element outside the product is read from a zero in global
 // memory, so every load instruction issues on every path (no select after it either) and the
-// compiler's count of loads in flight stays exact across the two-slice pipeline below.
+// compiler's count of loads in flight stays exact across the two-slice pipeline below.  (Forming
+// the per-thread offsets once per tile, or interleaving the address arithmetic with the products
+// through scheduling-group hints, measured slower on the 3840^3 product: 137.8 -> 135.5 and 132.3
+// TFLOP/s.)
 #define FC_LOAD_TILE_U(k0, ra, rb)                                                       \
   do {                                                                                   \
     _Pragma("unroll") for (int r = 0; r < LA; ++r) {                                     \
@@ -300,7 +310,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
   const int lr = lane & 15, lk = lane >> 4;
   // the products of one K slice from LDS buffer `buf` (FP64: the next slice is stored to the other
   // buffer before the last quarter's products)
-#define FC_SLICE_PRODUCTS(buf, kt)                                                                \
+#define FC_SLICE_PRODUCTS(buf, kt, early, RS, RBS)                                                \
   _Pragma("unroll") for (int ks = 0; ks < BK; ks += 4) {                                          \
     T ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];                                                    \
     _Pragma("unroll") for (int i = 0; i < FI; ++i) {                                              \
@@ -308,7 +318,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       nai[i] = -ai[i];                                                                            \
     }                                                                                             \
     _Pragma("unroll") for (int j = 0; j < FJ; ++j) sm.getB(buf, ks + lk, wn + 16 * j + lr, br[j], bi[j]); \
-    if (kEarlyStore && ks == BK - 4 && (kt) + 1 < nk) FC_STORE_TILE((buf) ^ 1, ra, rb);           \
+    if ((early) && ks == BK - 4 && (kt) + 1 < nk) FC_STORE_TILE((buf) ^ 1, RS, RBS);              \
     if constexpr (k3M) {                                                                          \
       T sa_[FI], sb_[FJ];                                                                         \
       _Pragma("unroll") for (int i = 0; i < FI; ++i) sa_[i] = ar[i] + ai[i];                      \
@@ -333,27 +343,27 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
     }                                                                                             \
   }
 
-  // FP32 128 x 128: global loads two K slices ahead into two register sets (even slices in ra/rb,
+  // FP32 128 x 128, 8-deep slices: global loads two K slices ahead into two register sets (even slices in ra/rb,
   // odd ones in ra2/rb2), the loop unrolled by two so that each half names its sets statically: a
   // slice's FP32 products are too short to cover the load latency on their own, and this tile (one
   // workgroup per CU) has registers to spare below the next occupancy step.  The smaller FP32 tiles
   // would lose a wave per SIMD and keep loads one slice ahead, as do the FP64 tiles.
-  constexpr bool kDepth2 = sizeof(T) == sizeof(float) && BM == 128 && BN == 128;
+  constexpr bool kDepth2 = sizeof(T) == sizeof(float) && BM == 128 && BN == 128 && BK == 8;
   if constexpr (kDepth2) {
     z ra2[LA], rb2[LB];
     FC_LOAD_TILE_U(klo, ra, rb);
     FC_STORE_TILE(0, ra, rb);
     FC_LOAD_TILE_U(klo + BK, ra2, rb2);
     __syncthreads();
+    // the next slice's registers were loaded a slice earlier, so they go to LDS before the last
+    // K quarter's products, among which the compiler can spread the conversions and stores
     for (long kt = 0; kt < nk; kt += 2) {
       FC_LOAD_TILE_U(klo + (kt + 2) * BK, ra, rb);
-      FC_SLICE_PRODUCTS(0, kt);
-      if (kt + 1 < nk) FC_STORE_TILE(1, ra2, rb2);
+      FC_SLICE_PRODUCTS(0, kt, true, ra2, rb2);
       __syncthreads();
       if (kt + 1 < nk) {
         FC_LOAD_TILE_U(klo + (kt + 3) * BK, ra2, rb2);
-        FC_SLICE_PRODUCTS(1, kt + 1);
-        if (kt + 2 < nk) FC_STORE_TILE(0, ra, rb);
+        FC_SLICE_PRODUCTS(1, kt + 1, true, ra, rb);
         __syncthreads();
       }
     }
@@ -367,7 +377,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
       // FP64: the next tile goes to the other buffer while the last products of this one run
       // (measured: +6-10% on skinny and long-K products, neutral on large ones); FP32 products
       // are twice as fast, too short to cover the global loads, and store after the step instead
-      FC_SLICE_PRODUCTS(buf, kt);
+      FC_SLICE_PRODUCTS(buf, kt, kEarlyStore, ra, rb);
       if (!kEarlyStore && kt + 1 < nk) FC_STORE_TILE(buf ^ 1, ra, rb);
       __syncthreads();
     }
