@@ -157,7 +157,8 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   // F_ae = sum_mf t_m^f <ma||fe> - 1/2 sum tau~_mn^af <mn||ef>,  <ma||fe> = (mf|ae) - (me|af)
   zein(ctx, "P,aeP->ae", one, xP, Lvv, zero, Fae);
   zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, Fae);
-  zein(ctx, "mnaf,mnef->ae", mhalf, taut, I->oovv, one, Fae);
+  // one (a x e) product per occupied pair (m, n), summed in pair order: no operand reordering
+  zgemm_sum(ctx, 'N', 'T', v, v, v, mhalf, taut.p(), v, v * v, I->oovv.p(), v, v * v, (int)(o * o), one, Fae.p(), v);
   // F_mi = sum_ne t_n^e <mn||ie> + 1/2 sum tau~_in^ef <mn||ef>
   zein(ctx, "ne,mnie->mi", one, T1, I->ooov, zero, Fmi);
   zein(ctx, "inef,mnef->mi", half, taut, I->oovv, one, Fmi);

@@ -112,7 +112,7 @@ void build_hbar(fc_ctx ctx, fc_ints I, fc_amps T) {
   H.Fae = ZTensor(ctx, {v, v});
   zein(ctx, "P,aeP->ae", one, xP, Lvv, zero, H.Fae);
   zein(ctx, "amP,meP->ae", mone, Y, I->Lov, one, H.Fae);
-  zein(ctx, "mnaf,mnef->ae", mhalf, tau, I->oovv, one, H.Fae);
+  zgemm_sum(ctx, 'N', 'T', v, v, v, mhalf, tau.p(), v, v * v, I->oovv.p(), v, v * v, (int)(o * o), one, H.Fae.p(), v);
   hipLaunchKernelGGL(k_add_diag, dim3(nblk(v)), dim3(TPB), 0, ctx->stream, H.Fae.p(), I->eps_d.as<double>() + o, v);
   // W_mnij = <mn||ij> + P(ij) t_j^e <mn||ie> + 1/2 tau_ij^ef <mn||ef>
   H.Wmnij = ZTensor(ctx, {o, o, o, o});

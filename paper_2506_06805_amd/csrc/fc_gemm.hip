@@ -1240,6 +1240,20 @@ void zgemm(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, cons
   zgemm_impl(ctx, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, batch, sA, sB, sC, nullptr);
 }
 
+void zgemm_sum(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, long sA,
+               const z* B, long ldb, long sB, int batch, z beta, z* C, long ldc) {
+  if (M <= 0 || N <= 0) return;
+  if (batch <= 0 || K <= 0) {
+    for (long m = 0; m < M; ++m) scale(ctx, C + m * ldc, N, beta);
+    return;
+  }
+  DBuf part(ctx, sizeof(z) * (size_t)batch * M * N);
+  zgemm(ctx, opA, opB, M, N, K, make_double2(1, 0), A, lda, B, ldb, make_double2(0, 0), part.as<z>(), N, batch,
+        sA, sB, M * N);
+  splitk_reduce(ctx->stream, part.as<z>(), batch, M, N, C, ldc, alpha, beta, nullptr);
+  FC_HIP(hipGetLastError());
+}
+
 void zgemm_mapped(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                   const z* B, long ldb, z beta, z* C, const OutMap& om, int batch, long sA, long sB, long sC) {
   zgemm_impl(ctx, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, 0, batch, sA, sB, sC, nullptr, &om);

@@ -133,6 +133,11 @@ struct OutMap {
     return (M / rd - 1) * rs1 + (rd - 1) * rs2 + (N / cd - 1) * cs1 + (cd - 1) * cs2 + 1;
   }
 };
+// C = alpha sum_b op(A_b) op(B_b) + beta C over b < batch (A_b = A + b sA, B_b = B + b sB): one
+// batched product into a workspace, then the partial products summed in batch order (a contraction
+// whose summed indices include the operands' leading ones, e.g. a pair index).
+void zgemm_sum(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda, long sA,
+               const z* B, long ldb, long sB, int batch, z beta, z* C, long ldc);
 // C_b = alpha op(A_b) op(B_b) + beta C_b with each C_b (at C + b sC) laid out by `om`.
 void zgemm_mapped(fc_ctx ctx, char opA, char opB, long M, long N, long K, z alpha, const z* A, long lda,
                   const z* B, long ldb, z beta, z* C, const OutMap& om, int batch = 1, long sA = 0, long sB = 0,
