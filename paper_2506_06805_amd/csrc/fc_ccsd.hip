@@ -201,15 +201,14 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   }
   zein(ctx, "mnae,nmei->ia", mhalf, T2, I->oovo, one, R1);
 
-  // ---- T2 residual
-  FC_HIP(hipMemcpyAsync(r2p, I->vvoo.p(), sizeof(z) * n2, hipMemcpyDeviceToDevice, ctx->stream));
+  // ---- T2 residual: R2 = <ab||ij> + ..., the integral block read by the first antisymmetrising add
   ZTensor x(ctx, {o, o, v, v});
   {  // P(ab) sum_e t_ij^ae (F_be - 1/2 sum_m t_m^b F_me)
     ZTensor Fp(ctx, {v, v});
     FC_HIP(hipMemcpyAsync(Fp.p(), Fae.p(), sizeof(z) * Fp.size(), hipMemcpyDeviceToDevice, ctx->stream));
     zein(ctx, "mb,me->be", mhalf, T1, Fme, one, Fp);
     zein(ctx, "ijae,be->ijab", one, T2, Fp, zero, x);
-    antisym_add(ctx, r2p, x.p(), o, v, 1, one);
+    antisym_add(ctx, r2p, x.p(), o, v, 1, one, I->vvoo.p());
     if (fdiag) hipLaunchKernelGGL(k_diag_copy, dim3(1), dim3(TPB), 0, ctx->stream, Fp.p(), v, fdiag + o);
   }
   {  // -P(ij) sum_m t_im^ab (F_mj + 1/2 sum_e t_j^e F_me)
@@ -224,10 +223,8 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   }
   zein(ctx, "mnab,mnij->ijab", half, tau, W0, one, R2);
   zein(ctx, "mnab,ijmn->ijab", quarter, T2, X, one, R2);
-  {  // particle-particle ladder with T1-dressed Cholesky vectors
-    ladder_dev(ctx, I, tau.p(), t1p, x.p(), precision);
-    axpy(ctx, n2, one, x.p(), r2p);
-  }
+  // particle-particle ladder with T1-dressed Cholesky vectors, added into R2 by its scatter
+  ladder_dev(ctx, I, tau.p(), t1p, r2p, precision, true);
   {  // P(ij)P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
     zein(ctx, "iame,mbej->ijab", one, T2r, Wmbej, zero, x);
     ZTensor U(ctx, {o, o, v, o});

@@ -200,18 +200,30 @@ __device__ inline long upair(long i, long j, long n) { return i * (2 * n - i - 1
 // Rp is [pair][i<j] (the contraction runs with the long (a,b)-pair dimension as rows, so the tiles
 // that share a panel of Wp are neighbours on one XCD and Wp is read from HBM about once).
 // Full output: R[i,j,a,b] and its three antisymmetric images.
+// acc: add into R (each of the four images belongs to one unique amplitude, so no two threads
+// touch the same element)
 __global__ void k_ladder_scatter(const z* __restrict__ Rp, z* __restrict__ R, long o, long v, const int2* pairs,
-                                 long npairs, const int2* po, long no) {
+                                 long npairs, const int2* po, long no, int acc) {
   GRID_STRIDE(t, no * npairs) {
     const long s = t % npairs, pi = t / npairs;
     const int2 ab = pairs[s];
     const int2 ij = po[pi];
     const z r = Rp[s * no + pi], m = make_double2(-r.x, -r.y);
     const long i = ij.x, j = ij.y, a = ab.x, b = ab.y;
-    R[((i * o + j) * v + a) * v + b] = r;
-    R[((j * o + i) * v + a) * v + b] = m;
-    R[((i * o + j) * v + b) * v + a] = m;
-    R[((j * o + i) * v + b) * v + a] = r;
+    const long x0 = ((i * o + j) * v + a) * v + b, x1 = ((j * o + i) * v + a) * v + b,
+               x2 = ((i * o + j) * v + b) * v + a, x3 = ((j * o + i) * v + b) * v + a;
+    if (acc) {
+      const z y0 = R[x0], y1 = R[x1], y2 = R[x2], y3 = R[x3];
+      R[x0] = make_double2(y0.x + r.x, y0.y + r.y);
+      R[x1] = make_double2(y1.x + m.x, y1.y + m.y);
+      R[x2] = make_double2(y2.x + m.x, y2.y + m.y);
+      R[x3] = make_double2(y3.x + r.x, y3.y + r.y);
+    } else {
+      R[x0] = r;
+      R[x1] = m;
+      R[x2] = m;
+      R[x3] = r;
+    }
   }
 }
 // Packed output: Rk[i<j][a<b]
@@ -247,6 +259,7 @@ namespace {
 struct Sink {
   bool packed;
   z* R;
+  bool accumulate = false;   // full layout: add into R
 };
 
 // The blocked contraction order: for each 32 x 32 block pair (E <= F) in the anti kernel's
@@ -432,7 +445,7 @@ static void ladder_core(fc_ctx ctx, fc_ints I, const z* taup, const z* t1dress, 
                          sink.R, v, slots_d.as<int2>(), nvalid, no);
     else
       hipLaunchKernelGGL(k_ladder_scatter, dim3(nblk(no * nvalid)), dim3(TPB), 0, ctx->stream, Rp.as<z>(), sink.R, o,
-                         v, slots_d.as<int2>(), nvalid, po.as<int2>(), no);
+                         v, slots_d.as<int2>(), nvalid, po.as<int2>(), no, sink.accumulate ? 1 : 0);
     FC_HIP(hipGetLastError());
     // the slot table is rewritten by the next chunk: keep host and device in order
     FC_HIP(hipStreamSynchronize(ctx->stream));
@@ -463,19 +476,20 @@ struct LadderEvents {
 };
 }  // namespace
 
-void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision) {
+void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision, bool accumulate) {
   StageTimer st(ctx, "ladder");
   LadderEvents evs(ctx);
   const long o = I->o, v = I->v;
   long no, nv;
   DBuf po = pair_table(ctx, o, no), pv = pair_table(ctx, v, nv);
-  fill(ctx, R, o * o * v * v, make_double2(0, 0));
+  // the scatter writes every element with i != j and a != b; the rest of the ladder term is zero
+  if (!accumulate) fill(ctx, R, o * o * v * v, make_double2(0, 0));
   if (no > 0 && nv > 0) {
     DBuf taup(ctx, sizeof(z) * no * nv);
     hipLaunchKernelGGL(k_pack_tau, dim3(nblk(no * nv)), dim3(TPB), 0, ctx->stream, tau, taup.as<z>(), o, v,
                        po.as<int2>(), pv.as<int2>(), no, nv);
     FC_HIP(hipGetLastError());
-    ladder_core(ctx, I, taup.as<z>(), t1dress, precision, Sink{false, R}, no, po);
+    ladder_core(ctx, I, taup.as<z>(), t1dress, precision, Sink{false, R, accumulate}, no, po);
   }
   evs.done();
 }

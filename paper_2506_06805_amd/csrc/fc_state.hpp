@@ -60,7 +60,8 @@ namespace fc {
 // t_ij^ab in the T2 residual (F_mi + 1/2 t_j^e F_me and F_ae - 1/2 t_m^b F_me).
 void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2, z* r1, z* r2, int precision,
                        z* fdiag = nullptr);
-void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision);
+// accumulate: R += the ladder term (no clear of R first)
+void ladder_dev(fc_ctx ctx, fc_ints I, const z* tau, const z* t1dress, z* R, int precision, bool accumulate = false);
 z ccsd_energy_dev(fc_ctx ctx, fc_ints I, const z* t1, const z* t2);
 void assemble_integrals(fc_ctx ctx, fc_ints I);
 // fc_integrals.hip: the stored integrals, assembled once on first use
