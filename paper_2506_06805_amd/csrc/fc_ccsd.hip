@@ -49,13 +49,6 @@ __global__ void k_sub_denom1(z* r, const z* t, const double* eps, long o, long v
     r[x].x -= d * t[x].x; r[x].y -= d * t[x].y;
   }
 }
-__global__ void k_sub_denom2(z* r, const z* t, const double* eps, long o, long v) {
-  GRID_STRIDE(x, o * o * v * v) {
-    long b = x % v, a = (x / v) % v, j = (x / (v * v)) % o, i = x / (v * v * o);
-    double d = eps[i] + eps[j] - eps[o + a] - eps[o + b];
-    r[x].x -= d * t[x].x; r[x].y -= d * t[x].y;
-  }
-}
 // out = t + r / D   (Jacobi step); diagonal (i==j or a==b) entries of t2 stay zero
 __global__ void k_jacobi1(const z* t, const z* r, z* out, const double* eps, long o, long v) {
   GRID_STRIDE(x, o * v) {
@@ -238,13 +231,12 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     zein(ctx, "ajP,biP->ijab", mone, I->Lvo, Y, one, x);
     antisym_add(ctx, r2p, x.p(), o, v, 2, one);
   }
-  {  // -P(ab) sum_m t_m^a <mb||ij>
+  {  // -P(ab) sum_m t_m^a <mb||ij>, and Omega = RHS - D t for the doubles in the same pass
     zein(ctx, "ma,mbij->ijab", one, T1, I->ovoo, zero, x);
-    antisym_add(ctx, r2p, x.p(), o, v, 1, mone);
+    antisym_add(ctx, r2p, x.p(), o, v, 1, mone, nullptr, t2p, I->eps_d.as<double>());
   }
-  // Omega = RHS - D t
+  // Omega = RHS - D t for the singles
   hipLaunchKernelGGL(k_sub_denom1, dim3(nblk(o * v)), dim3(TPB), 0, ctx->stream, r1p, t1p, I->eps_d.as<double>(), o, v);
-  hipLaunchKernelGGL(k_sub_denom2, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, r2p, t2p, I->eps_d.as<double>(), o, v);
   FC_HIP(hipGetLastError());
 }
 

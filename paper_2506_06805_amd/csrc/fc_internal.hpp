@@ -163,7 +163,10 @@ void zein(fc_ctx ctx, const char* spec, z alpha, const ZT& A, const ZT& B, z bet
 // r[i,j,a,b] += x - x^(a<->b) (mode 1), x - x^(i<->j) (mode 2),
 // x - x^(ij) - x^(ab) + x^(ij,ab) (mode 3); dims o,o,v,v.
 // base (mode 1 only, which writes every element once): r = base + alpha P(ab) x instead of r += ...
-void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha, const z* base = nullptr);
+// tsub, eps (mode 1 only): afterwards r -= (eps_i + eps_j - eps_a - eps_b) tsub (the doubles
+// residual's Omega = RHS - D t in the same pass)
+void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha, const z* base = nullptr,
+                 const z* tsub = nullptr, const double* eps = nullptr);
 // Dot products with FP64 accumulation in a fixed order (deterministic).
 z dotu(fc_ctx ctx, long n, const z* x, const z* y);    // sum x*y
 z dotc(fc_ctx ctx, long n, const z* x, const z* y);    // sum conj(x)*y

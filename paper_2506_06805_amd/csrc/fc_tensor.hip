@@ -215,7 +215,8 @@ __global__ void __launch_bounds__(TT * TR) k_permute_tiled(const z* __restrict__
 constexpr int AT = 16;
 __device__ inline z cneg(z a) { return make_double2(-a.x, -a.y); }
 __global__ __launch_bounds__(AT * AT) void k_antisym_tiles(z* r, const z* __restrict__ x, long o, long v, int mode,
-                                                           z alpha, const z* base) {
+                                                           z alpha, const z* base, const z* __restrict__ tsub,
+                                                           const double* __restrict__ eps) {
   __shared__ z T[4][AT][AT + 1];
   const int tx = threadIdx.x % AT, ty = threadIdx.x / AT;
   const long nb = (v + AT - 1) / AT;
@@ -245,12 +246,20 @@ __global__ __launch_bounds__(AT * AT) void k_antisym_tiles(z* r, const z* __rest
     const long e = R0 + ty, f = C0 + tx;
     T[k][ty][tx] = (e < v && f < v) ? x[plane + e * v + f] : make_double2(0.0, 0.0);
   };
-  // base == r: accumulate; otherwise r = base + alpha val (mode 1 writes every element once)
+  // base == r: accumulate; otherwise r = base + alpha val (mode 1 writes every element once);
+  // tsub (mode 1): then subtract (eps_i + eps_j - eps_e - eps_f) tsub
   auto add = [&](long plane, long R0, long C0, z val) {
     const long e = R0 + ty, f = C0 + tx;
     if (e < v && f < v) {
       const long off = plane + e * v + f;
-      r[off] = cadd(base[off], cmul(alpha, val));
+      z out = cadd(base[off], cmul(alpha, val));
+      if (tsub) {
+        const double d = eps[i] + eps[j] - eps[o + e] - eps[o + f];
+        const z t = tsub[off];
+        out.x -= d * t.x;
+        out.y -= d * t.y;
+      }
+      r[off] = out;
     }
   };
   if (mode == 2) {
@@ -526,8 +535,10 @@ void permute(fc_ctx ctx, const ZT& in, const std::vector<int>& perm, z alpha, z 
   FC_HIP(hipGetLastError());
 }
 
-void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha, const z* base) {
-  FC_REQUIRE(!base || mode == 1, FC_EARG, "antisym_add: a separate base needs mode 1");
+void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha, const z* base, const z* tsub,
+                 const double* eps) {
+  FC_REQUIRE((!base && !tsub) || mode == 1, FC_EARG, "antisym_add: a separate base or tsub needs mode 1");
+  FC_REQUIRE(!tsub || eps, FC_EARG, "antisym_add: tsub needs eps");
   long n = o * o * v * v;
   if (n <= 0) return;
   const long nb = (v + AT - 1) / AT;
@@ -535,7 +546,7 @@ void antisym_add(fc_ctx ctx, z* r, const z* x, long o, long v, int mode, z alpha
   if (gy <= 0) return;
   FC_REQUIRE(gx < (1L << 31) && gy <= 65535, FC_EARG, "antisym_add: too many tiles");
   hipLaunchKernelGGL(k_antisym_tiles, dim3((unsigned)gx, (unsigned)gy), dim3(AT * AT), 0, ctx->stream, r, x, o, v,
-                     mode, alpha, base ? base : r);
+                     mode, alpha, base ? base : r, tsub, eps);
   FC_HIP(hipGetLastError());
 }
 
