@@ -111,69 +111,74 @@ struct SplitOut {
   }
 };
 
+// One workgroup per (E <= F) block pair and group of slots: it walks the slots s = blockIdx.y,
+// blockIdx.y + gridDim.y, ... (a few per workgroup: one slot per workgroup made the pass
+// dispatch-bound, about 193,000 small workgroups per evaluation at v = 160).
 template <class T, class Out>
 __global__ __launch_bounds__(256) void k_ladder_anti(const T* __restrict__ W, const int* __restrict__ compact, long v,
-                                                    long nbv, const long* __restrict__ boff, Out out) {
+                                                    long nbv, const long* __restrict__ boff, long ns, Out out) {
   __shared__ T X[32][33], Y[32][33];
-  const long s = blockIdx.y;
-  const int c = compact[s];   // row of the valid pair (a < b) in Wp, or -1
-  if (c < 0) return;
   // block pair (E, F), E <= F, from the linear id
   long q = blockIdx.x, E = 0;
   while (q >= nbv - E) { q -= nbv - E; ++E; }
   const long F = E + q;
   const long off = boff[blockIdx.x];
   const long nE = std::min(32L, v - 32 * E), nF = std::min(32L, v - 32 * F);
-  const T* Ws = W + s * v * v;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  for (int r = ty; r < 32; r += 8) {
-    long e = E * 32 + r, f = F * 32 + tx;
-    X[r][tx] = (e < v && f < v) ? Ws[e * v + f] : T{};
-    long e2 = F * 32 + r, f2 = E * 32 + tx;
-    Y[r][tx] = (e2 < v && f2 < v) ? Ws[e2 * v + f2] : T{};
-  }
-  __syncthreads();
-  if constexpr (!Out::kRun4) {
+  for (long s = blockIdx.y; s < ns; s += gridDim.y) {
+    const int c = compact[s];   // row of the valid pair (a < b) in Wp, or -1 (uniform over the workgroup)
+    if (c < 0) continue;
+    const T* Ws = W + s * v * v;
+    __syncthreads();   // the previous slot's reads of X and Y are done
     for (int r = ty; r < 32; r += 8) {
-      if (r >= nE || tx >= nF) continue;
-      long local;
-      if (E < F) local = r * nF + tx;
-      else if (r < tx) local = (long)r * (2 * nE - r - 1) / 2 + (tx - r - 1);
-      else continue;
-      const T x = X[r][tx], y = Y[tx][r];
-      out.put(c, off + local, (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+      long e = E * 32 + r, f = F * 32 + tx;
+      X[r][tx] = (e < v && f < v) ? Ws[e * v + f] : T{};
+      long e2 = F * 32 + r, f2 = E * 32 + tx;
+      Y[r][tx] = (e2 < v && f2 < v) ? Ws[e2 * v + f2] : T{};
     }
-    return;
-  }
-  // runs: thread t takes row r = t / 8 of the block and its columns 4 (t % 8) + 0..3, written as
-  // one 4-slot run where the run is whole and 4-aligned (every off-diagonal run when v is a
-  // multiple of 32), slot by slot otherwise
-  const int r = threadIdx.x >> 3, c0 = 4 * (threadIdx.x & 7);
-  if (r >= nE) return;
-  if (E < F) {
-    const long pe = off + r * nF + c0;
-    if (c0 + 4 <= nF && (pe & 3) == 0) {
-      double re[4], im[4];
+    __syncthreads();
+    if constexpr (!Out::kRun4) {
+      for (int r = ty; r < 32; r += 8) {
+        if (r >= nE || tx >= nF) continue;
+        long local;
+        if (E < F) local = r * nF + tx;
+        else if (r < tx) local = (long)r * (2 * nE - r - 1) / 2 + (tx - r - 1);
+        else continue;
+        const T x = X[r][tx], y = Y[tx][r];
+        out.put(c, off + local, (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+      }
+      continue;
+    }
+    // runs: thread t takes row r = t / 8 of the block and its columns 4 (t % 8) + 0..3, written as
+    // one 4-slot run where the run is whole and 4-aligned (every off-diagonal run when v is a
+    // multiple of 32), slot by slot otherwise
+    const int r = threadIdx.x >> 3, c0 = 4 * (threadIdx.x & 7);
+    if (r >= nE) continue;
+    if (E < F) {
+      const long pe = off + r * nF + c0;
+      if (c0 + 4 <= nF && (pe & 3) == 0) {
+        double re[4], im[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const T x = X[r][c0 + q], y = Y[c0 + q][r];
-        re[q] = (double)x.x - (double)y.x;
-        im[q] = (double)x.y - (double)y.y;
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const T x = X[r][c0 + q4], y = Y[c0 + q4][r];
+          re[q4] = (double)x.x - (double)y.x;
+          im[q4] = (double)x.y - (double)y.y;
+        }
+        out.put4(c, pe, re, im);
+      } else {
+        for (int q4 = 0; q4 < 4 && c0 + q4 < nF; ++q4) {
+          const T x = X[r][c0 + q4], y = Y[c0 + q4][r];
+          out.put(c, pe + q4, (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+        }
       }
-      out.put4(c, pe, re, im);
     } else {
-      for (int q = 0; q < 4 && c0 + q < nF; ++q) {
-        const T x = X[r][c0 + q], y = Y[c0 + q][r];
-        out.put(c, pe + q, (double)x.x - (double)y.x, (double)x.y - (double)y.y);
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int f = c0 + q4;
+        if (f >= nE || f <= r) continue;
+        const T x = X[r][f], y = Y[f][r];
+        out.put(c, off + (long)r * (2 * nE - r - 1) / 2 + (f - r - 1), (double)x.x - (double)y.x,
+                (double)x.y - (double)y.y);
       }
-    }
-  } else {
-    for (int q = 0; q < 4; ++q) {
-      const int f = c0 + q;
-      if (f >= nE || f <= r) continue;
-      const T x = X[r][f], y = Y[f][r];
-      out.put(c, off + (long)r * (2 * nE - r - 1) / 2 + (f - r - 1), (double)x.x - (double)y.x,
-              (double)x.y - (double)y.y);
     }
   }
 }
@@ -403,11 +408,12 @@ static void ladder_core(fc_ctx ctx, fc_ints I, const z* taup, const z* t1dress, 
     }
     FC_HIP(hipMemcpyAsync(slots_d.p, hpairs.data(), sizeof(int2) * nvalid, hipMemcpyHostToDevice, ctx->stream));
     FC_HIP(hipMemcpyAsync(compact_d.p, hcompact.data(), sizeof(int) * ns, hipMemcpyHostToDevice, ctx->stream));
-    dim3 agrid((unsigned)bo.ntri, (unsigned)ns);
+    // a few slots per workgroup (see k_ladder_anti)
+    dim3 agrid((unsigned)bo.ntri, (unsigned)std::min(ns, 2048L));
     if (!split) {
       AntiOut<double2> out{Wp64.as<z>(), nv};
       k_ladder_anti<double2, AntiOut<double2>><<<agrid, 256, 0, ctx->stream>>>(
-          Wbuf.as<double2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), out);
+          Wbuf.as<double2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), ns, out);
       FC_HIP(hipGetLastError());
       zgemm(ctx, 'N', 'T', nvalid, no, nv, one, Wp64.as<z>(), nv, taub.p(), nv, zero, Rp.as<z>(), no);
     } else {
@@ -431,11 +437,11 @@ static void ladder_core(fc_ctx ctx, fc_ints I, const z* taup, const z* t1dress, 
       if (precision == FC_SPLIT_BF16) {
         SplitOut<FC_SPLIT_BF16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
         k_ladder_anti<float2, SplitOut<FC_SPLIT_BF16>><<<agrid, 256, 0, ctx->stream>>>(
-            Wbuf.as<float2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), out);
+            Wbuf.as<float2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), ns, out);
       } else {
         SplitOut<FC_SPLIT_FP16> out{Wps.buf.as<u16>(), plane, Wps.kp, Wps.scale};
         k_ladder_anti<float2, SplitOut<FC_SPLIT_FP16>><<<agrid, 256, 0, ctx->stream>>>(
-            Wbuf.as<float2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), out);
+            Wbuf.as<float2>(), compact_d.as<int>(), v, bo.nbv, bo.boff.as<long>(), ns, out);
       }
       FC_HIP(hipGetLastError());
       gemm_split_nt(ctx, Wps, 0, nvalid, Ts, 0, no, one, zero, Rp.as<z>(), no);
