@@ -127,8 +127,9 @@ struct TileSmem<BM, BN, BK, double> {
   }
 };
 
-// Source of the elements outside a product for loads that must issue on every path.
-__device__ __attribute__((aligned(16))) z g_dma_zero[1];   // source of elements outside the product
+// Source of the elements outside a product for loads that must issue on every path (the
+// direct-to-LDS tiles and the FP32 two-slice pipeline).
+__device__ __attribute__((aligned(16))) z g_dma_zero[1];
 
 // One output tile [m0, m0 + BM) x [n0, n0 + BN) of one product over the K range [klo, khi).
 struct TileJob {
@@ -308,8 +309,8 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
   constexpr bool kEarlyStore = sizeof(T) == sizeof(double);
   const long nk = (khi - klo + BK - 1) / BK;
   const int lr = lane & 15, lk = lane >> 4;
-  // the products of one K slice from LDS buffer `buf` (FP64: the next slice is stored to the other
-  // buffer before the last quarter's products)
+  // the products of one K slice from LDS buffer `buf`; with `early`, the next slice (registers RS,
+  // RBS) is stored to the other buffer before the last K quarter's products
 #define FC_SLICE_PRODUCTS(buf, kt, early, RS, RBS)                                                \
   _Pragma("unroll") for (int ks = 0; ks < BK; ks += 4) {                                          \
     T ar[FI], ai[FI], nai[FI], br[FJ], bi[FJ];                                                    \
@@ -343,11 +344,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob& g, TileSmem<BM, BN, BK,
     }                                                                                             \
   }
 
-  // FP32 128 x 128, 8-deep slices: global loads two K slices ahead into two register sets (even slices in ra/rb,
-  // odd ones in ra2/rb2), the loop unrolled by two so that each half names its sets statically: a
-  // slice's FP32 products are too short to cover the load latency on their own, and this tile (one
-  // workgroup per CU) has registers to spare below the next occupancy step.  The smaller FP32 tiles
-  // would lose a wave per SIMD and keep loads one slice ahead, as do the FP64 tiles.
+  // FP32 128 x 128 with 8-deep slices: global loads two K slices ahead into two register sets
+  // (even slices in ra/rb, odd ones in ra2/rb2), the loop unrolled by two so that each half names
+  // its sets statically: a slice's FP32 products are too short to cover the load latency on their
+  // own, and this tile (one workgroup per CU) has registers to spare below the next occupancy
+  // step.  The smaller FP32 tiles would lose a wave per SIMD and keep loads one slice ahead, as do
+  // the FP64 tiles (the 16-deep variant would spill).
   constexpr bool kDepth2 = sizeof(T) == sizeof(float) && BM == 128 && BN == 128 && BK == 8;
   if constexpr (kDepth2) {
     z ra2[LA], rb2[LB];
