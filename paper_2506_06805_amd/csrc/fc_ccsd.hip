@@ -221,8 +221,12 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   {  // P(ij)P(ab) sum_me (t_im^ae W_mbej - t_i^e t_m^a <mb||ej>)
     zein(ctx, "iame,mbej->ijab", one, T2r, Wmbej, zero, x);
     ZTensor U(ctx, {o, o, v, o});
-    // (one o x o product per (m, b) measured slower than the reorder plus one product)
-    zein(ctx, "ie,mbej->imbj", one, T1, I->ovvo, zero, U);
+    // U[i,m,b,j] = sum_e t_i^e <mb||ej> = -sum_e t_i^e <mb||je>: the stored ring-order block
+    // [m][e][b][j] of <mb||je> (the exact negation of <mb||ej>, as it is assembled) read in place,
+    // one (i) x (b,j) product per m.  (One o x o product per (m, b) on <mb||ej> itself measured
+    // slower than a reorder plus one product.)
+    zgemm(ctx, 'N', 'N', o, v * o, v, mone, t1p, v, I->ovov.p(), v * o, zero, U.p(), o * v * o, (int)o, 0, v * v * o,
+          v * o);
     zein(ctx, "ma,imbj->ijab", mone, T1, U, one, x);
     antisym_add(ctx, r2p, x.p(), o, v, 3, one);
   }
