@@ -71,8 +71,9 @@ def test_zgemm_fp32_arithmetic(gpu_ctx, M, N, K):
 # the tiles staged by direct-to-LDS loads (configuration 8: 128 x 128, four real products per
 # complex one; 9 and 10: 128 x 64, Gauss's three, K slices of 8 and 16) against the register-staged 128 x 128 tile
 # (configuration 2) and numpy: every operand layout, ragged rows, columns and K
-# (elements outside the product are fetched as zeros), split K (140 x 200, K = 3000)
-@pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 9), (256, 384, 520), (140, 200, 3000)])
+# (elements outside the product are fetched as zeros), split K (140 x 200, K = 3000), and a single
+# K slice (K = 5: the FP32 128 x 128 tile's two-slice pipeline with nothing past its first slice)
+@pytest.mark.parametrize("M,N,K", [(300, 257, 37), (129, 130, 9), (256, 384, 520), (140, 200, 3000), (130, 140, 5)])
 def test_zgemm_direct_to_lds_tile(M, N, K):
     import torch
     from paper_2506_06805_amd import fnscc
