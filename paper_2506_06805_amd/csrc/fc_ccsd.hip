@@ -33,12 +33,29 @@ __global__ void k_tau(const z* t1, const z* t2, z* tau, z* taut, long o, long v)
     if (taut) taut[t] = make_double2(s.x + 0.5 * d.x, s.y + 0.5 * d.y);
   }
 }
-// Z[j,n,f,b] = 1/2 t2[j,n,f,b] + t1[j,f] t1[n,b]   (scale_t2 = 1/2 for W_mbej, 1 for W-bar_mbej)
-__global__ void k_ring_amp(const z* t1, const z* t2, z* Z, long o, long v, double scale_t2) {
-  GRID_STRIDE(t, o * o * v * v) {
-    long b = t % v, f = (t / v) % v, n = (t / (v * v)) % o, j = t / (v * v * o);
-    z p = cmul(t1[j * v + f], t1[n * v + b]);
-    Z[t] = make_double2(scale_t2 * t2[t].x + p.x, scale_t2 * t2[t].y + p.y);
+// Z_jn^fb = scale_t2 t2[j,n,f,b] + t1[j,f] t1[n,b] (scale_t2 = 1/2 for W_mbej) written as
+// Zr[b][j][n][f], the order in which the ring product reads it: per (j, n) plane a 32 x 32 (f, b)
+// tile is formed from coalesced reads along b and written through LDS along f.
+// Grid: x = (f, b) tile, y = (j, n).
+__global__ __launch_bounds__(256) void k_ring_amp_t(const z* __restrict__ t1, const z* __restrict__ t2,
+                                                    z* __restrict__ Zr, long o, long v, double scale_t2) {
+  __shared__ z T[32][33];
+  const long nb = (v + 31) / 32;
+  const long F0 = (blockIdx.x / nb) * 32, B0 = (blockIdx.x % nb) * 32;
+  const long j = blockIdx.y / o, n = blockIdx.y % o;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const z* src = t2 + (j * o + n) * v * v;
+  for (int r = ty; r < 32; r += 8) {
+    const long f = F0 + r, b = B0 + tx;
+    if (f < v && b < v) {
+      const z p = cmul(t1[j * v + f], t1[n * v + b]), t = src[f * v + b];
+      T[r][tx] = make_double2(scale_t2 * t.x + p.x, scale_t2 * t.y + p.y);
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const long b = B0 + r, f = F0 + tx;
+    if (f < v && b < v) Zr[((b * o + j) * o + n) * v + f] = T[tx][r];
   }
 }
 // r -= D t with D_i^a = e_i - e_a, D_ij^ab = e_i + e_j - e_a - e_b
@@ -170,10 +187,14 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
   zein(ctx, "meP,bjP->mbej", one, I->Lov, Y, one, Wmbej);
   zein(ctx, "mjP,beP->mbej", mone, Cm, Lvv, one, Wmbej);
   zein(ctx, "nb,mnej->mbej", mone, T1, I->oovo, one, Wmbej);
-  {
-    ZTensor Z(ctx, {o, o, v, v});
-    hipLaunchKernelGGL(k_ring_amp, dim3(nblk(n2)), dim3(TPB), 0, ctx->stream, t1p, t2p, Z.p(), o, v, 0.5);
-    zein(ctx, "jnfb,menf->mbej", mone, Z, I->oovv_r, one, Wmbej);
+  {  // Z_jn^fb = t_jn^fb / 2 + t_j^f t_n^b, formed in the product's operand order [b][j][n][f]
+    ZTensor Zr(ctx, {v, o, o, v});
+    const long nbt = (v + 31) / 32;
+    FC_REQUIRE(o * o <= 65535, FC_EARG, "ccsd residual: too many occupied pairs for one launch");
+    if (nbt > 0 && o > 0)
+      hipLaunchKernelGGL(k_ring_amp_t, dim3((unsigned)(nbt * nbt), (unsigned)(o * o)), dim3(256), 0, ctx->stream, t1p,
+                         t2p, Zr.p(), o, v, 0.5);
+    zein(ctx, "bjnf,menf->mbej", mone, Zr, I->oovv_r, one, Wmbej);
   }
 
   // t_im^ae as [i][a][m][e]: the two products that sum over (m, e) with (i, a) free read it in place
