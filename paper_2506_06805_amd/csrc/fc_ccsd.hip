@@ -213,7 +213,9 @@ void ccsd_residual_dev(fc_ctx ctx, fc_ints I, const z* t1p, const z* t2p, z* r1p
     zein(ctx, "imef,meP->ifP", one, T2, I->Lov, zero, Q);
     zein(ctx, "ifP,afP->ia", mone, Q, Lvv, one, R1);
   }
-  zein(ctx, "mnae,nmei->ia", mhalf, T2, I->oovo, one, R1);
+  // -1/2 sum_mne t_mn^ae <nm||ei> = +1/2 sum_mn sum_e t_mn^ae <mn||ei> (<nm||ei> = -<mn||ei> exactly,
+  // as the block is assembled): one (i x a) product per occupied pair (m, n), summed in pair order
+  zgemm_sum(ctx, 'T', 'T', o, v, v, half, I->oovo.p(), o, v * o, t2p, v, v * v, (int)(o * o), one, r1p, v);
 
   // ---- T2 residual: R2 = <ab||ij> + ..., the integral block read by the first antisymmetrising add
   ZTensor x(ctx, {o, o, v, v});
